@@ -1,0 +1,420 @@
+/* FP64 CPU oracle for the KiloNeuS rendering hot path -- implementation.
+ *
+ * TEST INFRASTRUCTURE ONLY (see kno.h).  Plain per-ray loops in double
+ * precision with libm; no blocking, fusion or reordering beyond what each
+ * definition states.  Parameters are float32 in the scene and are promoted
+ * exactly to double.
+ */
+#include "kno.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define FEAT 15
+#define KNO_MAX_H 256   /* widest SDF hidden layer the oracle accepts */
+#define COL_HID 32
+
+static const double PI = 3.14159265358979323846;
+
+int kno_sdf_params(int H) {
+  int din = 3 + 6 * 6;
+  return din * H + H + H * H + H + (1 + FEAT) * H + (1 + FEAT);
+}
+
+int kno_col_params(void) {
+  int cin = 3 + (3 + 6 * 4) + 3 + FEAT;
+  return cin * COL_HID + COL_HID + 3 * COL_HID + 3;
+}
+
+/* Sec. 3.1, eq. 1-2: gamma_L(p) for p in R^n.  Raw coordinates first, then
+ * for every coordinate p_a the pairs sin(2^k pi p_a), cos(2^k pi p_a) for
+ * k = 0..L-1 (the raw input is kept because the paper states the encoding
+ * maps R^n to R^{n+2nL}).  out has n + 2nL entries. */
+void kno_encode(const double* p, int n, int L, double* out) {
+  for (int a = 0; a < n; ++a) out[a] = p[a];
+  for (int a = 0; a < n; ++a) {
+    for (int k = 0; k < L; ++k) {
+      double w = ldexp(PI, k) * p[a];
+      out[n + a * 2 * L + 2 * k] = sin(w);
+      out[n + a * 2 * L + 2 * k + 1] = cos(w);
+    }
+  }
+}
+
+/* softplus with sharpness beta, log(1 + exp(beta u)) / beta, written in its
+ * overflow-free form max(u, 0) + log1p(exp(-beta |u|)) / beta. */
+double kno_softplus(double u, double beta) {
+  return fmax(u, 0.0) + log1p(exp(-beta * fabs(u))) / beta;
+}
+
+/* logistic function, d softplus_beta(u) / du = sigmoid(beta u) */
+static double sigmoid(double x) {
+  if (x >= 0) return 1.0 / (1.0 + exp(-x));
+  double e = exp(x);
+  return e / (1.0 + e);
+}
+
+typedef struct {
+  const float *W1, *b1, *W2, *b2, *W3, *b3;
+} sdf_view;
+
+static sdf_view sdf_block(const kno_scene* s, int cell) {
+  const int H = s->H, din = 3 + 6 * s->pos_freqs;
+  const float* p = s->sdf + (size_t)cell * (size_t)kno_sdf_params(H);
+  sdf_view v;
+  v.W1 = p; p += din * H;
+  v.b1 = p; p += H;
+  v.W2 = p; p += H * H;
+  v.b2 = p; p += H;
+  v.W3 = p; p += (1 + FEAT) * H;
+  v.b3 = p;
+  return v;
+}
+
+/* KiloSDF MLP of one cell (Sec. 3.1, eq. 3): e = gamma_6(x_local),
+ * a1 = softplus(W1 e + b1), a2 = softplus(W2 a1 + b2), y = W3 a2 + b3;
+ * out[0] = d (world units), out[1..15] = feature z.
+ * If grad_xl is not NULL, the gradient of out[0] with respect to the local
+ * coordinates x_local is computed by the chain rule backwards through the
+ * layers and the encoding: d/dp sin(w p) = w cos(w p), d/dp cos(w p) =
+ * -w sin(w p), softplus' = sigmoid(beta u). */
+void kno_sdf_eval(const kno_scene* s, int cell, const double xl[3], double out[16],
+                  double grad_xl[3]) {
+  const int H = s->H, L = s->pos_freqs, din = 3 + 6 * L;
+  sdf_view w = sdf_block(s, cell);
+  double e[3 + 6 * 16];
+  kno_encode(xl, 3, L, e);
+  double u1[KNO_MAX_H], a1[KNO_MAX_H], u2[KNO_MAX_H], a2[KNO_MAX_H];
+  for (int j = 0; j < H; ++j) {
+    double acc = w.b1[j];
+    for (int k = 0; k < din; ++k) acc += (double)w.W1[j * din + k] * e[k];
+    u1[j] = acc;
+    a1[j] = kno_softplus(acc, s->beta);
+  }
+  for (int j = 0; j < H; ++j) {
+    double acc = w.b2[j];
+    for (int k = 0; k < H; ++k) acc += (double)w.W2[j * H + k] * a1[k];
+    u2[j] = acc;
+    a2[j] = kno_softplus(acc, s->beta);
+  }
+  for (int o = 0; o < 1 + FEAT; ++o) {
+    double acc = w.b3[o];
+    for (int k = 0; k < H; ++k) acc += (double)w.W3[o * H + k] * a2[k];
+    out[o] = acc;
+  }
+  if (grad_xl) {
+    double d2[KNO_MAX_H], d1[KNO_MAX_H];
+    for (int j = 0; j < H; ++j) d2[j] = (double)w.W3[j] * sigmoid(s->beta * u2[j]);
+    for (int k = 0; k < H; ++k) {
+      double acc = 0;
+      for (int j = 0; j < H; ++j) acc += (double)w.W2[j * H + k] * d2[j];
+      d1[k] = acc * sigmoid(s->beta * u1[k]);
+    }
+    double ge[3 + 6 * 16];
+    for (int m = 0; m < din; ++m) {
+      double acc = 0;
+      for (int k = 0; k < H; ++k) acc += (double)w.W1[k * din + m] * d1[k];
+      ge[m] = acc;
+    }
+    for (int a = 0; a < 3; ++a) {
+      double g = ge[a];
+      for (int k = 0; k < L; ++k) {
+        double wk = ldexp(PI, k);
+        double gs = ge[3 + a * 2 * L + 2 * k], gc = ge[3 + a * 2 * L + 2 * k + 1];
+        g += wk * (gs * cos(wk * xl[a]) - gc * sin(wk * xl[a]));
+      }
+      grad_xl[a] = g;
+    }
+  }
+}
+
+/* KiloColor MLP of one cell (Sec. 3.1, eq. 4): input
+ * [x_local(3), gamma_4(v)(27), n(3), z(15)] -> ReLU(32) -> sigmoid(3). */
+void kno_color_eval(const kno_scene* s, int cell, const double xl[3], const double v[3],
+                    const double n[3], const double z[15], double rgb[3]) {
+  const int L = s->dir_freqs;
+  const int cin = 3 + (3 + 6 * L) + 3 + FEAT;
+  const float* p = s->col + (size_t)cell * (size_t)kno_col_params();
+  const float *Wc1 = p, *bc1 = p + cin * COL_HID, *Wc2 = bc1 + COL_HID, *bc2 = Wc2 + 3 * COL_HID;
+  double in[3 + 3 + 6 * 16 + 3 + FEAT];
+  int q = 0;
+  for (int a = 0; a < 3; ++a) in[q++] = xl[a];
+  kno_encode(v, 3, L, in + q);
+  q += 3 + 6 * L;
+  for (int a = 0; a < 3; ++a) in[q++] = n[a];
+  for (int i = 0; i < FEAT; ++i) in[q++] = z[i];
+  double hid[COL_HID];
+  for (int j = 0; j < COL_HID; ++j) {
+    double acc = bc1[j];
+    for (int k = 0; k < cin; ++k) acc += (double)Wc1[j * cin + k] * in[k];
+    hid[j] = acc > 0 ? acc : 0.0;
+  }
+  for (int c = 0; c < 3; ++c) {
+    double acc = bc2[c];
+    for (int k = 0; k < COL_HID; ++k) acc += (double)Wc2[c * COL_HID + k] * hid[k];
+    rgb[c] = sigmoid(acc);
+  }
+}
+
+static void normalize3(double v[3]) {
+  double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+  v[0] /= l; v[1] /= l; v[2] /= l;
+}
+
+static void cross3(const double a[3], const double b[3], double c[3]) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+/* Pinhole camera.  The paper only states that the object sits in front of
+ * the camera with every ray meeting its bounding volume (Sec. 4.2); this
+ * model is the repository's reading: forward = normalize(look_at - eye),
+ * right = normalize(forward x up), up' = right x forward; the half-diagonal
+ * field of view has tangent T (0 selects 1/sqrt(D^2 - 1), D = |eye - look_at|,
+ * so the diagonal is tangent to the unit sphere).  Pixel (row, col) with
+ * sub-pixel offset (xi1, xi2): u = (2 (col + xi1)/W - 1) tx,
+ * v = (1 - 2 (row + xi2)/H) ty, tx = T W / sqrt(W^2 + H^2),
+ * ty = T H / sqrt(W^2 + H^2); d = normalize(forward + u right + v up'). */
+void kno_camera_ray(const kno_camera* c, int row, int colm, double xi1, double xi2,
+                    double o[3], double d[3]) {
+  double fwd[3] = {c->look_at[0] - c->eye[0], c->look_at[1] - c->eye[1],
+                   c->look_at[2] - c->eye[2]};
+  double dist2 = fwd[0] * fwd[0] + fwd[1] * fwd[1] + fwd[2] * fwd[2];
+  normalize3(fwd);
+  double right[3], upp[3];
+  cross3(fwd, c->up, right);
+  normalize3(right);
+  cross3(right, fwd, upp);
+  double T = c->tan_half_diag > 0 ? c->tan_half_diag : 1.0 / sqrt(dist2 - 1.0);
+  double W = c->width, Hh = c->height;
+  double diag = sqrt(W * W + Hh * Hh);
+  double tx = T * W / diag, ty = T * Hh / diag;
+  double u = (2.0 * (colm + xi1) / W - 1.0) * tx;
+  double v = (1.0 - 2.0 * (row + xi2) / Hh) * ty;
+  for (int a = 0; a < 3; ++a) {
+    o[a] = c->eye[a];
+    d[a] = fwd[a] + u * right[a] + v * upp[a];
+  }
+  normalize3(d);
+}
+
+/* Closest bounding-volume hit (Sec. 3.4.1), slab method on the box.
+ * Returns 1 and [t_near, t_far] when the ray meets the box ahead of it. */
+int kno_slab(const kno_scene* s, const double o[3], const double d[3], double* t_near,
+             double* t_far) {
+  double tn = -INFINITY, tf = INFINITY;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] != 0.0) {
+      double t1 = (s->bmin[a] - o[a]) / d[a], t2 = (s->bmax[a] - o[a]) / d[a];
+      tn = fmax(tn, fmin(t1, t2));
+      tf = fmin(tf, fmax(t1, t2));
+    } else if (o[a] < s->bmin[a] || o[a] > s->bmax[a]) {
+      return 0;
+    }
+  }
+  *t_near = tn;
+  *t_far = tf;
+  return (tn <= tf && tf > 0.0) ? 1 : 0;
+}
+
+static double cell_side(const kno_scene* s, int a) { return (s->bmax[a] - s->bmin[a]) / s->N; }
+
+/* Cell map m (Sec. 3.1) at parameter t: floor of the box-relative position
+ * over the cell side, clamped to the grid. */
+static void cell_at(const kno_scene* s, const double o[3], const double d[3], double t, int idx[3]) {
+  for (int a = 0; a < 3; ++a) {
+    double x = o[a] + t * d[a];
+    int i = (int)floor((x - s->bmin[a]) / cell_side(s, a));
+    idx[a] = i < 0 ? 0 : (i > s->N - 1 ? s->N - 1 : i);
+  }
+}
+
+/* Parameter where the ray leaves cell idx: the nearest of the three exit
+ * planes (the far plane along each axis the ray moves on).  *axis gets the
+ * plane's axis, ties going to the lowest axis. */
+static double cell_exit(const kno_scene* s, const double o[3], const double d[3], const int idx[3],
+                        int* axis) {
+  double best = INFINITY;
+  int ba = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (d[a] == 0.0) continue;
+    double plane = s->bmin[a] + (idx[a] + (d[a] > 0 ? 1 : 0)) * cell_side(s, a);
+    double ta = (plane - o[a]) / d[a];
+    if (ta < best) { best = ta; ba = a; }
+  }
+  if (axis) *axis = ba;
+  return best;
+}
+
+static int cell_index(const kno_scene* s, const int idx[3]) {
+  return idx[0] + s->N * (idx[1] + s->N * idx[2]);
+}
+
+static void local_coords(const kno_scene* s, const int idx[3], const double x[3], double xl[3]) {
+  for (int a = 0; a < 3; ++a) {
+    double side = cell_side(s, a);
+    double c = s->bmin[a] + (idx[a] + 0.5) * side;
+    xl[a] = (x[a] - c) / (0.5 * side);
+  }
+}
+
+/* Cells the ray passes through inside the box, in order, by the same
+ * cell-exit stepping the march uses (no SDF queries).  Returns the count. */
+int kno_cells_along_ray(const kno_scene* s, const double o[3], const double d[3], int max_cells,
+                        int32_t* cells, double* t_enter) {
+  double tn, tf;
+  if (!kno_slab(s, o, d, &tn, &tf)) return 0;
+  double t = fmax(tn, 0.0);
+  int idx[3];
+  cell_at(s, o, d, t, idx);
+  int n = 0;
+  while (n < max_cells) {
+    cells[n] = cell_index(s, idx);
+    t_enter[n] = t;
+    ++n;
+    int ax;
+    double te = fmax(t, cell_exit(s, o, d, idx, &ax));
+    t = te;
+    idx[ax] += d[ax] > 0 ? 1 : -1;
+    if (idx[ax] < 0 || idx[ax] >= s->N || t > tf) break;
+  }
+  return n;
+}
+
+/* Sphere tracing inside the box interval (Sec. 3.4.1; Hart's rule: advance
+ * by the SDF value).  Each step queries the MLP of the cell the ray is in,
+ * in that cell's local frame.  A step that would cross the cell's exit plane
+ * stops on the plane instead and the ray moves to the neighbouring cell
+ * (cell-boundary stepping: a cell's MLP is only evaluated inside its cell).
+ * HIT when the SDF is below eps (negative values included); MISS when the
+ * ray leaves the grid or the box interval, or after max_steps evaluations. */
+void kno_trace(const kno_scene* s, const double o[3], const double d[3], int max_steps,
+               double eps, kno_trace_result* r) {
+  memset(r, 0, sizeof(*r));
+  r->fmin = INFINITY;
+  double tn, tf;
+  if (!kno_slab(s, o, d, &tn, &tf)) {
+    r->status = KNO_BOX_MISS;
+    return;
+  }
+  double t = fmax(tn, 0.0);
+  int idx[3];
+  cell_at(s, o, d, t, idx);
+  double t_entry = t;
+  for (int k = 0; k < max_steps; ++k) {
+    double x[3], xl[3], y[16];
+    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+    local_coords(s, idx, x, xl);
+    kno_sdf_eval(s, cell_index(s, idx), xl, y, NULL);
+    double f = y[0];
+    r->steps = k + 1;
+    if (f < r->fmin) r->fmin = f;
+    if (f < eps) {
+      r->status = KNO_HIT;
+      r->t = t;
+      r->t_entry = t_entry;
+      memcpy(r->cell, idx, sizeof(idx));
+      return;
+    }
+    int ax;
+    double t_exit = fmax(t, cell_exit(s, o, d, idx, &ax));
+    if (t + f < t_exit) {
+      t = t + f;
+    } else {
+      t = t_exit;
+      idx[ax] += d[ax] > 0 ? 1 : -1;
+      t_entry = t;
+      if (idx[ax] < 0 || idx[ax] >= s->N || t > tf) {
+        r->status = KNO_EXIT_MISS;
+        r->t = t;
+        return;
+      }
+    }
+  }
+  r->status = KNO_BUDGET_MISS;
+  r->t = t;
+}
+
+/* Shading of a hit (Sec. 3.4.1).  Two guarded Newton steps along the ray on
+ * f(o + t d) refine the hit inside its cell (t stays within the cell's
+ * [entry, exit] interval; a step is taken only when the directional
+ * derivative is below -1e-3).  At the refined point: depth = t, the normal
+ * is the normalised world-space SDF gradient of the hit cell's MLP (-d if
+ * the gradient vanishes), and the color MLP gets x_local, gamma_4(d), n, z. */
+void kno_shade(const kno_scene* s, const double o[3], const double d[3],
+               const kno_trace_result* r, double* depth, double normal[3], double rgb[3],
+               double z[15]) {
+  const int idx[3] = {r->cell[0], r->cell[1], r->cell[2]};
+  const int cell = cell_index(s, idx);
+  double half[3];
+  for (int a = 0; a < 3; ++a) half[a] = 0.5 * cell_side(s, a);
+  double t = r->t;
+  double t_exit = cell_exit(s, o, d, idx, NULL);
+  double x[3], xl[3], y[16], gl[3], g[3];
+  for (int it = 0; it < 2; ++it) {
+    for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+    local_coords(s, idx, x, xl);
+    kno_sdf_eval(s, cell, xl, y, gl);
+    double gd = 0;
+    for (int a = 0; a < 3; ++a) gd += gl[a] / half[a] * d[a];
+    if (gd < -1e-3) {
+      double tn = t - y[0] / gd;
+      tn = fmax(tn, r->t_entry);
+      tn = fmin(tn, t_exit);
+      t = tn;
+    }
+  }
+  for (int a = 0; a < 3; ++a) x[a] = o[a] + t * d[a];
+  local_coords(s, idx, x, xl);
+  kno_sdf_eval(s, cell, xl, y, gl);
+  for (int a = 0; a < 3; ++a) g[a] = gl[a] / half[a];
+  double gn = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  if (gn < 1e-20) {
+    for (int a = 0; a < 3; ++a) normal[a] = -d[a];
+  } else {
+    for (int a = 0; a < 3; ++a) normal[a] = g[a] / gn;
+  }
+  for (int i = 0; i < FEAT; ++i) z[i] = y[1 + i];
+  kno_color_eval(s, cell, xl, d, normal, z, rgb);
+  *depth = t;
+}
+
+/* One primary ray per pixel through the pixel center; outputs laid out
+ * row-major, rgb and normal as [npix][3].  pixels == NULL renders the whole
+ * image (npix must be width*height); otherwise only the listed pixels. */
+void kno_render(const kno_scene* s, const kno_camera* c, const int64_t* pixels, int64_t npix,
+                double* rgb, double* depth, double* normal, uint8_t* hit, int32_t* steps,
+                int32_t* status, double* fmin, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < npix; ++q) {
+    int64_t p = pixels ? pixels[q] : q;
+    int row = (int)(p / c->width), colm = (int)(p % c->width);
+    double o[3], d[3];
+    kno_camera_ray(c, row, colm, 0.5, 0.5, o, d);
+    kno_trace_result r;
+    kno_trace(s, o, d, c->max_steps, c->eps, &r);
+    double dep = 0, n[3] = {0, 0, 0}, col[3], z[15];
+    if (r.status == KNO_HIT) {
+      kno_shade(s, o, d, &r, &dep, n, col, z);
+    } else {
+      for (int a = 0; a < 3; ++a) col[a] = c->background[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (rgb) rgb[q * 3 + a] = col[a];
+      if (normal) normal[q * 3 + a] = n[a];
+    }
+    if (depth) depth[q] = dep;
+    if (hit) hit[q] = r.status == KNO_HIT;
+    if (steps) steps[q] = r.steps;
+    if (status) status[q] = r.status;
+    if (fmin) fmin[q] = r.fmin;
+  }
+}

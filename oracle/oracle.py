@@ -1,0 +1,198 @@
+"""ctypes front end of the FP64 CPU oracle (oracle/kno.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the package's smoke check and the
+benchmark's CPU-baseline leg use it; the product library never does.  It
+imports nothing from the HIP package.  Scenes are passed as plain arrays in
+the C ABI's host layout (one float32 block per cell).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkno.so")
+
+BOX_MISS, HIT, EXIT_MISS, BUDGET_MISS = 0, 1, 2, 3
+
+
+def build(verbose: bool = False) -> str:
+    """Compile kno.c into libkno.so with gcc -O2 (no fast-math), OpenMP."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared",
+           os.path.join(HERE, "kno.c"), "-o", LIB_PATH, "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB_PATH
+
+
+class _Scene(C.Structure):
+    _fields_ = [("N", C.c_int32), ("H", C.c_int32), ("pos_freqs", C.c_int32),
+                ("dir_freqs", C.c_int32), ("beta", C.c_double),
+                ("bmin", C.c_double * 3), ("bmax", C.c_double * 3),
+                ("sdf", C.POINTER(C.c_float)), ("col", C.POINTER(C.c_float))]
+
+
+class _Camera(C.Structure):
+    _fields_ = [("eye", C.c_double * 3), ("look_at", C.c_double * 3), ("up", C.c_double * 3),
+                ("tan_half_diag", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
+                ("max_steps", C.c_int32), ("eps", C.c_double), ("background", C.c_double * 3)]
+
+
+class _Trace(C.Structure):
+    _fields_ = [("status", C.c_int32), ("steps", C.c_int32), ("cell", C.c_int32 * 3),
+                ("t", C.c_double), ("t_entry", C.c_double), ("fmin", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH) or (
+                os.path.getmtime(LIB_PATH) < os.path.getmtime(os.path.join(HERE, "kno.c"))):
+            build()
+        L = C.CDLL(LIB_PATH)
+        dp = C.POINTER(C.c_double)
+        L.kno_sdf_params.restype = C.c_int
+        L.kno_col_params.restype = C.c_int
+        L.kno_encode.argtypes = [dp, C.c_int, C.c_int, dp]
+        L.kno_softplus.argtypes = [C.c_double, C.c_double]
+        L.kno_softplus.restype = C.c_double
+        L.kno_sdf_eval.argtypes = [C.POINTER(_Scene), C.c_int, dp, dp, dp]
+        L.kno_color_eval.argtypes = [C.POINTER(_Scene), C.c_int, dp, dp, dp, dp, dp]
+        L.kno_camera_ray.argtypes = [C.POINTER(_Camera), C.c_int, C.c_int, C.c_double,
+                                     C.c_double, dp, dp]
+        L.kno_slab.argtypes = [C.POINTER(_Scene), dp, dp, dp, dp]
+        L.kno_slab.restype = C.c_int
+        L.kno_cells_along_ray.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int,
+                                          C.POINTER(C.c_int32), dp]
+        L.kno_cells_along_ray.restype = C.c_int
+        L.kno_trace.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int, C.c_double,
+                                C.POINTER(_Trace)]
+        L.kno_shade.argtypes = [C.POINTER(_Scene), dp, dp, C.POINTER(_Trace), dp, dp, dp, dp]
+        L.kno_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64,
+                                 dp, dp, dp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32), dp, C.c_int]
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _vec(v) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(v, np.float64))
+
+
+class OracleScene:
+    """Holds a scene's float32 arrays alive for the C side."""
+
+    def __init__(self, sdf: np.ndarray, col: np.ndarray, N: int, H: int,
+                 bbox_min=(-1, -1, -1), bbox_max=(1, 1, 1), beta: float = 100.0,
+                 pos_freqs: int = 6, dir_freqs: int = 4):
+        self.sdf = np.ascontiguousarray(sdf, np.float32)
+        self.col = np.ascontiguousarray(col, np.float32)
+        assert self.sdf.shape == (N ** 3, lib().kno_sdf_params(H))
+        assert self.col.shape == (N ** 3, lib().kno_col_params())
+        self.N, self.H = N, H
+        self.c = _Scene(N, H, pos_freqs, dir_freqs, beta, (C.c_double * 3)(*bbox_min),
+                        (C.c_double * 3)(*bbox_max),
+                        self.sdf.ctypes.data_as(C.POINTER(C.c_float)),
+                        self.col.ctypes.data_as(C.POINTER(C.c_float)))
+
+    @classmethod
+    def from_scene(cls, sc) -> "OracleScene":
+        return cls(sc.sdf, sc.col, sc.N, sc.H, sc.bbox_min, sc.bbox_max, sc.beta)
+
+    # -- primitives --------------------------------------------------------
+    def sdf_eval(self, cell: int, xl, grad: bool = False):
+        x = _vec(xl)
+        out = np.zeros(16)
+        g = np.zeros(3)
+        lib().kno_sdf_eval(C.byref(self.c), int(cell), _dp(x), _dp(out), _dp(g) if grad else None)
+        return (out, g) if grad else out
+
+    def color_eval(self, cell: int, xl, v, n, z):
+        rgb = np.zeros(3)
+        a, b, c, d = _vec(xl), _vec(v), _vec(n), _vec(z)
+        lib().kno_color_eval(C.byref(self.c), int(cell), _dp(a), _dp(b), _dp(c), _dp(d), _dp(rgb))
+        return rgb
+
+    def slab(self, o, d):
+        tn, tf = C.c_double(), C.c_double()
+        ok = lib().kno_slab(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), C.byref(tn), C.byref(tf))
+        return bool(ok), tn.value, tf.value
+
+    def cells_along_ray(self, o, d, max_cells: int = 4096):
+        cells = np.zeros(max_cells, np.int32)
+        tin = np.zeros(max_cells)
+        n = lib().kno_cells_along_ray(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), max_cells,
+                                      cells.ctypes.data_as(C.POINTER(C.c_int32)), _dp(tin))
+        return cells[:n], tin[:n]
+
+    def trace(self, o, d, max_steps: int, eps: float) -> dict:
+        r = _Trace()
+        lib().kno_trace(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), max_steps, eps, C.byref(r))
+        return dict(status=r.status, steps=r.steps, cell=tuple(r.cell), t=r.t,
+                    t_entry=r.t_entry, fmin=r.fmin, _raw=r)
+
+    def shade(self, o, d, tr: dict) -> dict:
+        depth = C.c_double()
+        n, rgb, z = np.zeros(3), np.zeros(3), np.zeros(15)
+        lib().kno_shade(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), C.byref(tr["_raw"]),
+                        C.byref(depth), _dp(n), _dp(rgb), _dp(z))
+        return dict(depth=depth.value, normal=n, rgb=rgb, z=z)
+
+    def render(self, view, width: int, height: int, max_steps: int, eps: float,
+               pixels=None, background=(0.0, 0.0, 0.0), nthreads: int = 0) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, background)
+        if pixels is None:
+            npix = width * height
+            pix_ptr = None
+        else:
+            pixels = np.ascontiguousarray(pixels, np.int64)
+            npix = pixels.size
+            pix_ptr = pixels.ctypes.data
+        rgb = np.zeros((npix, 3))
+        depth = np.zeros(npix)
+        normal = np.zeros((npix, 3))
+        hit = np.zeros(npix, np.uint8)
+        steps = np.zeros(npix, np.int32)
+        status = np.zeros(npix, np.int32)
+        fmin = np.zeros(npix)
+        lib().kno_render(C.byref(self.c), C.byref(cam), pix_ptr, npix, _dp(rgb), _dp(depth),
+                         _dp(normal), hit.ctypes.data_as(C.POINTER(C.c_uint8)),
+                         steps.ctypes.data_as(C.POINTER(C.c_int32)),
+                         status.ctypes.data_as(C.POINTER(C.c_int32)), _dp(fmin), nthreads)
+        return dict(rgb=rgb, depth=depth, normal=normal, hit=hit, steps=steps,
+                    status=status, fmin=fmin)
+
+
+def make_camera(view, width, height, max_steps, eps, background=(0.0, 0.0, 0.0)) -> _Camera:
+    return _Camera((C.c_double * 3)(*view.eye), (C.c_double * 3)(*view.look_at),
+                   (C.c_double * 3)(*view.up), float(view.tan_half_diag), width, height,
+                   max_steps, eps, (C.c_double * 3)(*background))
+
+
+def encode(p, L: int) -> np.ndarray:
+    x = _vec(p)
+    out = np.zeros(x.size + 2 * x.size * L)
+    lib().kno_encode(_dp(x), x.size, L, _dp(out))
+    return out
+
+
+def softplus(u: float, beta: float = 100.0) -> float:
+    return lib().kno_softplus(float(u), float(beta))
+
+
+def camera_ray(view, width, height, row, col, xi1=0.5, xi2=0.5):
+    cam = make_camera(view, width, height, 1, 1e-4)
+    o, d = np.zeros(3), np.zeros(3)
+    lib().kno_camera_ray(C.byref(cam), row, col, xi1, xi2, _dp(o), _dp(d))
+    return o, d

@@ -1,0 +1,401 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and mathematics.
+
+Each test checks the oracle against something other than its own formulas:
+closed forms (encoding at special points, the plane scene), textbook
+identities (softplus), an independent float64 torch re-implementation with
+autograd, central finite differences, analytic box/cell geometry and dense
+sampling.  None of these tests needs a GPU.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+import torch.nn.functional as F
+
+from oracle import oracle as O
+from paper_2206_10885_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# independent torch float64 re-implementation (test only)
+# --------------------------------------------------------------------------
+def t_encode(p: torch.Tensor, L: int) -> torch.Tensor:
+    """gamma_L on the last axis of p: raw coordinates, then per coordinate
+    sin/cos pairs with frequencies 2^k pi (Sec. 3.1, eq. 1-2)."""
+    parts = [p]
+    for a in range(p.shape[-1]):
+        for k in range(L):
+            w = (2.0 ** k) * math.pi * p[..., a:a + 1]
+            parts += [torch.sin(w), torch.cos(w)]
+    return torch.cat(parts, dim=-1)
+
+
+def t_softplus(u, beta=100.0):
+    return torch.logaddexp(torch.zeros_like(u), beta * u) / beta
+
+
+def t_sdf(block: np.ndarray, H: int, xl: torch.Tensor) -> torch.Tensor:
+    w = {k: torch.tensor(v, dtype=torch.float64) for k, v in synth.unpack_sdf(block, H).items()}
+    e = t_encode(xl, 6)
+    a1 = t_softplus(F.linear(e, w["W1"], w["b1"]))
+    a2 = t_softplus(F.linear(a1, w["W2"], w["b2"]))
+    return F.linear(a2, w["W3"], w["b3"])
+
+
+def t_color(block: np.ndarray, xl, v, n, z) -> torch.Tensor:
+    w = {k: torch.tensor(x, dtype=torch.float64) for k, x in synth.unpack_col(block).items()}
+    inp = torch.cat([xl, t_encode(v, 4), n, z], dim=-1)
+    return torch.sigmoid(F.linear(torch.relu(F.linear(inp, w["Wc1"], w["bc1"])), w["Wc2"], w["bc2"]))
+
+
+# --------------------------------------------------------------------------
+def test_paper_constants():
+    """Sizes the paper fixes (golden fixture with citations)."""
+    g = json.load(open(os.path.join(GOLDEN, "paper_constants.json")))
+    assert synth.pe_dim(3, g["pos_freqs"]) == g["sdf_input_dim"]
+    assert synth.pe_dim(3, g["dir_freqs"]) == g["dir_encoding_dim"]
+    assert 2 * g["grid_n"] ** 3 == g["mlp_count"]
+    assert synth.SDF_IN == g["sdf_input_dim"]
+
+
+def test_encoding_special_points():
+    """gamma_6 at 0 and at 1/2 in closed form (Sec. 3.1, eq. 1-2)."""
+    e0 = O.encode([0.0, 0.0, 0.0], 6)
+    assert e0.shape == (39,)
+    np.testing.assert_array_equal(e0[:3], 0.0)
+    np.testing.assert_allclose(e0[3:].reshape(18, 2), np.tile([0.0, 1.0], (18, 1)), atol=0)
+    e = O.encode([0.5, -0.5, 0.25], 6)
+    np.testing.assert_array_equal(e[:3], [0.5, -0.5, 0.25])
+    blocks = e[3:].reshape(3, 6, 2)
+    # p = 1/2: sin(2^k pi / 2) = 1, 0, 0, ...; cos = 0, -1, 1, 1, ...
+    np.testing.assert_allclose(blocks[0, :, 0], [1, 0, 0, 0, 0, 0], atol=1e-14)
+    np.testing.assert_allclose(blocks[0, :, 1], [0, -1, 1, 1, 1, 1], atol=1e-14)
+    np.testing.assert_allclose(blocks[1, :, 0], [-1, 0, 0, 0, 0, 0], atol=1e-14)
+    # p = 1/4: angles pi/4, pi/2, pi, 2pi, ...
+    r = math.sqrt(0.5)
+    np.testing.assert_allclose(blocks[2, :, 0], [r, 1, 0, 0, 0, 0], atol=1e-14)
+    np.testing.assert_allclose(blocks[2, :, 1], [r, 0, -1, 1, 1, 1], atol=1e-14)
+    assert O.encode([0.1, 0.2, 0.3], 4).shape == (27,)
+
+
+def test_softplus_identities():
+    beta = 100.0
+    assert O.softplus(0.0, beta) == pytest.approx(math.log(2.0) / beta, rel=1e-15)
+    for u in np.linspace(-0.05, 0.05, 41):
+        naive = math.log(1.0 + math.exp(beta * u)) / beta
+        assert O.softplus(u, beta) == pytest.approx(naive, rel=1e-13, abs=1e-17)
+        # sp(u) - sp(-u) = u
+        assert O.softplus(u, beta) - O.softplus(-u, beta) == pytest.approx(u, abs=1e-16)
+    assert O.softplus(5.0, beta) == 5.0
+    assert O.softplus(-5.0, beta) == pytest.approx(math.exp(-500.0) / beta, rel=1e-12)
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_sdf_mlp_matches_torch(H):
+    sc = synth.sphere_scene(4, H, 0.5, 0.02, seed=11 + H)
+    os_ = O.OracleScene.from_scene(sc)
+    rng = np.random.default_rng(H)
+    for _ in range(20):
+        cell = int(rng.integers(0, sc.cells))
+        xl = rng.uniform(-1, 1, 3)
+        ours = os_.sdf_eval(cell, xl)
+        ref = t_sdf(sc.sdf[cell], H, torch.tensor(xl)).numpy()
+        np.testing.assert_allclose(ours, ref, rtol=1e-12, atol=1e-13)
+
+
+def test_color_mlp_matches_torch():
+    sc = synth.sphere_scene(4, 32, 0.5, 0.02, seed=5)
+    os_ = O.OracleScene.from_scene(sc)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        cell = int(rng.integers(0, sc.cells))
+        xl = rng.uniform(-1, 1, 3)
+        v = rng.normal(size=3); v /= np.linalg.norm(v)
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        z = rng.normal(size=15)
+        ours = os_.color_eval(cell, xl, v, n, z)
+        ref = t_color(sc.col[cell], *(torch.tensor(a) for a in (xl, v, n, z))).numpy()
+        np.testing.assert_allclose(ours, ref, rtol=1e-13, atol=1e-14)
+
+
+@pytest.mark.parametrize("H", [32, 64])
+def test_gradient_autograd_and_finite_differences(H):
+    """Check (c): analytic normal against torch float64 autograd (<= 1e-12)
+    and against central differences with delta = 1e-6 world units in the
+    same cell (angle <= 1e-6 rad)."""
+    N = 16
+    sc = synth.sphere_scene(N, H, 0.6, 0.02, seed=21 + H)
+    os_ = O.OracleScene.from_scene(sc)
+    rng = np.random.default_rng(7)
+    h = 1.0 / N
+    for _ in range(12):
+        cell = int(rng.integers(0, sc.cells))
+        xl = rng.uniform(-0.9, 0.9, 3)
+        out, gl = os_.sdf_eval(cell, xl, grad=True)
+        x = torch.tensor(xl, requires_grad=True)
+        f = t_sdf(sc.sdf[cell], H, x)[0]
+        f.backward()
+        np.testing.assert_allclose(gl, x.grad.numpy(), rtol=1e-11, atol=1e-12)
+        # central differences in world units: x_local moves by delta / h
+        delta = 1e-6
+        fd = np.zeros(3)
+        for a in range(3):
+            e = np.zeros(3); e[a] = delta / h
+            fd[a] = (os_.sdf_eval(cell, xl + e)[0] - os_.sdf_eval(cell, xl - e)[0]) / (2 * delta)
+        g_world = gl / h
+        cosang = g_world @ fd / (np.linalg.norm(g_world) * np.linalg.norm(fd))
+        assert math.acos(min(1.0, cosang)) <= 1e-6
+
+
+def test_camera_corner_angle_and_symmetry():
+    view = synth.View(eye=(0.3, 1.1, 2.1))
+    W, Hh = 40, 24
+    T = 1.0 / math.sqrt(sum(c * c for c in view.eye) - 1.0)
+    o, d = O.camera_ray(view, W, Hh, 0, 0, 0.0, 0.0)   # image corner
+    fwd = -np.asarray(view.eye) / np.linalg.norm(view.eye)
+    assert math.acos(d @ fwd) == pytest.approx(math.atan(T), abs=1e-13)
+    np.testing.assert_allclose(o, view.eye, atol=0)
+    for (i, j) in [(0, 0), (3, 7), (11, 20)]:
+        _, d1 = O.camera_ray(view, W, Hh, i, j)
+        _, d2 = O.camera_ray(view, W, Hh, Hh - 1 - i, W - 1 - j)
+        s = d1 + d2
+        np.testing.assert_allclose(s / np.linalg.norm(s), fwd, atol=1e-14)
+        assert np.linalg.norm(d1) == pytest.approx(1.0, abs=1e-15)
+    # +y up: the top row looks up
+    _, dt = O.camera_ray(synth.front_view(), 8, 8, 0, 4)
+    assert dt[1] > 0
+    # every primary ray of the default field of view meets the unit sphere
+    for (i, j) in [(0, 0), (0, W - 1), (Hh - 1, 0), (Hh - 1, W - 1)]:
+        o, d = O.camera_ray(view, W, Hh, i, j)
+        b = o @ d
+        assert b * b - (o @ o - 1.0) >= -1e-12
+
+
+def test_slab_analytic():
+    sc = synth.sphere_scene(2, 32, 0.5, 0.0, seed=1)
+    os_ = O.OracleScene.from_scene(sc)
+    ok, tn, tf = os_.slab([0.2, 0.3, 5.0], [0, 0, -1.0])
+    assert ok and tn == pytest.approx(4.0) and tf == pytest.approx(6.0)
+    ok, tn, tf = os_.slab([3.0, 0.5, 0.5], [-1.0, 0, 0])
+    assert ok and tn == pytest.approx(2.0) and tf == pytest.approx(4.0)
+    ok, _, _ = os_.slab([0.0, 1.5, 5.0], [0, 0, -1.0])     # parallel, outside in y
+    assert not ok
+    ok, _, _ = os_.slab([0.0, 0.0, 5.0], [0, 0, 1.0])      # box behind the ray
+    assert not ok
+    ok, tn, tf = os_.slab([0.0, 0.0, 0.0], [1.0, 0, 0])    # starts inside
+    assert ok and tn == pytest.approx(-1.0) and tf == pytest.approx(1.0)
+    d = np.array([1.0, 1.0, 1.0]) / math.sqrt(3)
+    ok, tn, tf = os_.slab([-2.0, -2.0, -2.0], d)           # through opposite corners
+    assert ok and tn == pytest.approx(math.sqrt(3)) and tf == pytest.approx(3 * math.sqrt(3))
+
+
+def test_dda_matches_dense_sampling():
+    """Cells visited by the cell-exit stepping equal the cells found by
+    sampling the ray every 1e-5 (rays chosen away from cell corners)."""
+    N = 8
+    sc = synth.sphere_scene(N, 32, 0.5, 0.0, seed=1)
+    os_ = O.OracleScene.from_scene(sc)
+    rng = np.random.default_rng(5)
+    checked = 0
+    while checked < 30:
+        o = rng.normal(size=3); o = 2.5 * o / np.linalg.norm(o)
+        d = -o / np.linalg.norm(o) + 0.3 * rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        ok, tn, tf = os_.slab(o, d)
+        if not ok:
+            continue
+        cells, tin = os_.cells_along_ray(o, d)
+        ts = np.arange(max(tn, 0) + 5e-6, tf, 1e-5)
+        x = o[None, :] + ts[:, None] * d[None, :]
+        idx = np.clip(np.floor((x + 1) / (2.0 / N)).astype(int), 0, N - 1)
+        g = idx[:, 0] + N * (idx[:, 1] + N * idx[:, 2])
+        seq = g[np.r_[True, g[1:] != g[:-1]]]
+        # a corner crossing would show as a cell touched for < 1e-5
+        if len(seq) != len(cells):
+            continue
+        np.testing.assert_array_equal(seq, cells)
+        checked += 1
+
+
+def _plane_cases(N):
+    rng = np.random.default_rng(100 + N)
+    for case in range(10):
+        n = rng.normal(size=3); n /= np.linalg.norm(n)
+        p = rng.uniform(-0.3, 0.3)
+        yield case, n, p, rng
+
+
+@pytest.mark.parametrize("N", [1, 4])
+def test_plane_closed_form(N):
+    """Check (a): on the plane scene f(x) = g.x + c0 (the affine map of the
+    stored float32 parameters of the hit cell) the hit depth is
+    t* = -(g.o + c0)/(g.d) and the normal is g/|g|, for rays with g.d < 0
+    whose t* lies in the box interval; other rays miss."""
+    hits = misses = 0
+    for case, n, p, rng in _plane_cases(N):
+        sc = synth.plane_scene(N, 32, n, p, seed=case)
+        os_ = O.OracleScene.from_scene(sc)
+        for _ in range(40):
+            o = n * 2.5 + rng.normal(size=3) * 0.7
+            d = -n + 0.6 * rng.normal(size=3)
+            d /= np.linalg.norm(d)
+            tr = os_.trace(o, d, 256, 1e-4)
+            ok, tn, tf = os_.slab(o, d)
+            nd = n @ d
+            ts = (p - n @ o) / nd if nd != 0 else np.inf
+            if not ok or abs(nd) <= 0.2 or min(abs(ts - tn), abs(ts - tf)) < 1e-3:
+                continue   # grazing or near the box faces: both outcomes defensible
+            t0 = max(tn, 0.0)
+            inside = n @ (o + t0 * d) - p < 0      # enters the box behind the plane
+            expect_hit = inside or (nd < 0 and t0 <= ts <= tf)
+            assert (tr["status"] == O.HIT) == expect_hit
+            if inside:
+                # hit where the ray enters the box; refinement stays in the cell
+                assert tr["t"] == pytest.approx(t0, abs=1e-12)
+                assert os_.shade(o, d, tr)["depth"] == pytest.approx(t0, abs=1e-12)
+                continue
+            if expect_hit:
+                sh = os_.shade(o, d, tr)
+                cell = tr["cell"][0] + N * (tr["cell"][1] + N * tr["cell"][2])
+                g, c0 = synth.plane_affine_map(sc, cell)
+                t_star = -(g @ o + c0) / (g @ d)
+                assert abs(t_star - ts) < 1e-5          # float32 rounding of the plane
+                assert sh["depth"] == pytest.approx(t_star, abs=1e-10)
+                np.testing.assert_allclose(sh["normal"], g / np.linalg.norm(g), atol=1e-10)
+                # color: positive ReLU regime => rgb = sigmoid(affine(input))
+                x = o + t_star * d
+                c = synth.cell_centers(N)[cell]
+                xl = (x - c) * N
+                sdf = synth.unpack_sdf(sc.sdf[cell], 32)
+                z = np.asarray(sdf["W3"][1:], np.float64) @ _plane_hidden(sc, cell, xl) + sdf["b3"][1:]
+                w = synth.unpack_col(sc.col[cell])
+                inp = np.concatenate([xl, _encode_np(d, 4), g / np.linalg.norm(g), z])
+                pre = (w["Wc2"].astype(np.float64) @ (w["Wc1"].astype(np.float64) @ inp + w["bc1"])
+                       + w["bc2"])
+                np.testing.assert_allclose(sh["rgb"], 1 / (1 + np.exp(-pre)), atol=1e-10)
+                np.testing.assert_allclose(sh["z"], z, atol=1e-10)
+                hits += 1
+            else:
+                misses += 1
+    assert hits > 50 and misses > 20
+
+
+def _encode_np(p, L):
+    out = list(p)
+    for a in range(3):
+        for k in range(L):
+            out += [math.sin(2 ** k * math.pi * p[a]), math.cos(2 ** k * math.pi * p[a])]
+    return np.array(out)
+
+
+def _plane_hidden(sc, cell, xl):
+    """Second hidden layer of the plane scene in its affine regime."""
+    w = synth.unpack_sdf(sc.sdf[cell], 32)
+    e = _encode_np(xl, 6)
+    a1 = w["W1"].astype(np.float64) @ e + w["b1"]
+    return w["W2"].astype(np.float64) @ a1 + w["b2"]
+
+
+def _lipschitz_safe_c1():
+    base = synth.sphere_scene(4, 32, 0.5, 0.0, seed=1000)
+    os_ = O.OracleScene.from_scene(base)
+    rng = np.random.default_rng(0)
+    gmax = 0.0
+    for _ in range(400):
+        cell = int(rng.integers(0, base.cells))
+        _, gl = os_.sdf_eval(cell, rng.uniform(-1, 1, 3), grad=True)
+        gmax = max(gmax, np.linalg.norm(gl * 4))
+    return synth.lipschitz_safe(base, 1.0 / (1.25 * gmax)) if gmax > 1 else base
+
+
+def _np_sdf_world(sc, x):
+    """Independent float64 numpy evaluation of the KiloSDF field at world
+    points x [n, 3]: cell by floor, local frame, MLP."""
+    N, H = sc.N, sc.H
+    idx = np.clip(np.floor((x + 1) * N / 2).astype(int), 0, N - 1)
+    g = idx[:, 0] + N * (idx[:, 1] + N * idx[:, 2])
+    c = -1 + (idx + 0.5) * (2.0 / N)
+    xl = (x - c) * N
+    e = np.concatenate([xl] + [f(2.0 ** k * math.pi * xl[:, a:a + 1])
+                               for a in range(3) for k in range(6) for f in (np.sin, np.cos)], 1)
+    out = np.empty(len(x))
+    for cell in np.unique(g):
+        m = g == cell
+        w = {k: v.astype(np.float64) for k, v in synth.unpack_sdf(sc.sdf[cell], H).items()}
+        sp = lambda u: np.logaddexp(0.0, 100.0 * u) / 100.0
+        a1 = sp(e[m] @ w["W1"].T + w["b1"])
+        a2 = sp(a1 @ w["W2"].T + w["b2"])
+        out[m] = a2 @ w["W3"][0] + w["b3"][0]
+    return out
+
+
+@pytest.mark.slow
+def test_bruteforce_first_root():
+    """Check (b): on a Lipschitz-safe sphere scene, sphere tracing finds the
+    same first root as fine marching (step 1e-4, bisection to 1e-12) on a
+    16x16 image; exceptions only for exhausted step budgets or rays whose
+    smallest SDF value lies in (0, eps) (grazing)."""
+    sc = _lipschitz_safe_c1()
+    os_ = O.OracleScene.from_scene(sc)
+    view = synth.View(eye=(0.4, 0.7, 2.3))
+    W = Hh = 16
+    r = os_.render(view, W, Hh, 512, 1e-4)
+    agree = labelled = 0
+    for p in range(W * Hh):
+        o, d = O.camera_ray(view, W, Hh, p // W, p % W)
+        ok, tn, tf = os_.slab(o, d)
+        bf_t = None
+        t0 = max(tn, 0.0)
+        fprev = None
+        while ok and t0 < tf and bf_t is None:
+            ts = np.arange(t0, min(t0 + 0.2, tf), 1e-4)
+            f = _np_sdf_world(sc, o[None] + ts[:, None] * d[None])
+            if fprev is not None:
+                f = np.r_[fprev, f]; ts = np.r_[ts[0] - 1e-4, ts]
+            cross = np.nonzero((f[:-1] > 0) & (f[1:] <= 0))[0]
+            if f[0] <= 0 and fprev is None:
+                bf_t = ts[0]
+            elif len(cross):
+                a, b = ts[cross[0]], ts[cross[0] + 1]
+                while b - a > 1e-12:
+                    m = 0.5 * (a + b)
+                    if _np_sdf_world(sc, (o + m * d)[None])[0] > 0:
+                        a = m
+                    else:
+                        b = m
+                bf_t = 0.5 * (a + b)
+            fprev = f[-1]
+            t0 = ts[-1] + 1e-4
+        if (bf_t is not None) == bool(r["hit"][p]):
+            agree += 1
+            if bf_t is not None:
+                assert abs(r["depth"][p] - bf_t) <= 1e-6, (p, r["depth"][p], bf_t)
+        else:
+            grazing = 0 < r["fmin"][p] < 1e-4
+            assert r["status"][p] == O.BUDGET_MISS or grazing, (p, r["status"][p], bf_t)
+            labelled += 1
+    assert r["hit"].sum() > 50
+    assert labelled <= 3
+
+
+def test_render_subset_and_threads_consistent():
+    sc = synth.config_scene("c1")
+    os_ = O.OracleScene.from_scene(sc)
+    view = synth.front_view()
+    full = os_.render(view, 64, 64, 64, 1e-4, nthreads=4)
+    one = os_.render(view, 64, 64, 64, 1e-4, nthreads=1)
+    for k in full:
+        np.testing.assert_array_equal(full[k], one[k])
+    pix = synth.sample_pixels(64, 64, 300, seed=9)
+    sub = os_.render(view, 64, 64, 64, 1e-4, pixels=pix)
+    for k in ("rgb", "depth", "normal", "hit", "steps"):
+        np.testing.assert_array_equal(sub[k], full[k][pix])
+    # misses have background, zero depth and normal
+    m = full["hit"] == 0
+    assert m.any() and (full["depth"][m] == 0).all() and (full["rgb"][m] == 0).all()
+    assert (full["status"][m] != O.HIT).all()
