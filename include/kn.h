@@ -1,0 +1,206 @@
+/* kn.h -- C ABI of the MI355X KiloNeuS renderer.
+ *
+ * KiloNeuS (arXiv 2206.10885) represents an object as a regular N^3 grid
+ * over a fixed box, each cell holding a small SDF MLP and a small color MLP
+ * (Sec. 3.1).  This library renders it: camera rays are clipped to the box,
+ * sphere-traced through the grid (each step evaluates the MLP of the cell
+ * the ray is in), and each hit is shaded with the normalised analytic SDF
+ * gradient and the cell's color MLP (Sec. 3.4.1).
+ *
+ * Conventions for every call:
+ *  - Every function returns kn_status.  Negative values are errors; the
+ *    message of the calling thread's last error is kn_last_error().  No C++
+ *    exception crosses this boundary.
+ *  - A call that fails validation changes no output buffer.
+ *  - After a device (HIP) error the context is poisoned: later calls on it
+ *    return KN_E_DEVICE.
+ *  - All calls are thread-safe.  GPU work of one context is serialised on
+ *    the streams named below.
+ *  - "DEVICE pointer" means memory on the context's HIP device (for example
+ *    the data pointer of a torch tensor on that device); "HOST pointer"
+ *    means ordinary CPU memory.
+ */
+#ifndef KN_H
+#define KN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KN_ABI_VERSION 1u
+
+typedef enum {
+  KN_OK = 0,
+  KN_PENDING = 1,          /* serve_poll: request not finished yet */
+  KN_E_INVALID = -1,       /* bad argument (message says which) */
+  KN_E_NOMEM = -2,         /* device allocation failed or HBM budget exceeded */
+  KN_E_NOT_FOUND = -3,     /* unknown scene or request id */
+  KN_E_BUSY = -4,          /* scene still used by queued or running requests */
+  KN_E_DEVICE = -5,        /* HIP error; the context is poisoned */
+  KN_E_TIMEOUT = -6,       /* serve_poll: timeout elapsed */
+  KN_E_UNSUPPORTED = -7,   /* valid but not implemented (e.g. an MLP shape) */
+  KN_E_SHUTDOWN = -8       /* serving loop not running */
+} kn_status;
+
+typedef enum {
+  KN_FP32 = 0,             /* march weights and activations in float32 */
+  KN_BF16 = 1,             /* march in bfloat16 (RNE), float32 accumulate */
+  KN_FP8_E4M3 = 2          /* march in OCP fp8 e4m3 with per-(cell, layer) scales */
+} kn_precision;
+
+typedef struct kn_ctx kn_ctx;
+typedef uint32_t kn_scene_id;
+typedef uint64_t kn_request_id;
+
+/* Creates a context on HIP device `hip_device`.  `hbm_budget_bytes` caps
+ * the device memory the context may hold for scenes, ray state and serving
+ * requests (0 = 90% of the device's free memory).  *out receives the
+ * context; it owns every device allocation it makes.
+ * Errors: KN_E_INVALID (out NULL, bad device), KN_E_DEVICE. */
+kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out);
+
+/* Stops serving if running, frees every scene and buffer, destroys ctx. */
+kn_status kn_ctx_destroy(kn_ctx* ctx);
+
+/* Message of the calling thread's last failed call ("" if none).  Valid
+ * until that thread's next kn_ call. */
+const char* kn_last_error(void);
+
+/* ---------------------------------------------------------------------
+ * Scenes (Sec. 3.1).  Host parameter layout, one float32 block per cell,
+ * cells ordered g = ix + N*(iy + N*iz), ix along x:
+ *   SDF block (KiloSDF, eq. 3; softplus_beta activations), P_sdf floats:
+ *     W1[H][39]  b1[H]  W2[H][H]  b2[H]  W3[16][H]  b3[16]
+ *     input: gamma_6 of the cell-local position x_l = (x - c)/h, raw
+ *     coordinates first, then per axis sin(2^k pi x), cos(2^k pi x),
+ *     k = 0..5 (eq. 1-2); output row 0 = SDF d in world units, rows 1..15
+ *     = feature z.
+ *   Color block (KiloColor, eq. 4), P_col floats:
+ *     Wc1[32][48]  bc1[32]  Wc2[3][32]  bc2[3]
+ *     input [x_l(3), gamma_4(v)(27), n(3), z(15)], ReLU hidden layer,
+ *     sigmoid output; v is the unit ray direction.
+ *   P_sdf = 39H + H + H*H + H + 16H + 16; P_col = 1667.
+ * Supported: grid_n 1..64 (N^3 <= 2^18 cells), sdf_hidden 32 or 64,
+ * sdf_layers 2, feat_dim 15, col_hidden 32, col_layers 1, col_in_has_x 1,
+ * pos_freqs 6, dir_freqs 4; anything else returns KN_E_UNSUPPORTED.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  uint32_t abi_version;            /* KN_ABI_VERSION */
+  uint32_t grid_n;                 /* N */
+  float bbox_min[3], bbox_max[3];  /* the paper's box is [-1,1]^3 */
+  uint32_t pos_freqs, dir_freqs;   /* 6, 4 */
+  uint32_t sdf_hidden, sdf_layers, feat_dim;   /* 32|64, 2, 15 */
+  uint32_t col_hidden, col_layers, col_in_has_x; /* 32, 1, 1 */
+  float softplus_beta;             /* 100 */
+  const float* sdf_params;         /* HOST, [N^3][P_sdf], copied by the call */
+  const float* col_params;         /* HOST, [N^3][P_col], copied by the call */
+  uint32_t precisions;             /* bitmask of low-precision copies to keep
+                                      resident: bit KN_BF16, bit KN_FP8_E4M3
+                                      (the float32 copy is always kept) */
+} kn_scene_desc;
+
+/* Copies and packs a scene onto the device.  The host arrays may be freed
+ * when the call returns.  Errors: KN_E_INVALID, KN_E_UNSUPPORTED,
+ * KN_E_NOMEM (budget), KN_E_DEVICE. */
+kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* desc, kn_scene_id* out);
+
+/* Frees a scene.  KN_E_BUSY while serving requests still reference it. */
+kn_status kn_scene_destroy(kn_ctx* ctx, kn_scene_id scene);
+
+/* ---------------------------------------------------------------------
+ * Rendering (Sec. 3.4.1).
+ * Camera: pinhole at `eye` looking at `look_at`, `up` fixes the roll; the
+ * half-diagonal field of view has tangent tan_half_diag (0 selects
+ * 1/sqrt(|eye-look_at|^2 - 1), which makes the image diagonal tangent to
+ * the unit sphere).  Pixel (row i from the top, column j) looks through
+ * u = (2(j+1/2)/W - 1) tx, v = (1 - 2(i+1/2)/H) ty, tx = T W/sqrt(W^2+H^2),
+ * ty = T H/sqrt(W^2+H^2), d = normalize(f + u r + v u'), f = forward,
+ * r = normalize(f x up), u' = r x f.
+ * Tracing: the ray is clipped to the box; inside, each step evaluates the
+ * SDF MLP of the current cell; f < eps is a hit; otherwise the ray advances
+ * by f, but never past the current cell's exit plane: there it moves to the
+ * neighbouring cell.  A ray that leaves the grid, or uses max_steps SDF
+ * evaluations without a hit, misses.  Hits are refined by two guarded
+ * Newton steps along the ray (float32 weights), then depth, normal and
+ * color are computed there.
+ * --------------------------------------------------------------------- */
+typedef struct {
+  float eye[3], look_at[3], up[3];
+  float tan_half_diag;
+  uint32_t width, height;
+  uint32_t spp;                    /* 1 (primary rays through pixel centers) */
+  uint32_t bounces;                /* 0 */
+  uint32_t max_steps;              /* S, 1..1023 */
+  float eps;                       /* hit threshold, > 0 */
+  kn_precision precision;          /* weights used by the march */
+  uint64_t seed;                   /* random stream for path tracing */
+  const float* env_rgb;            /* DEVICE [env_h][env_w][3] or NULL (black) */
+  uint32_t env_w, env_h;
+} kn_camera;
+
+/* Per-pixel march record, for diagnostics and replay of a hit's shading:
+ * t_march = ray parameter where the march stopped, t_entry = where the ray
+ * entered that cell, cell = global cell index (-1 for a box miss), status =
+ * 0 box miss, 1 hit, 2 left the grid, 3 step budget used up. */
+typedef struct {
+  float t_march;
+  float t_entry;
+  int32_t cell;
+  int32_t status;
+} kn_trace_record;
+
+/* Output buffers, all DEVICE pointers owned by the caller, row-major
+ * [height][width] (rgb and normal with 3 floats per pixel).  Only rgb is
+ * required; NULL skips an output.  Misses get rgb = background (black, or
+ * the environment map looked up along the ray), depth = 0, normal = 0,
+ * hit = 0.  depth is the distance along the unit ray from the eye. */
+typedef struct {
+  float* rgb;
+  float* depth;
+  float* normal;
+  uint8_t* hit;
+  uint16_t* steps;                 /* SDF evaluations of the march */
+  kn_trace_record* trace;          /* optional diagnostics */
+  void* hip_stream;                /* hipStream_t to run on; NULL = ctx stream */
+} kn_frame;
+
+typedef struct {
+  double gpu_ms;                   /* first to last kernel of the call (hipEvents) */
+  double wall_ms;                  /* host time of the call */
+  uint64_t rays, evals, hits, rounds;
+} kn_stats;
+
+/* Renders one frame into `frame` and returns when it is complete on the
+ * stream.  Errors: KN_E_INVALID, KN_E_NOT_FOUND, KN_E_UNSUPPORTED,
+ * KN_E_NOMEM, KN_E_DEVICE. */
+kn_status kn_render(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const kn_frame* frame,
+                    kn_stats* stats_opt);
+
+/* Batched point query (the paper's "n MLPs on n batches of m points",
+ * Sec. 3.3): for each world point x (DEVICE float [n][3]) evaluates the
+ * SDF MLP of the cell containing x (points outside the box are clamped to
+ * the nearest cell): d (DEVICE float [n]), and optionally the world-space
+ * gradient of d (DEVICE float [n][3]) and the feature z (DEVICE float
+ * [n][15]).  `precision` selects the weights for d; gradients and features
+ * use float32.  Runs on `hip_stream` (NULL = ctx stream) and returns when
+ * done. */
+kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points,
+                   uint64_t n, float* d_out, float* grad_out, float* z_out, void* hip_stream);
+
+/* ---------------------------------------------------------------------
+ * Serving: a loop that keeps scenes resident and renders queued requests
+ * with continuous batching (requests arriving while others run join the
+ * shared ray pool as memory allows).
+ * --------------------------------------------------------------------- */
+kn_status kn_serve_start(kn_ctx* ctx, uint32_t max_inflight, kn_precision precision);
+kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam,
+                          const kn_frame* frame, kn_request_id* out);
+kn_status kn_serve_poll(kn_ctx* ctx, kn_request_id req, int64_t timeout_us, kn_stats* stats_opt);
+kn_status kn_serve_stop(kn_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,208 @@
+"""Thin ctypes binding of the C ABI in include/kn.h.
+
+Argument marshalling only: every step of rendering runs in the HIP library
+libkn.so.  torch provides device memory (output tensors) and the stream.
+Importing this module fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkn.so")
+
+KN_OK, KN_PENDING = 0, 1
+KN_FP32, KN_BF16, KN_FP8_E4M3 = 0, 1, 2
+KN_ABI_VERSION = 1
+_STATUS = {0: "KN_OK", 1: "KN_PENDING", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_NOT_FOUND",
+           -4: "KN_E_BUSY", -5: "KN_E_DEVICE", -6: "KN_E_TIMEOUT", -7: "KN_E_UNSUPPORTED",
+           -8: "KN_E_SHUTDOWN"}
+PRECISIONS = {"fp32": KN_FP32, "bf16": KN_BF16, "fp8": KN_FP8_E4M3}
+
+
+class KnError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class SceneDesc(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("grid_n", C.c_uint32),
+                ("bbox_min", C.c_float * 3), ("bbox_max", C.c_float * 3),
+                ("pos_freqs", C.c_uint32), ("dir_freqs", C.c_uint32),
+                ("sdf_hidden", C.c_uint32), ("sdf_layers", C.c_uint32), ("feat_dim", C.c_uint32),
+                ("col_hidden", C.c_uint32), ("col_layers", C.c_uint32), ("col_in_has_x", C.c_uint32),
+                ("softplus_beta", C.c_float),
+                ("sdf_params", C.POINTER(C.c_float)), ("col_params", C.POINTER(C.c_float)),
+                ("precisions", C.c_uint32)]
+
+
+class Camera(C.Structure):
+    _fields_ = [("eye", C.c_float * 3), ("look_at", C.c_float * 3), ("up", C.c_float * 3),
+                ("tan_half_diag", C.c_float), ("width", C.c_uint32), ("height", C.c_uint32),
+                ("spp", C.c_uint32), ("bounces", C.c_uint32), ("max_steps", C.c_uint32),
+                ("eps", C.c_float), ("precision", C.c_int), ("seed", C.c_uint64),
+                ("env_rgb", C.c_void_p), ("env_w", C.c_uint32), ("env_h", C.c_uint32)]
+
+
+class Frame(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("normal", C.c_void_p),
+                ("hit", C.c_void_p), ("steps", C.c_void_p), ("trace", C.c_void_p),
+                ("hip_stream", C.c_void_p)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("gpu_ms", C.c_double), ("wall_ms", C.c_double), ("rays", C.c_uint64),
+                ("evals", C.c_uint64), ("hits", C.c_uint64), ("rounds", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+EXPORTS = ["kn_ctx_create", "kn_ctx_destroy", "kn_last_error", "kn_scene_create",
+           "kn_scene_destroy", "kn_render", "kn_query", "kn_serve_start", "kn_serve_submit",
+           "kn_serve_poll", "kn_serve_stop"]
+
+_lib = None
+
+
+def lib():
+    """Loads libkn.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2206_10885_amd/build.py "
+                              "(or __graft_entry__.build()) first")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.kn_last_error.restype = C.c_char_p
+        L.kn_ctx_create.argtypes = [C.c_int, C.c_uint64, C.POINTER(vp)]
+        L.kn_ctx_destroy.argtypes = [vp]
+        L.kn_scene_create.argtypes = [vp, C.POINTER(SceneDesc), C.POINTER(C.c_uint32)]
+        L.kn_scene_destroy.argtypes = [vp, C.c_uint32]
+        L.kn_render.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame), C.POINTER(Stats)]
+        L.kn_query.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
+        L.kn_serve_start.argtypes = [vp, C.c_uint32, C.c_int]
+        L.kn_serve_submit.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame),
+                                      C.POINTER(C.c_uint64)]
+        L.kn_serve_poll.argtypes = [vp, C.c_uint64, C.c_int64, C.POINTER(Stats)]
+        L.kn_serve_stop.argtypes = [vp]
+        for name in EXPORTS:
+            if name != "kn_last_error":
+                getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise KnError(status, lib().kn_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def make_camera(view, width: int, height: int, max_steps: int, eps: float,
+                precision: str = "fp32", spp: int = 1, bounces: int = 0, seed: int = 0,
+                env=None) -> Camera:
+    env_ptr, ew, eh = None, 0, 0
+    if env is not None:
+        env_ptr, eh, ew = env.data_ptr(), env.shape[0], env.shape[1]
+    return Camera((C.c_float * 3)(*view.eye), (C.c_float * 3)(*view.look_at),
+                  (C.c_float * 3)(*view.up), float(view.tan_half_diag), width, height, spp,
+                  bounces, max_steps, eps, PRECISIONS[precision], seed, env_ptr, ew, eh)
+
+
+class Context:
+    """A kn_ctx on one HIP device (torch device index)."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        h = C.c_void_p()
+        check(lib().kn_ctx_create(device, hbm_budget_bytes, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if self.h:
+            check(lib().kn_ctx_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- scenes -------------------------------------------------------------
+    def scene_create(self, scene, precisions=("bf16",)) -> int:
+        sdf = np.ascontiguousarray(scene.sdf, np.float32)
+        col = np.ascontiguousarray(scene.col, np.float32)
+        bits = 0
+        for p in precisions:
+            bits |= 1 << PRECISIONS[p]
+        d = SceneDesc(KN_ABI_VERSION, scene.N, (C.c_float * 3)(*scene.bbox_min),
+                      (C.c_float * 3)(*scene.bbox_max), 6, 4, scene.H, 2, 15, 32, 1, 1,
+                      float(scene.beta), sdf.ctypes.data_as(C.POINTER(C.c_float)),
+                      col.ctypes.data_as(C.POINTER(C.c_float)), bits)
+        sid = C.c_uint32()
+        check(lib().kn_scene_create(self.h, C.byref(d), C.byref(sid)))
+        return sid.value
+
+    def scene_destroy(self, sid: int):
+        check(lib().kn_scene_destroy(self.h, sid))
+
+    # -- rendering ----------------------------------------------------------
+    def alloc_frame(self, width: int, height: int, with_trace: bool = False) -> dict:
+        import torch
+        dev = torch.device("cuda", self.device)
+        f = dict(rgb=torch.empty((height, width, 3), dtype=torch.float32, device=dev),
+                 depth=torch.empty((height, width), dtype=torch.float32, device=dev),
+                 normal=torch.empty((height, width, 3), dtype=torch.float32, device=dev),
+                 hit=torch.empty((height, width), dtype=torch.uint8, device=dev),
+                 steps=torch.empty((height, width), dtype=torch.int16, device=dev))
+        if with_trace:
+            f["trace"] = torch.empty((height, width, 4), dtype=torch.int32, device=dev)
+        return f
+
+    def render_into(self, sid: int, cam: Camera, out: dict, stream=None) -> dict:
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
+                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
+                   C.c_void_p(stream.cuda_stream))
+        st = Stats()
+        check(lib().kn_render(self.h, sid, C.byref(cam), C.byref(fr), C.byref(st)))
+        return st.as_dict()
+
+    def render(self, sid: int, view, width: int, height: int, max_steps: int, eps: float,
+               precision: str = "fp32", with_trace: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, precision)
+        out = self.alloc_frame(width, height, with_trace)
+        out["stats"] = self.render_into(sid, cam, out)
+        return out
+
+    def query(self, sid: int, points, precision: str = "fp32", grad: bool = False,
+              feat: bool = False, stream=None) -> dict:
+        import torch
+        pts = points.contiguous()
+        n = pts.shape[0]
+        d = torch.empty(n, dtype=torch.float32, device=pts.device)
+        g = torch.empty((n, 3), dtype=torch.float32, device=pts.device) if grad else None
+        z = torch.empty((n, 15), dtype=torch.float32, device=pts.device) if feat else None
+        if stream is None:
+            stream = torch.cuda.current_stream(pts.device)
+        check(lib().kn_query(self.h, sid, PRECISIONS[precision], _ptr(pts), n, _ptr(d), _ptr(g),
+                             _ptr(z), C.c_void_p(stream.cuda_stream)))
+        return dict(d=d, grad=g, z=z)
