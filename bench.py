@@ -1,0 +1,192 @@
+"""Benchmark: shaded rays/s of the KiloNeuS hot path on one MI355X.
+
+Workload (C3): a 16^3 grid over [-1,1]^3 of per-cell MLPs (SDF: 39 -> 2x64
+softplus -> 16; color: 48 -> 32 ReLU -> 3 sigmoid), seeded geometric
+initialisation toward a sphere of radius 0.6 with N(0, 0.02^2) noise,
+1920x1080 primary rays per frame, 8 seeded orbit views cycled, at most 128
+sphere-tracing steps, eps 1e-4.  One step = one frame (2,073,600 rays)
+through every stage: ray generation and box clip, per-round cell binning,
+the march (bfloat16 MLP on MFMA), hit binning, refinement and shading.
+The same frames are then timed with the float32 march for the ratio.
+
+Prints one JSON line (see the design doc for the field definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "shaded rays/sec at 1920×1080 (BF16/FP8 vs FP32) + p50/p99 frame latency"
+# Peaks (MI355X): dense float32 MFMA 157.3 TFLOP/s; transcendentals (exp2,
+# log2, sin, cos, rcp) issue at a quarter of the float32 FMA rate of 128
+# lanes/clock per CU: 256 CU x 32 /clock x 2.4 GHz = 19.7 T/s.
+PEAK_FP32_MFMA = 157.3e12
+PEAK_TRANS = 256 * 32 * 2.4e9
+
+
+def march_work(H: int) -> dict:
+    """Algorithmic work of one SDF evaluation in the march (per point):
+    dense MLP FLOPs and transcendental operations (exp and log per softplus
+    unit, sin or cos per encoding component)."""
+    flop = 2 * (39 * H + H * H + H)
+    trans = 2 * (2 * H) + 36
+    return dict(flop=flop, trans=trans)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=56, help="timed frames")
+    ap.add_argument("--warmup", type=int, default=16, help="untimed frames")
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle time")
+    return ap.parse_args()
+
+
+def pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return 0.0
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = math.floor(k), math.ceil(k)
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def timed_frames(ctx, sid, cams, out, steps, warmup, torch):
+    for i in range(warmup):
+        ctx.render_into(sid, cams[i % len(cams)], out)
+    torch.cuda.synchronize()
+    gpu_ms, wall_ms, march_ms, launches, evals, hits = [], [], [], 0, 0, 0
+    t0 = time.perf_counter()
+    for i in range(steps):
+        w0 = time.perf_counter()
+        st = ctx.render_into(sid, cams[i % len(cams)], out, kernel_times=True)
+        wall_ms.append((time.perf_counter() - w0) * 1e3)
+        gpu_ms.append(st["gpu_ms"])
+        march_ms.append(st["march_ms"])
+        launches += st["march_launches"]
+        evals += st["evals"]
+        hits += st["hits"]
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return dict(total_s=total, gpu_ms=gpu_ms, wall_ms=wall_ms, march_ms=sum(march_ms),
+                march_launches=launches, evals=evals, hits=hits)
+
+
+def cpu_baseline(scene, views, W, H, S, eps, target_s):
+    """The FP64 oracle on a seeded pixel sample of the same frames."""
+    from oracle import oracle as O
+    from paper_2206_10885_amd import synth
+    cores = min(16, os.cpu_count() or 1)
+    os_ = O.OracleScene.from_scene(scene)
+    n = 2000
+    pix = synth.sample_pixels(W, H, n, seed=77)
+    t = time.perf_counter()
+    os_.render(views[0], W, H, S, eps, pixels=pix, nthreads=cores)
+    dt = time.perf_counter() - t
+    n = int(min(W * H, max(2000, n * target_s / max(dt, 1e-3) / len(views))))
+    total_px, total_t = 0, 0.0
+    for vi, v in enumerate(views):
+        pix = synth.sample_pixels(W, H, n, seed=77 + vi)
+        t = time.perf_counter()
+        os_.render(v, W, H, S, eps, pixels=pix, nthreads=cores)
+        total_t += time.perf_counter() - t
+        total_px += len(pix)
+    return dict(value=total_px / total_t, unit="rays/s", cores=cores, kind="oracle",
+                sample=f"{total_px} seeded pixels ({n} per view) of the 8 C3 views, FP64, "
+                       f"{total_t:.1f} s")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the ray "
+                                   "sharding across GPUs is described in DESIGN.md)"}))
+        sys.exit(2)
+    import torch
+
+    from paper_2206_10885_amd import kn, synth
+
+    c = synth.CONFIGS["c3"]
+    W, H, S, eps = c["width"], c["height"], c["max_steps"], c["eps"]
+    scene = synth.config_scene("c3")
+    views = synth.config_views("c3")
+    ctx = kn.Context(0)
+    sid = ctx.scene_create(scene, precisions=("bf16",))
+    out = ctx.alloc_frame(W, H)
+    rays = W * H
+
+    cams = [kn.make_camera(v, W, H, S, eps, args.precision) for v in views]
+    r = timed_frames(ctx, sid, cams, out, args.steps, args.warmup, torch)
+    value = args.steps * rays / r["total_s"]
+    work = march_work(scene.H)
+    avg_launch_s = r["march_ms"] / 1e3 / max(1, r["march_launches"])
+    evals_per_launch = r["evals"] / max(1, r["march_launches"])
+    if args.precision == "bf16":
+        achieved = evals_per_launch * work["trans"] / avg_launch_s
+        roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_TRANS / 1e12,
+                        unit="Tops/s transcendental", frac=achieved / PEAK_TRANS, traffic=None,
+                        kernel="k_march<64,bf16>", avg_launch_ms=avg_launch_s * 1e3,
+                        evals_per_launch=evals_per_launch)
+    else:
+        achieved = evals_per_launch * work["flop"] / avg_launch_s
+        roofline = dict(bound="mfma", achieved=achieved / 1e12, peak=PEAK_FP32_MFMA / 1e12,
+                        unit="TFLOP/s", frac=achieved / PEAK_FP32_MFMA, traffic=None,
+                        kernel="k_march<64,fp32>", avg_launch_ms=avg_launch_s * 1e3,
+                        evals_per_launch=evals_per_launch)
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "rays/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["total_s"] * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": "C3: 16^3 grid of per-cell SDF MLPs (39->2x64 softplus->16) and "
+                               "color MLPs (48->32->3), 1920x1080, 8 seeded orbit views, "
+                               "<=128 steps, eps 1e-4; march in " + args.precision +
+                               ", refinement and shading in fp32",
+                   "rays_per_frame": rays, "views": len(views)},
+        "frame_ms_p50": pct(r["gpu_ms"], 50),
+        "frame_ms_p99": pct(r["gpu_ms"], 99),
+        "frame_wall_ms_p50": pct(r["wall_ms"], 50),
+        "frame_wall_ms_p99": pct(r["wall_ms"], 99),
+        "evals_per_ray": r["evals"] / (args.steps * rays),
+        "hit_fraction": r["hits"] / (args.steps * rays),
+        "roofline": roofline,
+    }
+    if not args.no_fp32 and args.precision != "fp32":
+        cams32 = [kn.make_camera(v, W, H, S, eps, "fp32") for v in views]
+        r32 = timed_frames(ctx, sid, cams32, out, args.steps, args.warmup // 2, torch)
+        v32 = args.steps * rays / r32["total_s"]
+        line["fp32_value"] = v32
+        line["bf16_over_fp32"] = value / v32
+        line["fp32_frame_ms_p50"] = pct(r32["gpu_ms"], 50)
+        line["fp32_frame_ms_p99"] = pct(r32["gpu_ms"], 99)
+        a32 = (r32["evals"] / max(1, r32["march_launches"])) * work["flop"] / (
+            r32["march_ms"] / 1e3 / max(1, r32["march_launches"]))
+        line["fp32_march_roofline"] = dict(bound="mfma", achieved=a32 / 1e12, peak=PEAK_FP32_MFMA / 1e12,
+                                           unit="TFLOP/s", frac=a32 / PEAK_FP32_MFMA)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(scene, views, W, H, S, eps, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

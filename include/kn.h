@@ -170,6 +170,14 @@ typedef struct {
   double gpu_ms;                   /* first to last kernel of the call (hipEvents) */
   double wall_ms;                  /* host time of the call */
   uint64_t rays, evals, hits, rounds;
+  uint32_t kernel_times;           /* in: nonzero => also time each march and
+                                      shading launch with hipEvents (adds two
+                                      event records per launch) */
+  uint32_t march_launches;         /* out (kernel_times): march launches */
+  double march_ms;                 /* out (kernel_times): summed march kernel time */
+  double shade_ms;                 /* out (kernel_times): shading kernel time */
+  uint64_t march_tiles;            /* out: 16-ray MFMA tiles evaluated by the march */
+  uint64_t march_chunks;           /* out: march work items (<= 256 rays of one cell) */
 } kn_stats;
 
 /* Renders one frame into `frame` and returns when it is complete on the

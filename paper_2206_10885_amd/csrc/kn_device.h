@@ -28,9 +28,11 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 
 // softplus_beta(u) = max(u, 0) + log1p(exp(-beta |u|)) / beta, evaluated as
 // max(u,0) + log2(1 + 2^(-beta log2e |u|)) * ln2 / beta.
+// max(u, 0) is written as (u + |u|) / 2, which is exact and avoids the NaN
+// canonicalisation the compiler adds in front of v_max_f32.
 __device__ __forceinline__ float softplus(float u, SoftplusK k) {
   float e = __builtin_amdgcn_exp2f(k.nbl2e * fabsf(u));
-  return fmaxf(u, 0.0f) + __builtin_amdgcn_logf(1.0f + e) * k.ln2b;
+  return fmaf(__builtin_amdgcn_logf(1.0f + e), k.ln2b, 0.5f * (u + fabsf(u)));
 }
 // softplus and its derivative sigmoid(beta u) from one exponential
 __device__ __forceinline__ float softplus_d(float u, SoftplusK k, float* dsp) {

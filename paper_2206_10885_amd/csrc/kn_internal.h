@@ -3,12 +3,15 @@
 // Data layout in HBM (per render):
 //   RayStatic[rid]   32 B  origin, box exit t_far, direction, output pixel
 //   RayRec  lists    16 B  march state (t, t_entry, cell|steps, rid)
-//     unsorted list U  : appended by ray generation / the march
-//     sorted list  S   : U counting-sorted by global cell (one bin per cell)
+//     U  : rays for the next round; ray generation writes one per pixel,
+//          the march writes each chunk's leavers into that chunk's range
+//     S  : U counting-sorted by global cell (one bin per cell)
+//     HL : hits, indexed by ray id (key 0xFFFFFFFF = no hit)
 //   counts[2][cells] : per-cell arrivals for the current / next round
-//   cursor[cells]    : scatter positions, offsets[cells+1] : bin starts
-//   chunks[]         : (cell, start, count<=T) work items of one round
-//   hit list / sorted hits, hit_count[cells] : hits binned by cell for shading
+//   cursor[cells]    : scatter positions (bin starts)
+//   chunks[2][]      : (cell | count << 22, start) work items of a round
+//   chunk_out[2][]   : per chunk, rays leaving through each of the 6 faces
+//   hit_count[cells] : hits binned by cell for shading
 // Packed per-cell weights (built on the host, see runtime):
 //   march block  : MFMA A-operand fragments of W1, W2 in per-lane order
 //                  (float32, or bfloat16 bits), then float32 vectors
@@ -52,17 +55,22 @@ struct TraceRec {   // mirrors kn_trace_record
 };
 
 // Device-side counters of one render (zeroed per frame).
+constexpr int kGroups = 8;          // work ranges, one per XCD-like group of workgroups
+constexpr int kGroupStride = 32;    // words between range cursors (one 128-byte line each)
+
 struct Ctrl {
-  uint32_t n_list[2];      // records in U for round parity 0/1
-  uint32_t n_chunks;       // chunk descriptors of the current round
-  uint32_t chunk_next;     // work cursor of the current round
-  uint32_t n_hits;         // records in the hit list
+  uint32_t n_chunks[3];    // chunks of the round with parity 0 / 1; of the hit binning
   uint32_t pad0;
   unsigned long long evals;  // SDF evaluations by the march
-  unsigned long long hits_shaded;
-  uint32_t rounds_active;  // rounds that had work
-  uint32_t pad1[3];
+  unsigned long long tiles;  // 16-ray tiles evaluated by the march
+  unsigned long long chunks; // march work items
+  uint32_t n_hits;           // hits shaded
+  uint32_t pad[3];
+  uint32_t grab[kGroups * kGroupStride];  // work cursors of the current kernel, per range
+  uint32_t grab0[kGroups * kGroupStride]; // their initial values
 };
+
+constexpr uint32_t kChunk = 256;    // rays per march work item (one per thread)
 
 // Encoding slot assignment: lane group g (lane / 16) computes the values of
 // slots j = 0..9; slot (j, g) holds gamma_6 component pe_index(j, g), or

@@ -3,14 +3,16 @@
 // Wavefront design (one frame):
 //   k_raygen   pinhole rays, box clip (Sec. 3.4.1), entry cell, box misses
 //   per round: k_scan    per-cell exclusive scan -> bin starts, work chunks
-//              k_scatter counting-sort of the round's rays by global cell
-//              k_march   one workgroup per chunk of a cell's bin: the cell's
-//                        SDF MLP weights are staged once in LDS then held in
-//                        registers as MFMA fragments; 16-ray tiles step the
-//                        sphere tracer while rays stay in the cell, empty
-//                        tile slots are refilled from the chunk; rays that
-//                        cross into a neighbour cell are compacted (wave
-//                        ballot + one atomic per wave) into the next round
+//              k_scatter counting sort of the round's rays by global cell
+//                        (round 0: per ray; later rounds: per chunk and exit
+//                        face, six atomics per chunk)
+//              k_march   one workgroup per chunk (<= 256 rays) of a cell's
+//                        bin: the cell's MLP weights (MFMA A fragments) and
+//                        the rays are staged in LDS; the four waves step
+//                        16-ray tiles in passes over an LDS active list while
+//                        rays stay in the cell; rays leaving for a neighbour
+//                        cell are written to the chunk's own output range,
+//                        grouped by exit face (no global list counter)
 //   after the rounds: hits are binned by cell the same way, then k_shade
 //              refines each hit with two Newton steps, takes the normalised
 //              analytic gradient (forward-mode: value + 3 tangent columns per
@@ -19,6 +21,8 @@
 #include "kn_launch.h"
 
 namespace kn {
+
+constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;  // record without a cell (box miss, no hit)
 
 // ---------------------------------------------------------------------------
 // wave-aggregated atomics
@@ -49,17 +53,6 @@ __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t 
     todo &= ~grp;
   }
   return pos;
-}
-
-// one atomic per wave on a list counter; returns this lane's slot (valid lanes)
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool valid) {
-  uint64_t m = __ballot(valid);
-  uint32_t base = 0;
-  if (m) {
-    if (lane_id() == __ffsll((unsigned long long)m) - 1) base = atomicAdd(counter, (uint32_t)__popcll(m));
-    base = __shfl(base, __ffsll((unsigned long long)m) - 1);
-  }
-  return base + (uint32_t)__popcll(m & lanemask_lt());
 }
 
 __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int steps, float t,
@@ -124,70 +117,175 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
       }
       cell = sg.cell_base + (uint32_t)(idx[0] + sg.N * (idx[1] + sg.N * idx[2]));
       a.rs[pix] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2], pix};
+      a.U[pix] = RayRec{t0, t0, cell, pix};
     } else {
+      a.U[pix] = RayRec{0.0f, 0.0f, kInvalidKey, pix};
       write_miss(a.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss);
     }
   }
-  const uint32_t pos = wave_append(&a.ctrl->n_list[0], inbox);
-  if (inbox) a.U[pos] = RayRec{t0, t0, cell, pix};
   atomic_count_grouped(a.counts, cell, inbox);
 }
 
 // ---------------------------------------------------------------------------
 // per-round scan (one workgroup): bin starts, scatter cursors, work chunks
 // ---------------------------------------------------------------------------
+// inclusive prefix sum over the 64 lanes of a wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t u = __shfl_up(v, off);
+    if (lane >= off) v += u;
+  }
+  return v;
+}
+
 __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
-  __shared__ uint32_t s_r[1024], s_k[1024];
-  const uint32_t tid = threadIdx.x;
+  __shared__ uint32_t s_wr[16], s_wk[16];
+  const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id(), wave = tid >> 6;
   const uint32_t per = (a.C + 1023u) / 1024u;
   const uint32_t c0 = min(a.C, tid * per), c1 = min(a.C, c0 + per);
   uint32_t sr = 0, sk = 0;
   for (uint32_t c = c0; c < c1; ++c) {
-    uint32_t n = a.counts[c];
+    const uint32_t n = a.counts[c];
     sr += n;
     sk += (n + a.T - 1u) / a.T;
   }
-  s_r[tid] = sr;
-  s_k[tid] = sk;
-  __syncthreads();
-  for (uint32_t off = 1; off < 1024u; off <<= 1) {
-    uint32_t vr = tid >= off ? s_r[tid - off] : 0u;
-    uint32_t vk = tid >= off ? s_k[tid - off] : 0u;
-    __syncthreads();
-    s_r[tid] += vr;
-    s_k[tid] += vk;
-    __syncthreads();
+  const uint32_t ir = wave_incl_scan(sr), ik = wave_incl_scan(sk);
+  if (lane == 63) {
+    s_wr[wave] = ir;
+    s_wk[wave] = ik;
   }
-  uint32_t R = s_r[tid] - sr, K = s_k[tid] - sk;
+  __syncthreads();
+  if (wave == 0) {
+    const uint32_t vr = lane < 16 ? s_wr[lane] : 0u, vk = lane < 16 ? s_wk[lane] : 0u;
+    const uint32_t er = wave_incl_scan(vr) - vr, ek = wave_incl_scan(vk) - vk;
+    if (lane < 16) {
+      s_wr[lane] = er;
+      s_wk[lane] = ek;
+    }
+    const uint32_t nch = __shfl(ek + vk, 15);
+    if (lane == 15) {
+      *a.n_chunks = nch;
+      if (a.zero_word) *a.zero_word = 0u;
+      if (a.total) *a.total = er + vr;
+    }
+    if (lane < (uint32_t)kGroups) {
+      const uint32_t g0 = (uint32_t)(((uint64_t)nch * lane) / kGroups);
+      a.grab[lane * kGroupStride] = g0;
+      a.grab0[lane * kGroupStride] = g0;
+    }
+  }
+  __syncthreads();
+  uint32_t R = s_wr[wave] + ir - sr, K = s_wk[wave] + ik - sk;
   for (uint32_t c = c0; c < c1; ++c) {
-    uint32_t n = a.counts[c];
+    const uint32_t n = a.counts[c];
     a.cursor[c] = R;
     for (uint32_t i = 0; i < n; i += a.T) {
-      uint32_t m = min(a.T, n - i);
+      const uint32_t m = min(a.T, n - i);
       a.chunks[K++] = make_uint2(c | (m << kCellBits), R + i);
     }
     R += n;
     if (a.zero_counts) a.counts[c] = 0u;
   }
-  if (tid == 1023u) {
-    *a.n_chunks = s_k[1023];
-    *a.chunk_next = 0u;
-    if (a.zero_word) *a.zero_word = 0u;
+}
+
+// ---------------------------------------------------------------------------
+// Work distribution without one hot counter: the n items of a kernel are
+// split into kGroups contiguous ranges, each with its own cursor on its own
+// cache line; a workgroup takes `batch` consecutive items from the range of
+// its group (blockIdx % kGroups, which follows the round-robin placement of
+// workgroups on the XCDs) and steals from the other ranges once its own is
+// used up.  Returns false when every range is exhausted.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool grab_batch(uint32_t* grab, uint32_t n, uint32_t batch, uint32_t& first,
+                                           uint32_t& last) {
+  const uint32_t home = blockIdx.x % (uint32_t)kGroups;
+  for (uint32_t k = 0; k < (uint32_t)kGroups; ++k) {
+    const uint32_t x = (home + k) % (uint32_t)kGroups;
+    const uint32_t end = (uint32_t)(((uint64_t)n * (x + 1)) / kGroups);
+    if (*(volatile uint32_t*)&grab[x * kGroupStride] >= end) continue;  // early-out; the atomic decides
+    const uint32_t j = atomicAdd(&grab[x * kGroupStride], batch);
+    if (j < end) {
+      first = j;
+      last = min(j + batch, end);
+      return true;
+    }
   }
+  return false;
+}
+
+// thread 0 of the shading and query kernels: next chunk into s[0..3]
+__device__ __forceinline__ void next_item(uint32_t* grab, uint32_t n, const uint2* chunks, uint32_t* s) {
+  if (s[4] >= s[5]) {
+    uint32_t first, last;
+    if (!grab_batch(grab, n, 2u, first, last)) {
+      s[3] = 0u;
+      return;
+    }
+    s[4] = first;
+    s[5] = last;
+  }
+  const uint2 c = chunks[s[4]++];
+  s[0] = c.x & kCellMask;
+  s[1] = c.y;
+  s[2] = c.x >> kCellBits;
+  s[3] = 1u;
 }
 
 // ---------------------------------------------------------------------------
 // counting-sort scatter of a record list by cell
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
-  const uint32_t n = *a.n_in;
+  const uint32_t n = a.n;
   for (uint32_t base = blockIdx.x * 256u; base < n; base += gridDim.x * 256u) {
     const uint32_t i = base + threadIdx.x;
-    const bool valid = i < n;
-    RayRec r = valid ? a.in[i] : RayRec{0, 0, 0, 0};
+    RayRec r = i < n ? a.in[i] : RayRec{0, 0, kInvalidKey, 0};
+    const bool valid = r.key != kInvalidKey;
     const uint32_t cell = r.key & kCellMask;
     const uint32_t pos = atomic_slot_grouped(a.cursor, cell, valid);
     if (valid) a.out[pos] = r;
+  }
+}
+
+// Neighbour of `cell` through face f = 2 * axis + (positive side); f = 6 is
+// the cell itself (rays that used their step quota in this round).
+__device__ __forceinline__ uint32_t neighbor_cell(const SceneGeom& sg, uint32_t cell, int face) {
+  if (face == 6) return cell;
+  const uint32_t N = (uint32_t)sg.N, lc = cell - sg.cell_base;
+  int idx[3] = {(int)(lc % N), (int)((lc / N) % N), (int)(lc / (N * N))};
+  idx[face >> 1] += (face & 1) ? 1 : -1;
+  return sg.cell_base + (uint32_t)(idx[0] + (int)N * (idx[1] + (int)N * idx[2]));
+}
+
+// Rounds >= 1: each chunk of the previous round left its next-round rays in
+// its own range of U, grouped by exit face (and a seventh group that stays
+// in the cell); one wave moves each run into its cell's bin (one atomic per
+// run).
+__global__ __launch_bounds__(256) void k_scatter_chunks(ScatterChunksArgs a) {
+  const uint32_t nch = *a.n_chunks;
+  const int lane = lane_id();
+  const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  for (uint32_t j = wave; j < nch; j += nwaves) {
+    const uint2 c = a.chunks[j];
+    const uint32_t cell = c.x & kCellMask, start = c.y;
+    const uint4 fa = a.chunk_out[2 * j], fb = a.chunk_out[2 * j + 1];
+    const uint32_t faces[7] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z};
+    // lanes 0..6 reserve the seven runs' destinations at once
+    uint32_t mine = 0, dst = 0;
+#pragma unroll
+    for (int f = 0; f < 7; ++f)
+      if (lane == f) mine = faces[f];
+    if (lane < 7 && mine) dst = atomicAdd(&a.cursor[neighbor_cell(a.sg, cell, lane)], mine);
+    uint32_t off = 0;
+#pragma unroll
+    for (int f = 0; f < 7; ++f) {
+      const uint32_t n = faces[f];
+      const uint32_t base = __shfl(dst, f);
+      for (uint32_t i = (uint32_t)lane; i < n; i += 64u) a.S[base + i] = a.U[start + off + i];
+      off += n;
+    }
   }
 }
 
@@ -197,135 +295,245 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
 // 16b + 4g + r of point p.  Returns the SDF value d for the lane's point
 // (identical in the 4 lanes of the point).
 // ---------------------------------------------------------------------------
+// float32: A fragments from the LDS block ([slot/4][lane][slot%4] floats)
+template <int H>
+__device__ __forceinline__ float march_eval_f32(const float* blk, int lane, int g,
+                                                const float (&v)[kPeSlots], SoftplusK k) {
+  constexpr int NB = H / 16, S1 = NB * kPeSlots, S2 = NB * (H / 4), SF = S1 + S2;
+  const f32x4* fr = reinterpret_cast<const f32x4*>(blk);
+  const float* vec = blk + 64 * SF;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+  {
+    float w[S1];
+#pragma unroll
+    for (int s4 = 0; s4 < S1 / 4; ++s4) {
+      const f32x4 t = fr[s4 * 64 + lane];
+      w[4 * s4 + 0] = t[0]; w[4 * s4 + 1] = t[1]; w[4 * s4 + 2] = t[2]; w[4 * s4 + 3] = t[3];
+    }
+#pragma unroll
+    for (int q = 0; q < kPeSlots; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc[b] = mfma_f32(w[b * kPeSlots + q], v[q], acc[b]);
+  }
+  float a1[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a1[b][r] = softplus(acc[b][r], k);
+  f32x4 acc2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+  {
+    float w[S2];
+#pragma unroll
+    for (int s4 = 0; s4 < S2 / 4; ++s4) {
+      const f32x4 t = fr[(S1 / 4 + s4) * 64 + lane];
+      w[4 * s4 + 0] = t[0]; w[4 * s4 + 1] = t[1]; w[4 * s4 + 2] = t[2]; w[4 * s4 + 3] = t[3];
+    }
+#pragma unroll
+    for (int q = 0; q < H / 4; ++q)
+#pragma unroll
+      for (int b = 0; b < NB; ++b) acc2[b] = mfma_f32(w[b * (H / 4) + q], a1[q / 4][q % 4], acc2[b]);
+  }
+  float f = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], softplus(acc2[b][r], k), f);
+  }
+  f += __shfl_xor(f, 16);
+  f += __shfl_xor(f, 32);
+  return f + vec[3 * H];
+}
+
+// bfloat16: A fragments ([frag][lane] x 8 bf16) from the LDS block; every
+// layer input rounded to bfloat16, float32 accumulation, bias and softplus
+template <int H>
+__device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int g,
+                                                 const float (&v)[kPeSlots], SoftplusK k) {
+  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  const uint4* fr = reinterpret_cast<const uint4*>(blk);
+  const float* vec = blk + 64 * 4 * NF;
+  bf16x8 e0, e1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) e0[i] = (__bf16)v[i];
+  e1[0] = (__bf16)v[8];
+  e1[1] = (__bf16)v[9];
+#pragma unroll
+  for (int i = 2; i < 8; ++i) e1[i] = (__bf16)0.0f;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(2 * b) * 64 + lane]), e0, acc[b]);
+    acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(2 * b + 1) * 64 + lane]), e1, acc[b]);
+  }
+  bf16x8 x[H / 32];
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus(acc[2 * c + i / 4][i % 4], k);
+  f32x4 acc2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc2[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc2[b]);
+  float f = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], bf16_round(softplus(acc2[b][r], k)), f);
+  }
+  f += __shfl_xor(f, 16);
+  f += __shfl_xor(f, 32);
+  return f + vec[3 * H];
+}
+
 template <int H, bool BF>
-struct MarchW;
+__device__ __forceinline__ float march_eval(const float* blk, int lane, int g, const float (&v)[kPeSlots],
+                                            SoftplusK k) {
+  if constexpr (BF) return march_eval_bf16<H>(blk, lane, g, v, k);
+  else return march_eval_f32<H>(blk, lane, g, v, k);
+}
+
+// Two 16-point tiles at once: every weight fragment read from LDS feeds two
+// MFMAs, and the two independent chains hide each other's latency.
+template <int H>
+__device__ __forceinline__ void march_eval2_f32(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
+                                                const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
+  constexpr int NB = H / 16, S1 = NB * kPeSlots, S2 = NB * (H / 4), SF = S1 + S2;
+  const f32x4* fr = reinterpret_cast<const f32x4*>(blk);
+  const float* vec = blk + 64 * SF;
+  f32x4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+#pragma unroll
+  for (int s4 = 0; s4 < S1 / 4; ++s4) {
+    const f32x4 t = fr[s4 * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int sl = 4 * s4 + c, b = sl / kPeSlots, q = sl % kPeSlots;
+      acc0[b] = mfma_f32(t[c], v0[q], acc0[b]);
+      acc1[b] = mfma_f32(t[c], v1[q], acc1[b]);
+    }
+  }
+  float a0[NB][4], a1[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a0[b][r] = softplus(acc0[b][r], k);
+      a1[b][r] = softplus(acc1[b][r], k);
+    }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+#pragma unroll
+  for (int s4 = 0; s4 < S2 / 4; ++s4) {
+    const f32x4 t = fr[(S1 / 4 + s4) * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int sl = 4 * s4 + c, b = sl / (H / 4), q = sl % (H / 4);
+      acc0[b] = mfma_f32(t[c], a0[q / 4][q % 4], acc0[b]);
+      acc1[b] = mfma_f32(t[c], a1[q / 4][q % 4], acc1[b]);
+    }
+  }
+  float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s0 = fmaf(w3[r], softplus(acc0[b][r], k), s0);
+      s1 = fmaf(w3[r], softplus(acc1[b][r], k), s1);
+    }
+  }
+  s0 += __shfl_xor(s0, 16);
+  s1 += __shfl_xor(s1, 16);
+  s0 += __shfl_xor(s0, 32);
+  s1 += __shfl_xor(s1, 32);
+  f0 = s0 + vec[3 * H];
+  f1 = s1 + vec[3 * H];
+}
 
 template <int H>
-struct MarchW<H, false> {
-  static constexpr int NB = H / 16, S1 = NB * kPeSlots, SF = S1 + NB * (H / 4);
-  float fr[SF];
-  float b1[NB][4], b2[NB][4], w3[NB][4];
-  float b3;
-
-  __device__ __forceinline__ void load(const float* blk, int lane, int g) {
-    const f32x4* p = reinterpret_cast<const f32x4*>(blk);
+__device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
+                                                 const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
+  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  const uint4* fr = reinterpret_cast<const uint4*>(blk);
+  const float* vec = blk + 64 * 4 * NF;
+  bf16x8 e0[2], e1[2];
 #pragma unroll
-    for (int s4 = 0; s4 < SF / 4; ++s4) {
-      f32x4 v = p[s4 * 64 + lane];
-      fr[4 * s4 + 0] = v[0];
-      fr[4 * s4 + 1] = v[1];
-      fr[4 * s4 + 2] = v[2];
-      fr[4 * s4 + 3] = v[3];
+  for (int i = 0; i < 8; ++i) {
+    e0[0][i] = (__bf16)v0[i];
+    e1[0][i] = (__bf16)v1[i];
+  }
+  e0[1][0] = (__bf16)v0[8];
+  e0[1][1] = (__bf16)v0[9];
+  e1[1][0] = (__bf16)v1[8];
+  e1[1][1] = (__bf16)v1[9];
+#pragma unroll
+  for (int i = 2; i < 8; ++i) e0[1][i] = e1[1][i] = (__bf16)0.0f;
+  f32x4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const bf16x8 w = __builtin_bit_cast(bf16x8, fr[(2 * b + c) * 64 + lane]);
+      acc0[b] = mfma_bf16(w, e0[c], acc0[b]);
+      acc1[b] = mfma_bf16(w, e1[c], acc1[b]);
     }
-    const float* vec = blk + 64 * SF;
+  bf16x8 x0[H / 32], x1[H / 32];
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      x0[c][i] = (__bf16)softplus(acc0[2 * c + i / 4][i % 4], k);
+      x1[c][i] = (__bf16)softplus(acc1[2 * c + i / 4][i % 4], k);
+    }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        b1[b][r] = vec[16 * b + 4 * g + r];
-        b2[b][r] = vec[H + 16 * b + 4 * g + r];
-        w3[b][r] = vec[2 * H + 16 * b + 4 * g + r];
-      }
+      const bf16x8 w = __builtin_bit_cast(bf16x8, fr[(F1 + b * (H / 32) + c) * 64 + lane]);
+      acc0[b] = mfma_bf16(w, x0[c], acc0[b]);
+      acc1[b] = mfma_bf16(w, x1[c], acc1[b]);
     }
-    b3 = vec[3 * H];
+  float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s0 = fmaf(w3[r], bf16_round(softplus(acc0[b][r], k)), s0);
+      s1 = fmaf(w3[r], bf16_round(softplus(acc1[b][r], k)), s1);
+    }
   }
+  s0 += __shfl_xor(s0, 16);
+  s1 += __shfl_xor(s1, 16);
+  s0 += __shfl_xor(s0, 32);
+  s1 += __shfl_xor(s1, 32);
+  f0 = s0 + vec[3 * H];
+  f1 = s1 + vec[3 * H];
+}
 
-  __device__ __forceinline__ float eval(const float (&v)[kPeSlots], SoftplusK k) const {
-    f32x4 acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = f32x4{b1[b][0], b1[b][1], b1[b][2], b1[b][3]};
-#pragma unroll
-    for (int q = 0; q < kPeSlots; ++q) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc[b] = mfma_f32(fr[b * kPeSlots + q], v[q], acc[b]);
-    }
-    float a1[NB][4];
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) a1[b][r] = softplus(acc[b][r], k);
-    f32x4 acc2[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc2[b] = f32x4{b2[b][0], b2[b][1], b2[b][2], b2[b][3]};
-#pragma unroll
-    for (int q = 0; q < H / 4; ++q) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b)
-        acc2[b] = mfma_f32(fr[S1 + b * (H / 4) + q], a1[q / 4][q % 4], acc2[b]);
-    }
-    float f = 0.0f;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) f = fmaf(w3[b][r], softplus(acc2[b][r], k), f);
-    f += __shfl_xor(f, 16);
-    f += __shfl_xor(f, 32);
-    return f + b3;
-  }
-};
-
-template <int H>
-struct MarchW<H, true> {
-  static constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
-  bf16x8 fr[NF];
-  float b1[NB][4], b2[NB][4], w3[NB][4];
-  float b3;
-
-  __device__ __forceinline__ void load(const float* blk, int lane, int g) {
-    const uint4* p = reinterpret_cast<const uint4*>(blk);
-#pragma unroll
-    for (int f = 0; f < NF; ++f) fr[f] = __builtin_bit_cast(bf16x8, p[f * 64 + lane]);
-    const float* vec = blk + 64 * 4 * NF;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        b1[b][r] = vec[16 * b + 4 * g + r];
-        b2[b][r] = vec[H + 16 * b + 4 * g + r];
-        w3[b][r] = vec[2 * H + 16 * b + 4 * g + r];
-      }
-    }
-    b3 = vec[3 * H];
-  }
-
-  __device__ __forceinline__ float eval(const float (&v)[kPeSlots], SoftplusK k) const {
-    bf16x8 e0, e1;
-#pragma unroll
-    for (int i = 0; i < 8; ++i) e0[i] = (__bf16)v[i];
-    e1[0] = (__bf16)v[8];
-    e1[1] = (__bf16)v[9];
-#pragma unroll
-    for (int i = 2; i < 8; ++i) e1[i] = (__bf16)0.0f;
-    f32x4 acc[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = f32x4{b1[b][0], b1[b][1], b1[b][2], b1[b][3]};
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(fr[2 * b + 0], e0, acc[b]);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc[b] = mfma_bf16(fr[2 * b + 1], e1, acc[b]);
-    bf16x8 x[H / 32];
-#pragma unroll
-    for (int c = 0; c < H / 32; ++c)
-#pragma unroll
-      for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus(acc[2 * c + i / 4][i % 4], k);
-    f32x4 acc2[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) acc2[b] = f32x4{b2[b][0], b2[b][1], b2[b][2], b2[b][3]};
-#pragma unroll
-    for (int c = 0; c < H / 32; ++c) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) acc2[b] = mfma_bf16(fr[F1 + b * (H / 32) + c], x[c], acc2[b]);
-    }
-    float f = 0.0f;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) f = fmaf(w3[b][r], bf16_round(softplus(acc2[b][r], k)), f);
-    f += __shfl_xor(f, 16);
-    f += __shfl_xor(f, 32);
-    return f + b3;
-  }
-};
+template <int H, bool BF>
+__device__ __forceinline__ void march_eval2(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
+                                            const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
+  if constexpr (BF) march_eval2_bf16<H>(blk, lane, g, v0, v1, k, f0, f1);
+  else march_eval2_f32<H>(blk, lane, g, v0, v1, k, f0, f1);
+}
 
 // copies one packed per-cell block (words % 4 == 0) into LDS
 __device__ __forceinline__ void stage_block(float* lds, const float* src, uint32_t words) {
@@ -378,160 +586,242 @@ __device__ __forceinline__ float cell_exit(const SceneGeom& sg, const CellBox& c
   return best;
 }
 
-enum : int { kStay = 0, kOutHit = 1, kOutNext = 2, kOutExit = 3, kOutBudget = 4 };
+// in-cell status of a staged ray
+enum : uint32_t { kStay = 0, kOutHit = 1, kOutNext = 2, kOutExit = 3, kOutBudget = 4 };
 
 // ---------------------------------------------------------------------------
-// the march: one workgroup (4 waves) per chunk of a cell's bin
+// the march: one workgroup (4 waves) per chunk of <= kChunk rays of one cell
 // ---------------------------------------------------------------------------
+struct Job {
+  uint32_t cell, start, count, id;
+  bool valid;
+};
+
+__device__ __forceinline__ Job read_job(const volatile uint32_t* s) {
+  return Job{s[0], s[1], s[2], s[3], s[4] != 0u};
+}
+
+// thread 0: next work item, from the batch held in s[5], s[6] or a new batch
+__device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s) {
+  if (s[5] >= s[6]) {
+    uint32_t first, last;
+    if (!grab_batch(a.grab, *a.n_chunks, 2u, first, last)) {
+      s[4] = 0u;
+      return;
+    }
+    s[5] = first;
+    s[6] = last;
+  }
+  const uint32_t j = s[5]++;
+  const uint2 c = a.chunks[j];
+  s[0] = c.x & kCellMask;
+  s[1] = c.y;
+  s[2] = c.x >> kCellBits;
+  s[3] = j;
+  s[4] = 1u;
+}
+
 template <int H, bool BF>
 __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
-  using W = MarchW<H, BF>;
-  extern __shared__ float s_block[];
-  __shared__ uint32_t s_job[4];
-  __shared__ uint32_t s_cursor, s_nhit, s_evals;
-  __shared__ uint32_t s_face[6];
-  const int lane = lane_id(), g = lane >> 4, p = lane & 15;
-  const bool rep = g == 0;  // lanes 0..15 write the results of their point
+  extern __shared__ float s_dyn[];
+  float* s_w = s_dyn;
+  float* s_t = s_dyn + a.block_words;
+  float* s_te = s_t + kChunk;
+  float* s_o = s_te + kChunk;        // [3][kChunk]
+  float* s_d = s_o + 3 * kChunk;     // [3][kChunk]
+  float* s_tf = s_d + 3 * kChunk;
+  float* s_ce = s_tf + kChunk;
+  uint32_t* s_rid = reinterpret_cast<uint32_t*>(s_ce + kChunk);
+  uint32_t* s_pix = s_rid + kChunk;
+  uint32_t* s_st = s_pix + kChunk;   // steps | exit axis << 10 | status << 12
+  uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
+  __shared__ uint32_t s_job[7];   // cell, start, count, id, valid, batch cursor, batch end
+  __shared__ uint32_t s_nact[2];
+  __shared__ uint32_t s_face[7], s_foff[7];
+  __shared__ uint32_t s_nhit, s_evals, s_tiles;
+  const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
   const SceneGeom& sg = a.sg;
   const int N = sg.N;
-  W w;
+  unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
   uint32_t loaded = 0xFFFFFFFFu;
+  if (tid == 0) s_job[5] = s_job[6] = 0u;
   for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t j = atomicAdd(a.chunk_next, 1u);
-      const uint32_t nch = *a.n_chunks;
-      if (j < nch) {
-        const uint2 c = a.chunks[j];
-        s_job[0] = c.x & kCellMask;
-        s_job[1] = c.y;
-        s_job[2] = c.x >> kCellBits;
-        s_job[3] = 1u;
-      } else {
-        s_job[3] = 0u;
-      }
-      s_cursor = 0u;
+    if (tid == 0) {
+      grab_job(a, s_job);
+      s_nact[0] = s_job[2];
+      s_nact[1] = 0u;
       s_nhit = 0u;
       s_evals = 0u;
-      for (int f = 0; f < 6; ++f) s_face[f] = 0u;
+      s_tiles = 0u;
+      for (int f = 0; f < 7; ++f) s_face[f] = 0u;
     }
     __syncthreads();
-    if (!s_job[3]) break;
-    const uint32_t cell = s_job[0], start = s_job[1], count = s_job[2];
+    const Job jb = read_job(s_job);
+    if (!jb.valid) break;
+    const uint32_t cell = jb.cell, start = jb.start, count = jb.count, job = jb.id;
     const uint32_t lc = cell - sg.cell_base;
+    const CellBox cb = cell_box(sg, lc);
     if (cell != loaded) {
-      stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
-      __syncthreads();
-      w.load(s_block, lane, g);
+      stage_block(s_w, a.blocks + (size_t)lc * a.block_words, a.block_words);
       loaded = cell;
     }
-    const CellBox cb = cell_box(sg, lc);
-
-    // per-slot state
-    bool have = false, exhausted = false;
-    RayRec r = {0, 0, 0, 0};
-    float o[3] = {0, 0, 0}, d[3] = {0, 0, 0}, t_far = 0.0f, ce = 0.0f;
-    int eax = 0;
-    uint32_t pix = 0, wave_evals = 0;
-    for (;;) {
-      const uint32_t empty = (uint32_t)(__ballot(!have) & 0xFFFFull);
-      if (empty && !exhausted) {
-        const uint32_t ne = (uint32_t)__popc(empty);
-        uint32_t base = 0;
-        if (lane == 0) base = atomicAdd(&s_cursor, ne);
-        base = __shfl(base, 0);
-        if (base + ne >= count) exhausted = true;
-        if (!have) {
-          const uint32_t idx = base + (uint32_t)__popc(empty & ((1u << p) - 1u));
-          if (idx < count) {
-            r = a.S[start + idx];
-            const RayStatic st = a.rs[r.rid];
-            o[0] = st.ox; o[1] = st.oy; o[2] = st.oz;
-            d[0] = st.dx; d[1] = st.dy; d[2] = st.dz;
-            t_far = st.t_far;
-            pix = st.pix;
-            ce = cell_exit(sg, cb, o, d, &eax);
-            have = true;
-          }
-        }
+    if ((uint32_t)tid < count) {
+      const RayRec r = a.S[start + tid];
+      const RayStatic st = a.rs[r.rid];
+      const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
+      int eax;
+      const float ce = cell_exit(sg, cb, o, d, &eax);
+      s_t[tid] = r.t;
+      s_te[tid] = r.t_entry;
+      for (int k = 0; k < 3; ++k) {
+        s_o[k * kChunk + tid] = o[k];
+        s_d[k * kChunk + tid] = d[k];
       }
-      const uint64_t act = __ballot(have) & 0xFFFFull;
-      if (!act) break;
-      wave_evals += (uint32_t)__popcll(act);
-      float xl[3];
+      s_tf[tid] = st.t_far;
+      s_ce[tid] = ce;
+      s_rid[tid] = r.rid;
+      s_pix[tid] = st.pix;
+      s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10);
+      s_act[tid] = (uint16_t)tid;
+    }
+    __syncthreads();
+
+    // passes over the rays still inside the cell; after max_passes the rest
+    // go on in the next round (same cell), so a few slow rays near the
+    // surface do not hold the workgroup
+    uint32_t nact = count, wave_evals = 0, wave_tiles = 0;
+    int cur = 0;
+    for (int pass = 0; nact && pass < a.max_passes; ++pass) {
+      const uint32_t ntiles = (nact + 15u) >> 4;
+      const uint16_t* act_in = s_act + cur * kChunk;
+      uint16_t* act_out = s_act + (cur ^ 1) * kChunk;
+      // tile pairs: wave w takes tiles 2w, 2w+1, 2w+8, 2w+9, ...
+      for (uint32_t tile = 2u * (uint32_t)wave; tile < ntiles; tile += 8u) {
+        uint32_t ri[2];
+        bool valid[2];
+        float t[2], o[2][3], d[2][3], v[2][kPeSlots];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) xl[k] = have ? fmaf(fmaf(r.t, d[k], o[k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
-      float v[kPeSlots];
-      pe_values(pl, xl[0], xl[1], xl[2], v);
-      const float f = w.eval(v, a.spk);
-
-      int out = kStay;
-      uint32_t next_cell = 0;
-      int face = 0;
-      if (have) {
-        const uint32_t steps = (r.key >> kCellBits) + 1u;
-        if (f < a.eps) {
-          out = kOutHit;
-        } else {
-          const float te = fmaxf(r.t, ce);
-          if (r.t + f < te) {
-            r.t = r.t + f;
-          } else {
-            r.t = te;
-            const int sgn = d[eax] > 0.0f ? 1 : -1;
-            int nidx[3] = {cb.ix, cb.iy, cb.iz};
-            nidx[eax] += sgn;
-            face = 2 * eax + (sgn > 0 ? 1 : 0);
-            if (nidx[eax] < 0 || nidx[eax] >= N || r.t > t_far) {
-              out = kOutExit;
-            } else {
-              out = kOutNext;
-              next_cell = sg.cell_base + (uint32_t)(nidx[0] + N * (nidx[1] + N * nidx[2]));
-            }
+        for (int u = 0; u < 2; ++u) {
+          const uint32_t idx = (tile + (uint32_t)u) * 16u + (uint32_t)p;
+          valid[u] = idx < nact;
+          ri[u] = valid[u] ? act_in[idx] : 0u;
+          t[u] = s_t[ri[u]];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            o[u][k] = s_o[k * kChunk + ri[u]];
+            d[u][k] = s_d[k * kChunk + ri[u]];
           }
-          if ((out == kStay || out == kOutNext) && steps >= (uint32_t)a.max_steps) out = kOutBudget;
+          float xl[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            xl[k] = valid[u] ? fmaf(fmaf(t[u], d[u][k], o[u][k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
+          pe_values(pl, xl[0], xl[1], xl[2], v[u]);
         }
-        r.key = (out == kOutNext ? next_cell : cell) | (steps << kCellBits);
-        if (out == kOutNext) r.t_entry = r.t;
-      }
-      // next round
-      {
-        const bool e = rep && have && out == kOutNext;
-        const uint32_t pos = wave_append(a.n_out, e);
-        if (e) {
-          a.U[pos] = r;
-          atomicAdd(&s_face[face], 1u);
+        float f[2];
+        march_eval2<H, BF>(s_w, lane, g, v[0], v[1], a.spk, f[0], f[1]);
+        ++wave_tiles;
+        bool stay[2] = {false, false};
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          wave_evals += (uint32_t)__popcll(__ballot(valid[u]) & 0xFFFFull);
+          if (valid[u] && g == 0) {
+            const uint32_t r_ = ri[u];
+            const uint32_t stw = s_st[r_];
+            const uint32_t steps = (stw & 1023u) + 1u, eax = (stw >> 10) & 3u;
+            uint32_t status = kStay;
+            float tt = t[u];
+            if (f[u] < a.eps) {
+              status = kOutHit;
+            } else {
+              const float te = fmaxf(tt, s_ce[r_]);
+              if (tt + f[u] < te) {
+                tt = tt + f[u];
+              } else {
+                tt = te;
+                const int sgn = d[u][eax] > 0.0f ? 1 : -1;
+                const int ni = (eax == 0 ? cb.ix : (eax == 1 ? cb.iy : cb.iz)) + sgn;
+                status = (ni < 0 || ni >= N || tt > s_tf[r_]) ? kOutExit : kOutNext;
+              }
+              if ((status == kStay || status == kOutNext) && steps >= (uint32_t)a.max_steps) status = kOutBudget;
+            }
+            s_t[r_] = tt;
+            s_st[r_] = steps | (eax << 10) | (status << 12);
+            stay[u] = status == kStay;
+          }
+        }
+        const uint64_t sm0 = __ballot(stay[0]), sm1 = __ballot(stay[1]);
+        if (sm0 | sm1) {
+          const uint32_t n0 = (uint32_t)__popcll(sm0);
+          uint32_t base = 0;
+          if (lane == 0) base = atomicAdd(&s_nact[cur ^ 1], n0 + (uint32_t)__popcll(sm1));
+          base = __shfl(base, 0);
+          if (stay[0]) act_out[base + (uint32_t)__popcll(sm0 & lanemask_lt())] = (uint16_t)ri[0];
+          if (stay[1]) act_out[base + n0 + (uint32_t)__popcll(sm1 & lanemask_lt())] = (uint16_t)ri[1];
         }
       }
-      // hits (binned by cell for shading)
-      {
-        const bool e = rep && have && out == kOutHit;
-        const uint32_t pos = wave_append(a.n_hits, e);
-        if (e) {
-          a.hits[pos] = r;
-          atomicAdd(&s_nhit, 1u);
-        }
-      }
-      if (rep && have && (out == kOutExit || out == kOutBudget))
-        write_miss(a.out, pix, (int)(r.key >> kCellBits), r.t, r.t_entry, (int32_t)cell,
-                   out == kOutExit ? kExitMiss : kBudgetMiss);
-      if (out != kStay) have = false;
+      __syncthreads();
+      if (tid == 0) s_nact[cur] = 0u;
+      nact = s_nact[cur ^ 1];
+      __syncthreads();
+      cur ^= 1;
     }
-    if (lane == 0) atomicAdd(&s_evals, wave_evals);
-    __syncthreads();
-    if (threadIdx.x < 6) {
-      const uint32_t n = s_face[threadIdx.x];
-      if (n) {
-        const int ax = threadIdx.x >> 1, sgn = (threadIdx.x & 1) ? 1 : -1;
-        int nidx[3] = {cb.ix, cb.iy, cb.iz};
-        nidx[ax] += sgn;
-        atomicAdd(&a.counts_next[sg.cell_base + (uint32_t)(nidx[0] + N * (nidx[1] + N * nidx[2]))], n);
+    if (lane == 0) {
+      atomicAdd(&s_evals, wave_evals);
+      atomicAdd(&s_tiles, wave_tiles);
+    }
+
+    // results: misses written out, hits to the per-ray hit array, rays for
+    // the next round into this chunk's range of U, grouped by exit face
+    // (face 6: still in this cell after max_passes)
+    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0;
+    float t = 0.0f, t_entry = 0.0f;
+    if ((uint32_t)tid < count) {
+      const uint32_t stw = s_st[tid];
+      status = stw >> 12;
+      steps = stw & 1023u;
+      t = s_t[tid];
+      t_entry = s_te[tid];
+      if (status == kOutNext || status == kStay) {
+        const uint32_t eax = (stw >> 10) & 3u;
+        face = status == kStay ? 6u : 2u * eax + (s_d[eax * kChunk + tid] > 0.0f ? 1u : 0u);
+        if (status == kOutNext) t_entry = t;
+        rank = atomicAdd(&s_face[face], 1u);
+      } else if (status == kOutHit) {
+        a.HL[s_rid[tid]] = RayRec{t, s_te[tid], cell | (steps << kCellBits), s_rid[tid]};
+        atomicAdd(&s_nhit, 1u);
+      } else {
+        write_miss(a.out, s_pix[tid], (int)steps, t, s_te[tid], (int32_t)cell,
+                   status == kOutExit ? kExitMiss : kBudgetMiss);
       }
-    } else if (threadIdx.x == 6) {
+    }
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t off = 0;
+      for (int f = 0; f < 7; ++f) {
+        s_foff[f] = off;
+        off += s_face[f];
+      }
+      a.chunk_out[2 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
+      a.chunk_out[2 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
       if (s_nhit) atomicAdd(&a.hit_count[cell], s_nhit);
-      atomicAdd(a.evals, (unsigned long long)s_evals);
+      wg_evals += s_evals;
+      wg_tiles += s_tiles;
+      ++wg_chunks;
+    } else if (tid <= 7) {
+      const uint32_t n = s_face[tid - 1];
+      if (n) atomicAdd(&a.counts_next[neighbor_cell(sg, cell, tid - 1)], n);
     }
     __syncthreads();
+    if ((uint32_t)tid < count && (status == kOutNext || status == kStay))
+      a.U[start + s_foff[face] + rank] =
+          RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
+    __syncthreads();
+  }
+  if (tid == 0 && wg_chunks) {
+    atomicAdd(&a.evals[0], wg_evals);
+    atomicAdd(&a.evals[1], wg_tiles);
+    atomicAdd(&a.evals[2], wg_chunks);
   }
 }
 
@@ -610,7 +900,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   extern __shared__ float s_mem[];
   float* s_block = s_mem;
   float* s_stage = s_mem + a.block_words;  // 4 waves x 4 hits x 48
-  __shared__ uint32_t s_job[4];
+  __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
   const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
   const int wave = threadIdx.x >> 6;
   const bool value_col = s == 0;
@@ -618,22 +908,11 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   const SceneGeom& sg = a.sg;
   const float* vec = nullptr;
   uint32_t loaded = 0xFFFFFFFFu;
+  if (threadIdx.x == 0) s_job[4] = s_job[5] = 0u;
   constexpr int NB = H / 16;
   constexpr int SC1 = NB * kPeSlots + NB * (H / 4) + H / 4;  // first color fragment slot
   for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t j = atomicAdd(a.chunk_next, 1u);
-      const uint32_t nch = *a.n_chunks;
-      if (j < nch) {
-        const uint2 c = a.chunks[j];
-        s_job[0] = c.x & kCellMask;
-        s_job[1] = c.y;
-        s_job[2] = c.x >> kCellBits;
-        s_job[3] = 1u;
-      } else {
-        s_job[3] = 0u;
-      }
-    }
+    if (threadIdx.x == 0) next_item(a.grab, *a.n_chunks, a.chunks, s_job);
     __syncthreads();
     if (!s_job[3]) break;
     const uint32_t cell = s_job[0], start = s_job[1], count = s_job[2];
@@ -657,7 +936,11 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
       float t = r.t;
       float xl[3], gr[3], fval = 0.0f;
       f32x4 y;
+#pragma unroll 1
       for (int it = 0; it < 3; ++it) {
+        // weights stay in LDS: reload fragments each evaluation instead of
+        // keeping ~150 of them live in registers across the Newton steps
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(fmaf(t, d[k], o[k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
         float v[kPeSlots];
@@ -752,27 +1035,15 @@ __global__ __launch_bounds__(256) void k_query_bin(QueryBinArgs a) {
 
 template <int H, bool BF>
 __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
-  using W = MarchW<H, BF>;
   extern __shared__ float s_block[];
-  __shared__ uint32_t s_job[4];
+  __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
   const int lane = lane_id(), g = lane >> 4, p = lane & 15, wave = threadIdx.x >> 6;
   const PeLane pl = make_pe_lane(g);
   const SceneGeom& sg = a.sg;
-  W w;
   uint32_t loaded = 0xFFFFFFFFu;
+  if (threadIdx.x == 0) s_job[4] = s_job[5] = 0u;
   for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t j = atomicAdd(a.chunk_next, 1u);
-      if (j < *a.n_chunks) {
-        const uint2 c = a.chunks[j];
-        s_job[0] = c.x & kCellMask;
-        s_job[1] = c.y;
-        s_job[2] = c.x >> kCellBits;
-        s_job[3] = 1u;
-      } else {
-        s_job[3] = 0u;
-      }
-    }
+    if (threadIdx.x == 0) next_item(a.grab, *a.n_chunks, a.chunks, s_job);
     __syncthreads();
     if (!s_job[3]) break;
     const uint32_t cell = s_job[0], start = s_job[1], count = s_job[2];
@@ -780,7 +1051,6 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
     if (cell != loaded) {
       stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
       __syncthreads();
-      w.load(s_block, lane, g);
       loaded = cell;
     }
     const CellBox cb = cell_box(sg, lc);
@@ -793,7 +1063,7 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
       for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(a.pts[3 * (size_t)pi + k], sg.inv_half[k], cb.cs[k]) : 0.0f;
       float v[kPeSlots];
       pe_values(pl, xl[0], xl[1], xl[2], v);
-      const float f = w.eval(v, a.spk);
+      const float f = march_eval<H, BF>(s_block, lane, g, v, a.spk);
       if (valid && g == 0) a.d_out[pi] = f;
     }
     __syncthreads();
@@ -803,25 +1073,15 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
 template <int H>
 __global__ __launch_bounds__(256) void k_query_full(QueryArgs a) {
   extern __shared__ float s_block[];
-  __shared__ uint32_t s_job[4];
+  __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
   const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
   const int wave = threadIdx.x >> 6;
   const PeLane pl = make_pe_lane(g);
   const SceneGeom& sg = a.sg;
   uint32_t loaded = 0xFFFFFFFFu;
+  if (threadIdx.x == 0) s_job[4] = s_job[5] = 0u;
   for (;;) {
-    if (threadIdx.x == 0) {
-      const uint32_t j = atomicAdd(a.chunk_next, 1u);
-      if (j < *a.n_chunks) {
-        const uint2 c = a.chunks[j];
-        s_job[0] = c.x & kCellMask;
-        s_job[1] = c.y;
-        s_job[2] = c.x >> kCellBits;
-        s_job[3] = 1u;
-      } else {
-        s_job[3] = 0u;
-      }
-    }
+    if (threadIdx.x == 0) next_item(a.grab, *a.n_chunks, a.chunks, s_job);
     __syncthreads();
     if (!s_job[3]) break;
     const uint32_t cell = s_job[0], start = s_job[1], count = s_job[2];
@@ -877,9 +1137,18 @@ hipError_t launch_scatter(const ScatterArgs& a, uint32_t grid, hipStream_t st) {
   return hipGetLastError();
 }
 
+hipError_t launch_scatter_chunks(const ScatterChunksArgs& a, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_chunks, dim3(grid), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+size_t march_lds_bytes(uint32_t block_words) {
+  return (size_t)block_words * 4u + (size_t)kChunk * (13u * 4u + 2u * 2u);  // 13 words + 2 list slots per ray
+}
+
 template <int H, bool BF>
 static hipError_t march_t(const MarchArgs& a, uint32_t grid, hipStream_t st) {
-  const size_t lds = (size_t)a.block_words * 4u;
+  const size_t lds = march_lds_bytes(a.block_words);
   hipLaunchKernelGGL((k_march<H, BF>), dim3(grid), dim3(256), lds, st, a);
   return hipGetLastError();
 }

@@ -203,7 +203,8 @@ struct Workspace {
   uint32_t* counts = nullptr;      // [2][cells]
   uint32_t* hit_count = nullptr;   // [cells]
   uint32_t* cursor = nullptr;      // [cells]
-  uint2* chunk = nullptr;          // [chunks]
+  uint2* chunk = nullptr;          // [2][chunks]
+  uint4* chunk_out = nullptr;      // [2][chunks][2]
   Ctrl* ctrl = nullptr;
   size_t bytes = 0;
 };
@@ -223,6 +224,8 @@ struct kn_ctx {
   uint32_t* pinned = nullptr;  // round counters read back by the host
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   hipEvent_t ev_round[4] = {nullptr, nullptr, nullptr, nullptr};
+  int max_passes = 4;          // in-cell passes of a march chunk per round
+  std::vector<hipEvent_t> ev_kernel;  // pairs around timed kernel launches
   std::unique_ptr<kn::ServeLoop> serve;
 };
 
@@ -244,20 +247,22 @@ kn_status check_ctx(kn_ctx* ctx) {
 }
 
 void free_ws(Workspace& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.HL, w.counts, w.hit_count, w.cursor, w.chunk, w.ctrl};
+  void* ptrs[] = {w.rs, w.U, w.S, w.HL, w.counts, w.hit_count, w.cursor, w.chunk, w.chunk_out, w.ctrl};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   w = Workspace{};
 }
 
-// grow-only workspace for `rays` records over `cells` cells
+// grow-only workspace for `rays` records over `cells` cells; work chunks of
+// at least `min_chunk` records
 kn_status ensure_ws(kn_ctx* ctx, size_t rays, size_t cells, uint32_t min_chunk) {
   Workspace& w = ctx->ws;
   const size_t chunks = rays / min_chunk + cells + 2;
   if (w.rays >= rays && w.cells >= cells && w.chunks >= chunks && w.ctrl) return KN_OK;
   const size_t R = std::max(w.rays, rays), C = std::max(w.cells, cells),
                K = std::max(w.chunks, chunks);
-  const size_t bytes = R * (sizeof(RayStatic) + 3 * sizeof(RayRec)) + C * 4 * 4 + K * 8 + sizeof(Ctrl);
+  const size_t bytes = R * (sizeof(RayStatic) + 3 * sizeof(RayRec)) + C * 4 * 4 + K * 2 * (8 + 32) +
+                       sizeof(Ctrl);
   const uint64_t other = ctx->used.load() - w.bytes;
   if (other + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "ray workspace of %zu bytes exceeds the HBM budget", bytes);
@@ -275,7 +280,8 @@ kn_status ensure_ws(kn_ctx* ctx, size_t rays, size_t cells, uint32_t min_chunk) 
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * 4));
   KN_HIP(ctx, hipMalloc(&n.cursor, C * 4));
-  KN_HIP(ctx, hipMalloc(&n.chunk, K * 8));
+  KN_HIP(ctx, hipMalloc(&n.chunk, 2 * K * 8));
+  KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 32));
   KN_HIP(ctx, hipMalloc(&n.ctrl, sizeof(Ctrl)));
   w = n;
   ctx->used += bytes;
@@ -336,6 +342,7 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
   if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
   for (auto& e : ctx->ev_round)
     if (e) (void)hipEventDestroy(e);
+  for (auto& e : ctx->ev_kernel) (void)hipEventDestroy(e);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return KN_OK;
@@ -540,10 +547,18 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   const bool bf = c->precision == KN_BF16;
   const SoftplusK spk = softplus_consts(s->geom.beta);
 
+  const bool timed = stats && stats->kernel_times;
+  const size_t need_ev = 2 * ((size_t)c->max_steps + 3);
+  while (timed && ctx->ev_kernel.size() < need_ev) {
+    hipEvent_t e;
+    KN_HIP(ctx, hipEventCreate(&e));
+    ctx->ev_kernel.push_back(e);
+  }
   KN_HIP(ctx, hipEventRecord(ctx->ev_start, stream));
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
   KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * cells * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, cells * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
 
   RaygenArgs rg{};
   rg.sg = s->geom;
@@ -553,58 +568,81 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   rg.rs = w.rs;
   rg.U = w.U;
   rg.counts = w.counts;
-  rg.ctrl = w.ctrl;
   rg.out = out;
   KN_HIP(ctx, launch_raygen(rg, stream));
 
   const uint32_t scatter_grid = (uint32_t)std::min<size_t>((rays + 255) / 256, 4096);
-  const uint32_t march_grid = persistent_grid(ctx, 2);
-  const int max_rounds = std::min<int>((int)c->max_steps, 3 * s->N) + 2;
+  const uint32_t march_grid = persistent_grid(ctx, 4);
+  // every round takes at least one SDF evaluation of every live ray
+  const int max_rounds = (int)c->max_steps + 2;
   int rounds = 0;
   for (int r = 0; r < max_rounds; ++r) {
     const int par = r & 1;
+    uint2* chunks = w.chunk + (size_t)par * w.chunks;
+    uint4* chunk_out = w.chunk_out + (size_t)par * w.chunks * 2;
     ScanArgs sa{};
     sa.counts = w.counts + par * cells;
     sa.C = (uint32_t)cells;
-    sa.T = kMarchChunk;
+    sa.T = kChunk;
     sa.zero_counts = 1;
     sa.cursor = w.cursor;
-    sa.chunks = w.chunk;
-    sa.n_chunks = &w.ctrl->n_chunks;
-    sa.chunk_next = &w.ctrl->chunk_next;
-    sa.zero_word = &w.ctrl->n_list[par ^ 1];
+    sa.chunks = chunks;
+    sa.n_chunks = &w.ctrl->n_chunks[par];
+    sa.grab = w.ctrl->grab;
+    sa.grab0 = w.ctrl->grab0;
+    sa.zero_word = nullptr;
     KN_HIP(ctx, launch_scan(sa, stream));
-    ScatterArgs sc{w.U, w.S, &w.ctrl->n_list[par], w.cursor};
-    KN_HIP(ctx, launch_scatter(sc, scatter_grid, stream));
+    if (r == 0) {
+      ScatterArgs sc{w.U, w.S, (uint32_t)rays, w.cursor};
+      KN_HIP(ctx, launch_scatter(sc, scatter_grid, stream));
+    } else {
+      ScatterChunksArgs sc{s->geom,
+                           w.chunk + (size_t)(par ^ 1) * w.chunks,
+                           w.chunk_out + (size_t)(par ^ 1) * w.chunks * 2,
+                           &w.ctrl->n_chunks[par ^ 1],
+                           w.U,
+                           w.S,
+                           w.cursor};
+      KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 4), stream));
+    }
     MarchArgs ma{};
     ma.sg = s->geom;
     ma.blocks = bf ? s->march_bf16 : s->march_f32;
     ma.block_words = bf ? s->march_bf16_words : s->march_f32_words;
     ma.S = w.S;
     ma.rs = w.rs;
-    ma.chunks = w.chunk;
-    ma.n_chunks = &w.ctrl->n_chunks;
-    ma.chunk_next = &w.ctrl->chunk_next;
+    ma.chunks = chunks;
+    ma.n_chunks = &w.ctrl->n_chunks[par];
+    ma.grab = w.ctrl->grab;
+    ma.chunk_out = chunk_out;
     ma.U = w.U;
-    ma.n_out = &w.ctrl->n_list[par ^ 1];
     ma.counts_next = w.counts + (par ^ 1) * cells;
-    ma.hits = w.HL;
-    ma.n_hits = &w.ctrl->n_hits;
+    ma.HL = w.HL;
     ma.hit_count = w.hit_count;
     ma.evals = &w.ctrl->evals;
     ma.max_steps = (int)c->max_steps;
+    ma.max_passes = ctx->max_passes;
     ma.eps = c->eps;
     ma.spk = spk;
     ma.out = out;
+    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[2 * r], stream));
     KN_HIP(ctx, launch_march(ma, s->H, bf ? 1 : 0, march_grid, stream));
+    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[2 * r + 1], stream));
     ++rounds;
-    // read back how many rays go on to the next round; stop two rounds later
-    KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[r & 3], &w.ctrl->n_list[par ^ 1], 4, hipMemcpyDeviceToHost,
-                               stream));
-    KN_HIP(ctx, hipEventRecord(ctx->ev_round[r & 3], stream));
-    if (r >= 2) {
-      KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[(r - 2) & 3]));
-      if (ctx->pinned[(r - 2) & 3] == 0) break;
+    // every kReadback rounds, read back how many chunks the round had; stop
+    // once an earlier readback shows an empty round (rounds enqueued after
+    // it find no work and return at once)
+    constexpr int kReadback = 4;
+    if (r % kReadback == kReadback - 1) {
+      const int slot = (r / kReadback) & 3;
+      KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[slot], &w.ctrl->n_chunks[par], 4, hipMemcpyDeviceToHost,
+                                 stream));
+      KN_HIP(ctx, hipEventRecord(ctx->ev_round[slot], stream));
+      if (r >= 2 * kReadback - 1) {
+        const int prev = ((r / kReadback) - 1) & 3;
+        KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[prev]));
+        if (ctx->pinned[prev] == 0) break;
+      }
     }
   }
 
@@ -617,11 +655,13 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     sa.zero_counts = 0;
     sa.cursor = w.cursor;
     sa.chunks = w.chunk;
-    sa.n_chunks = &w.ctrl->n_chunks;
-    sa.chunk_next = &w.ctrl->chunk_next;
+    sa.n_chunks = &w.ctrl->n_chunks[2];
+    sa.grab = w.ctrl->grab;
+    sa.grab0 = w.ctrl->grab0;
     sa.zero_word = nullptr;
+    sa.total = &w.ctrl->n_hits;
     KN_HIP(ctx, launch_scan(sa, stream));
-    ScatterArgs sc{w.HL, w.S, &w.ctrl->n_hits, w.cursor};
+    ScatterArgs sc{w.HL, w.S, (uint32_t)rays, w.cursor};
     KN_HIP(ctx, launch_scatter(sc, scatter_grid, stream));
     ShadeArgs sh{};
     sh.sg = s->geom;
@@ -630,11 +670,13 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     sh.S = w.S;
     sh.rs = w.rs;
     sh.chunks = w.chunk;
-    sh.n_chunks = &w.ctrl->n_chunks;
-    sh.chunk_next = &w.ctrl->chunk_next;
+    sh.n_chunks = &w.ctrl->n_chunks[2];
+    sh.grab = w.ctrl->grab;
     sh.spk = spk;
     sh.out = out;
+    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[need_ev - 2], stream));
     KN_HIP(ctx, launch_shade(sh, s->H, persistent_grid(ctx, 2), stream));
+    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[need_ev - 1], stream));
   }
   KN_HIP(ctx, hipEventRecord(ctx->ev_end, stream));
   KN_HIP(ctx, hipEventSynchronize(ctx->ev_end));
@@ -648,8 +690,23 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     stats->rays = rays;
     stats->evals = hc.evals;
+    stats->march_tiles = hc.tiles;
+    stats->march_chunks = hc.chunks;
     stats->hits = hc.n_hits;
     stats->rounds = (uint64_t)rounds;
+    stats->march_launches = 0;
+    stats->march_ms = stats->shade_ms = 0.0;
+    if (timed) {
+      for (int r = 0; r < rounds; ++r) {
+        float kms = 0.0f;
+        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[2 * r], ctx->ev_kernel[2 * r + 1]));
+        stats->march_ms += kms;
+      }
+      stats->march_launches = (uint32_t)rounds;
+      float kms = 0.0f;
+      KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[need_ev - 2], ctx->ev_kernel[need_ev - 1]));
+      stats->shade_ms = kms;
+    }
   }
   return KN_OK;
 }
@@ -699,8 +756,6 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   const SoftplusK spk = softplus_consts(s->geom.beta);
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
   KN_HIP(ctx, hipMemsetAsync(w.counts, 0, cells * 4, stream));
-  ctx->pinned[16] = (uint32_t)n;
-  KN_HIP(ctx, hipMemcpyAsync(&w.ctrl->n_list[0], &ctx->pinned[16], 4, hipMemcpyHostToDevice, stream));
   QueryBinArgs qb{s->geom, points, n, w.U, w.counts};
   KN_HIP(ctx, launch_query_bin(qb, stream));
   ScanArgs sa{};
@@ -710,19 +765,20 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.zero_counts = 0;
   sa.cursor = w.cursor;
   sa.chunks = w.chunk;
-  sa.n_chunks = &w.ctrl->n_chunks;
-  sa.chunk_next = &w.ctrl->chunk_next;
+  sa.n_chunks = &w.ctrl->n_chunks[0];
+  sa.grab = w.ctrl->grab;
+    sa.grab0 = w.ctrl->grab0;
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
-  ScatterArgs sc{w.U, w.S, &w.ctrl->n_list[0], w.cursor};
+  ScatterArgs sc{w.U, w.S, (uint32_t)n, w.cursor};
   KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), stream));
   QueryArgs qa{};
   qa.sg = s->geom;
   qa.S = w.S;
   qa.pts = points;
   qa.chunks = w.chunk;
-  qa.n_chunks = &w.ctrl->n_chunks;
-  qa.chunk_next = &w.ctrl->chunk_next;
+  qa.n_chunks = &w.ctrl->n_chunks[0];
+  qa.grab = w.ctrl->grab;
   qa.spk = spk;
   if (d_out) {
     const bool bf = precision == KN_BF16;
@@ -732,7 +788,8 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
     KN_HIP(ctx, launch_query_d(qa, s->H, bf ? 1 : 0, persistent_grid(ctx, 2), stream));
   }
   if (grad_out || z_out) {
-    KN_HIP(ctx, hipMemsetAsync(&w.ctrl->chunk_next, 0, 4, stream));
+    KN_HIP(ctx, hipMemcpyAsync(w.ctrl->grab, w.ctrl->grab0, sizeof(w.ctrl->grab), hipMemcpyDeviceToDevice,
+                               stream));
     qa.blocks = s->shade;
     qa.block_words = s->shade_words;
     qa.d_out = nullptr;

@@ -56,7 +56,10 @@ class Frame(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("gpu_ms", C.c_double), ("wall_ms", C.c_double), ("rays", C.c_uint64),
-                ("evals", C.c_uint64), ("hits", C.c_uint64), ("rounds", C.c_uint64)]
+                ("evals", C.c_uint64), ("hits", C.c_uint64), ("rounds", C.c_uint64),
+                ("kernel_times", C.c_uint32), ("march_launches", C.c_uint32),
+                ("march_ms", C.c_double), ("shade_ms", C.c_double),
+                ("march_tiles", C.c_uint64), ("march_chunks", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -175,7 +178,8 @@ class Context:
             f["trace"] = torch.empty((height, width, 4), dtype=torch.int32, device=dev)
         return f
 
-    def render_into(self, sid: int, cam: Camera, out: dict, stream=None) -> dict:
+    def render_into(self, sid: int, cam: Camera, out: dict, stream=None,
+                    kernel_times: bool = False) -> dict:
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
@@ -183,6 +187,7 @@ class Context:
                    _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
                    C.c_void_p(stream.cuda_stream))
         st = Stats()
+        st.kernel_times = 1 if kernel_times else 0
         check(lib().kn_render(self.h, sid, C.byref(cam), C.byref(fr), C.byref(st)))
         return st.as_dict()
 
