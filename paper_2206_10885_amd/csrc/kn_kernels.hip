@@ -601,18 +601,19 @@ __device__ __forceinline__ Job read_job(const volatile uint32_t* s) {
   return Job{s[0], s[1], s[2], s[3], s[4] != 0u};
 }
 
-// thread 0: next work item, from the batch held in s[5], s[6] or a new batch
-__device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s) {
-  if (s[5] >= s[6]) {
+// thread 0: next work item into s[0..4], from the batch [bat[0], bat[1]) or
+// a new batch
+__device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s, uint32_t* bat) {
+  if (bat[0] >= bat[1]) {
     uint32_t first, last;
     if (!grab_batch(a.grab, *a.n_chunks, 2u, first, last)) {
       s[4] = 0u;
       return;
     }
-    s[5] = first;
-    s[6] = last;
+    bat[0] = first;
+    bat[1] = last;
   }
-  const uint32_t j = s[5]++;
+  const uint32_t j = bat[0]++;
   const uint2 c = a.chunks[j];
   s[0] = c.x & kCellMask;
   s[1] = c.y;
@@ -635,8 +636,9 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   uint32_t* s_pix = s_rid + kChunk;
   uint32_t* s_st = s_pix + kChunk;   // steps | exit axis << 10 | status << 12
   uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
-  __shared__ uint32_t s_job[7];   // cell, start, count, id, valid, batch cursor, batch end
-  __shared__ uint32_t s_nact[2];
+  __shared__ uint32_t s_job[5], s_jn[5];   // current / next work item: cell, start, count, id, valid
+  __shared__ uint32_t s_bat[2];            // thread 0's batch of work items
+  __shared__ uint32_t s_nact[2], s_pair;
   __shared__ uint32_t s_face[7], s_foff[7];
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
@@ -645,15 +647,24 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   const int N = sg.N;
   unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
   uint32_t loaded = 0xFFFFFFFFu;
-  if (tid == 0) s_job[5] = s_job[6] = 0u;
+  // this chunk's ray record and static data, loaded ahead during the
+  // previous chunk when possible
+  RayRec pf_rec = {0, 0, 0, 0};
+  RayStatic pf_st = {0, 0, 0, 0, 0, 0, 1, 0};
+  bool pf_rec_ok = false, pf_st_ok = false;
+  if (tid == 0) {
+    s_bat[0] = s_bat[1] = 0u;
+    grab_job(a, s_job, s_bat);
+  }
   for (;;) {
     if (tid == 0) {
-      grab_job(a, s_job);
       s_nact[0] = s_job[2];
       s_nact[1] = 0u;
+      s_pair = 0u;
       s_nhit = 0u;
       s_evals = 0u;
       s_tiles = 0u;
+      s_jn[4] = 0u;
       for (int f = 0; f < 7; ++f) s_face[f] = 0u;
     }
     __syncthreads();
@@ -667,8 +678,8 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       loaded = cell;
     }
     if ((uint32_t)tid < count) {
-      const RayRec r = a.S[start + tid];
-      const RayStatic st = a.rs[r.rid];
+      const RayRec r = pf_rec_ok ? pf_rec : a.S[start + tid];
+      const RayStatic st = pf_st_ok ? pf_st : a.rs[r.rid];
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
       int eax;
       const float ce = cell_exit(sg, cb, o, d, &eax);
@@ -685,7 +696,11 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10);
       s_act[tid] = (uint16_t)tid;
     }
+    pf_rec_ok = pf_st_ok = false;
     __syncthreads();
+    // thread 0 takes the next work item now; its wave catches up because
+    // the tile pairs of a pass are handed out dynamically
+    if (tid == 0) grab_job(a, s_jn, s_bat);
 
     // passes over the rays still inside the cell; after max_passes the rest
     // go on in the next round (same cell), so a few slow rays near the
@@ -696,8 +711,12 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       const uint32_t ntiles = (nact + 15u) >> 4;
       const uint16_t* act_in = s_act + cur * kChunk;
       uint16_t* act_out = s_act + (cur ^ 1) * kChunk;
-      // tile pairs: wave w takes tiles 2w, 2w+1, 2w+8, 2w+9, ...
-      for (uint32_t tile = 2u * (uint32_t)wave; tile < ntiles; tile += 8u) {
+      // tile pairs handed out through an LDS counter
+      for (;;) {
+        uint32_t tile = 0;
+        if (lane == 0) tile = atomicAdd(&s_pair, 2u);
+        tile = __shfl(tile, 0);
+        if (tile >= ntiles) break;
         uint32_t ri[2];
         bool valid[2];
         float t[2], o[2][3], d[2][3], v[2][kPeSlots];
@@ -761,8 +780,23 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         }
       }
       __syncthreads();
-      if (tid == 0) s_nact[cur] = 0u;
+      if (tid == 0) {
+        s_nact[cur] = 0u;
+        s_pair = 0u;
+      }
       nact = s_nact[cur ^ 1];
+      // the next work item is known after the first barrier: start loading
+      // its rays (the static data one pass later, once the record is in)
+      if (pass == 0) {
+        const Job nx = read_job(s_jn);
+        if (nx.valid && (uint32_t)tid < nx.count) {
+          pf_rec = a.S[nx.start + tid];
+          pf_rec_ok = true;
+        }
+      } else if (pass == 1 && pf_rec_ok) {
+        pf_st = a.rs[pf_rec.rid];
+        pf_st_ok = true;
+      }
       __syncthreads();
       cur ^= 1;
     }
@@ -816,6 +850,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
     if ((uint32_t)tid < count && (status == kOutNext || status == kStay))
       a.U[start + s_foff[face] + rank] =
           RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
+    if (tid < 5) s_job[tid] = s_jn[tid];
     __syncthreads();
   }
   if (tid == 0 && wg_chunks) {
