@@ -30,6 +30,28 @@ METRIC = "shaded rays/sec at 1920×1080 (BF16/FP8 vs FP32) + p50/p99 frame laten
 # lanes/clock per CU: 256 CU x 32 /clock x 2.4 GHz = 19.7 T/s.
 PEAK_FP32_MFMA = 157.3e12
 PEAK_TRANS = 256 * 32 * 2.4e9
+PEAK_HBM = 8.0e12
+
+# HBM bytes per launch of the bfloat16 march kernel on this workload, from
+# two hardware-counter runs (FETCH_SIZE, then WRITE_SIZE, averaged over the
+# launches of 10 frames), each scaled by what the same counter reads for a
+# 1 GiB device copy in the same run (fetch x2.0, write x1.0); summary and
+# commands in profiles/k_march_bf16_c3_1080p.md.  Valid only for the kernel
+# sources they were taken on: any change to them makes the figure null.
+MARCH_TRAFFIC = dict(sources_sha256="30881306b50f13ee9a26c91ff26c16d0d385729afcbd146c84f116adc2aa8543",
+                     bytes_per_launch=65124979.6, fetch_kib=24152.56, write_kib=15295.22,
+                     fetch_factor=2.0, write_factor=1.0)
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    root = os.path.join(ROOT, "paper_2206_10885_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(root)):
+        h.update(f.encode())
+        with open(os.path.join(root, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def march_work(H: int) -> dict:
@@ -50,6 +72,9 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle time")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after timing, run one plain float32 device copy of this many MiB "
+                         "(a kernel of known HBM traffic, used to scale hardware byte counters)")
     return ap.parse_args()
 
 
@@ -134,8 +159,14 @@ def main():
     evals_per_launch = r["evals"] / max(1, r["march_launches"])
     if args.precision == "bf16":
         achieved = evals_per_launch * work["trans"] / avg_launch_s
+        traffic = None
+        if kernel_sources_sha256() == MARCH_TRAFFIC["sources_sha256"]:
+            traffic = MARCH_TRAFFIC["bytes_per_launch"]
         roofline = dict(bound="alu", achieved=achieved / 1e12, peak=PEAK_TRANS / 1e12,
-                        unit="Tops/s transcendental", frac=achieved / PEAK_TRANS, traffic=None,
+                        unit="Tops/s transcendental", frac=achieved / PEAK_TRANS, traffic=traffic,
+                        traffic_unit="bytes per launch",
+                        traffic_frac_of_hbm=(None if traffic is None else
+                                             traffic / avg_launch_s / PEAK_HBM),
                         kernel="k_march<64,bf16>", avg_launch_ms=avg_launch_s * 1e3,
                         evals_per_launch=evals_per_launch)
     else:
@@ -182,6 +213,14 @@ def main():
             r32["march_ms"] / 1e3 / max(1, r32["march_launches"]))
         line["fp32_march_roofline"] = dict(bound="mfma", achieved=a32 / 1e12, peak=PEAK_FP32_MFMA / 1e12,
                                            unit="TFLOP/s", frac=a32 / PEAK_FP32_MFMA)
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, views, W, H, S, eps, args.cpu_seconds)
     print(json.dumps(line), flush=True)
