@@ -418,3 +418,174 @@ void kno_render(const kno_scene* s, const kno_camera* c, const int64_t* pixels, 
     if (fmin) fmin[q] = r.fmin;
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Path tracing (Sec. 3.4.1: the renderer is a path tracer; surfaces are
+ * Lambertian, with the color MLP output as albedo).  Readings: cosine-
+ * weighted scattering about the normal, throughput times albedo at each
+ * scatter, at most `bounces` scatters, an escaping ray adds throughput times
+ * the environment, a hit after the last scatter adds nothing; the pixel is
+ * the mean of its samples.
+ * ------------------------------------------------------------------------ */
+
+/* Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds; each round multiplies counter
+ * words 0 and 2 by the two round constants, keeps the low halves, and xors
+ * the high halves with the other two words and the key; the key advances by
+ * the two Weyl constants between rounds. */
+void kno_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+  const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+  uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3], k0 = key[0], k1 = key[1];
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+/* uniform in [0, 1) from the top 24 bits */
+static double u01(uint32_t x) { return (double)(x >> 8) * (1.0 / 16777216.0); }
+
+/* two uniforms of path (pixel, sample) at event k: Philox keyed by the seed,
+ * counter (pixel, sample, k, 0); k = 0 is the pixel jitter, k >= 1 the k-th
+ * scatter */
+static void path_uniforms(uint64_t seed, int64_t pixel, int sample, int k, double* a, double* b) {
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  const uint32_t ctr[4] = {(uint32_t)pixel, (uint32_t)sample, (uint32_t)k, 0u};
+  uint32_t x[4];
+  kno_philox4x32_10(ctr, key, x);
+  *a = u01(x[0]);
+  *b = u01(x[1]);
+}
+
+/* orthonormal basis (b1, b2, n) of a unit normal (Duff, Burgess, Christensen,
+ * Hery, Kensler, Liani, Villemin, "Building an Orthonormal Basis,
+ * Revisited", JCGT 2017) */
+void kno_onb(const double n[3], double b1[3], double b2[3]) {
+  const double sign = n[2] >= 0.0 ? 1.0 : -1.0;
+  const double a = -1.0 / (sign + n[2]);
+  const double b = n[0] * n[1] * a;
+  b1[0] = 1.0 + sign * n[0] * n[0] * a;
+  b1[1] = sign * b;
+  b1[2] = -sign * n[0];
+  b2[0] = b;
+  b2[1] = sign + n[1] * n[1] * a;
+  b2[2] = -n[1];
+}
+
+/* cosine-weighted direction about n from (u1, u2) in [0,1)^2: local
+ * (sqrt(u1) cos 2 pi u2, sqrt(u1) sin 2 pi u2, sqrt(1 - u1)) */
+void kno_cosine_dir(const double n[3], double u1, double u2, double out[3]) {
+  double b1[3], b2[3];
+  kno_onb(n, b1, b2);
+  const double r = sqrt(u1), phi = 2.0 * PI * u2;
+  const double lx = r * cos(phi), ly = r * sin(phi), lz = sqrt(1.0 - u1);
+  for (int a = 0; a < 3; ++a) out[a] = lx * b1[a] + ly * b2[a] + lz * n[a];
+}
+
+/* equirectangular environment: u = 1/2 + atan2(d_x, -d_z) / 2 pi,
+ * v = acos(d_y) / pi (row 0 looks up +y); bilinear between texel centres,
+ * wrapping in u, clamping in v */
+void kno_env_lookup(const kno_env* e, const double d[3], double rgb[3]) {
+  if (!e->rgb || e->w <= 0 || e->h <= 0) {
+    rgb[0] = rgb[1] = rgb[2] = 0.0;
+    return;
+  }
+  const double dy = d[1] < -1.0 ? -1.0 : (d[1] > 1.0 ? 1.0 : d[1]);
+  const double u = 0.5 + atan2(d[0], -d[2]) / (2.0 * PI);
+  const double v = acos(dy) / PI;
+  const double x = u * e->w - 0.5, y = v * e->h - 0.5;
+  const double fx0 = floor(x), fy0 = floor(y);
+  const double fx = x - fx0, fy = y - fy0;
+  int x0 = (int)fx0 % e->w;
+  if (x0 < 0) x0 += e->w;
+  const int x1 = (x0 + 1) % e->w;
+  int y0 = (int)fy0, y1 = (int)fy0 + 1;
+  y0 = y0 < 0 ? 0 : (y0 > e->h - 1 ? e->h - 1 : y0);
+  y1 = y1 < 0 ? 0 : (y1 > e->h - 1 ? e->h - 1 : y1);
+  for (int c = 0; c < 3; ++c) {
+    const double t00 = e->rgb[((size_t)y0 * e->w + x0) * 3 + c], t01 = e->rgb[((size_t)y0 * e->w + x1) * 3 + c];
+    const double t10 = e->rgb[((size_t)y1 * e->w + x0) * 3 + c], t11 = e->rgb[((size_t)y1 * e->w + x1) * 3 + c];
+    rgb[c] = (1.0 - fy) * ((1.0 - fx) * t00 + fx * t01) + fy * ((1.0 - fx) * t10 + fx * t11);
+  }
+}
+
+/* One path from the camera; returns its radiance.  `first` (may be NULL)
+ * receives the primary segment's trace and shading for the auxiliary
+ * outputs. */
+static void trace_path(const kno_scene* s, const kno_camera* c, const kno_pt* pt, int64_t p, int sample,
+                       double L[3], kno_trace_result* first, double* first_depth, double first_n[3]) {
+  const int row = (int)(p / c->width), colm = (int)(p % c->width);
+  double xi1 = 0.5, xi2 = 0.5;
+  if (pt->spp > 1) path_uniforms(pt->seed, p, sample, 0, &xi1, &xi2);
+  double o[3], d[3];
+  kno_camera_ray(c, row, colm, xi1, xi2, o, d);
+  double T[3] = {1.0, 1.0, 1.0};
+  L[0] = L[1] = L[2] = 0.0;
+  for (int k = 0;; ++k) {
+    kno_trace_result r;
+    kno_trace(s, o, d, c->max_steps, c->eps, &r);
+    if (k == 0 && first) *first = r;
+    if (r.status != KNO_HIT) {
+      double env[3];
+      kno_env_lookup(&pt->env, d, env);
+      for (int a = 0; a < 3; ++a) L[a] += T[a] * env[a];
+      return;
+    }
+    double dep, n[3], rgb[3], z[15];
+    kno_shade(s, o, d, &r, &dep, n, rgb, z);
+    if (k == 0 && first_depth) {
+      *first_depth = dep;
+      for (int a = 0; a < 3; ++a) first_n[a] = n[a];
+    }
+    if (k >= pt->bounces) return;
+    for (int a = 0; a < 3; ++a) T[a] *= rgb[a];
+    double u1, u2, nd[3];
+    path_uniforms(pt->seed, p, sample, k + 1, &u1, &u2);
+    kno_cosine_dir(n, u1, u2, nd);
+    for (int a = 0; a < 3; ++a) {
+      o[a] = o[a] + dep * d[a] + 1e-3 * n[a];
+      d[a] = nd[a];
+    }
+  }
+}
+
+void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
+                    int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t q = 0; q < npix; ++q) {
+    const int64_t p = pixels ? pixels[q] : q;
+    double acc[3] = {0.0, 0.0, 0.0};
+    kno_trace_result first;
+    double dep = 0.0, n[3] = {0.0, 0.0, 0.0};
+    for (int smp = 0; smp < pt->spp; ++smp) {
+      double L[3];
+      trace_path(s, c, pt, p, smp, L, smp == 0 ? &first : NULL, smp == 0 ? &dep : NULL,
+                 smp == 0 ? n : NULL);
+      for (int a = 0; a < 3; ++a) acc[a] += L[a];
+    }
+    const int h = first.status == KNO_HIT;
+    for (int a = 0; a < 3; ++a) {
+      if (rgb) rgb[q * 3 + a] = acc[a] / pt->spp;
+      if (normal) normal[q * 3 + a] = h ? n[a] : 0.0;
+    }
+    if (depth) depth[q] = h ? dep : 0.0;
+    if (hit) hit[q] = (uint8_t)h;
+  }
+}

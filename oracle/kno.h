@@ -86,6 +86,26 @@ void kno_render(const kno_scene* s, const kno_camera* c, const int64_t* pixels, 
                 double* rgb, double* depth, double* normal, uint8_t* hit, int32_t* steps,
                 int32_t* status, double* fmin, int nthreads);
 
+/* path tracing (Sec. 3.4.1) */
+typedef struct {
+  const float* rgb;       /* [h][w][3] equirectangular map, or NULL (black) */
+  int32_t w, h;
+} kno_env;
+
+typedef struct {
+  int32_t spp;            /* samples per pixel (1: through the pixel centre) */
+  int32_t bounces;        /* scatters per path */
+  uint64_t seed;          /* Philox key */
+  kno_env env;
+} kno_pt;
+
+void kno_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+void kno_onb(const double n[3], double b1[3], double b2[3]);
+void kno_cosine_dir(const double n[3], double u1, double u2, double out[3]);
+void kno_env_lookup(const kno_env* e, const double d[3], double rgb[3]);
+void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
+                    int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

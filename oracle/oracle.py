@@ -47,6 +47,14 @@ class _Trace(C.Structure):
                 ("t", C.c_double), ("t_entry", C.c_double), ("fmin", C.c_double)]
 
 
+class _Env(C.Structure):
+    _fields_ = [("rgb", C.POINTER(C.c_float)), ("w", C.c_int32), ("h", C.c_int32)]
+
+
+class _PT(C.Structure):
+    _fields_ = [("spp", C.c_int32), ("bounces", C.c_int32), ("seed", C.c_uint64), ("env", _Env)]
+
+
 _lib = None
 
 
@@ -78,6 +86,13 @@ def lib():
         L.kno_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64,
                                  dp, dp, dp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32), dp, C.c_int]
+        u32p = C.POINTER(C.c_uint32)
+        L.kno_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.kno_onb.argtypes = [dp, dp, dp]
+        L.kno_cosine_dir.argtypes = [dp, C.c_double, C.c_double, dp]
+        L.kno_env_lookup.argtypes = [C.POINTER(_Env), dp, dp]
+        L.kno_path_trace.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_PT), C.c_void_p,
+                                     C.c_int64, dp, dp, dp, C.POINTER(C.c_uint8), C.c_int]
         _lib = L
     return _lib
 
@@ -172,6 +187,71 @@ class OracleScene:
                          status.ctypes.data_as(C.POINTER(C.c_int32)), _dp(fmin), nthreads)
         return dict(rgb=rgb, depth=depth, normal=normal, hit=hit, steps=steps,
                     status=status, fmin=fmin)
+
+
+    def path_trace(self, view, width: int, height: int, max_steps: int, eps: float, spp: int,
+                   bounces: int, seed: int, env=None, pixels=None, nthreads: int = 0) -> dict:
+        """Path-traced pixels (mean radiance over spp) plus the primary
+        segment's depth, normal and hit of sample 0."""
+        cam = make_camera(view, width, height, max_steps, eps)
+        envp = _make_env(env)
+        pt = _PT(spp, bounces, seed, envp)
+        if pixels is None:
+            npix, pix_ptr = width * height, None
+        else:
+            pixels = np.ascontiguousarray(pixels, np.int64)
+            npix, pix_ptr = pixels.size, pixels.ctypes.data
+        rgb = np.zeros((npix, 3))
+        depth = np.zeros(npix)
+        normal = np.zeros((npix, 3))
+        hit = np.zeros(npix, np.uint8)
+        lib().kno_path_trace(C.byref(self.c), C.byref(cam), C.byref(pt), pix_ptr, npix, _dp(rgb),
+                             _dp(depth), _dp(normal), hit.ctypes.data_as(C.POINTER(C.c_uint8)), nthreads)
+        return dict(rgb=rgb, depth=depth, normal=normal, hit=hit)
+
+
+_env_keep = []
+
+
+def _make_env(env) -> _Env:
+    if env is None:
+        return _Env(None, 0, 0)
+    a = np.ascontiguousarray(env, np.float32)
+    _env_keep.append(a)
+    if len(_env_keep) > 8:
+        del _env_keep[0]
+    return _Env(a.ctypes.data_as(C.POINTER(C.c_float)), a.shape[1], a.shape[0])
+
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    u32p = C.POINTER(C.c_uint32)
+    lib().kno_philox4x32_10(c.ctypes.data_as(u32p), k.ctypes.data_as(u32p), out.ctypes.data_as(u32p))
+    return out
+
+
+def onb(n):
+    n = _vec(n)
+    b1, b2 = np.zeros(3), np.zeros(3)
+    lib().kno_onb(_dp(n), _dp(b1), _dp(b2))
+    return b1, b2
+
+
+def cosine_dir(n, u1: float, u2: float) -> np.ndarray:
+    n = _vec(n)
+    out = np.zeros(3)
+    lib().kno_cosine_dir(_dp(n), u1, u2, _dp(out))
+    return out
+
+
+def env_lookup(env, d) -> np.ndarray:
+    e = _make_env(env)
+    d = _vec(d)
+    out = np.zeros(3)
+    lib().kno_env_lookup(C.byref(e), _dp(d), _dp(out))
+    return out
 
 
 def make_camera(view, width, height, max_steps, eps, background=(0.0, 0.0, 0.0)) -> _Camera:

@@ -331,8 +331,36 @@ CONFIGS = {
                views=8, max_steps=128, eps=1e-4, precision="bf16"),
     # 32^3 grid, H=64, 1920x1080, 4 spp, 3 bounces, FP8 vs BF16
     "c5": dict(N=32, H=64, radius=0.6, sigma=0.02, seed=5000, width=1920, height=1080,
-               views=1, max_steps=256, eps=1e-4, precision="fp8", spp=4, bounces=3),
+               views=1, max_steps=256, eps=1e-4, precision="fp8", spp=4, bounces=3,
+               env_seed=5005, path_seed=5006),
 }
+
+
+def env_map(width: int = 512, height: int = 256, seed: int = 5005) -> np.ndarray:
+    """Seeded procedural HDR environment, float32 [height][width][3] in the
+    equirectangular layout of the renderer (row 0 looks up +y; column u
+    looks along azimuth 2 pi (u - 1/2) from -z towards +x): a sky gradient
+    from horizon to zenith, a darker ground, and three Gaussian lobes of
+    random direction, width and intensity."""
+    rng = np.random.default_rng(seed)
+    v = (np.arange(height) + 0.5) / height
+    u = (np.arange(width) + 0.5) / width
+    th = np.pi * v[:, None]
+    ph = 2.0 * np.pi * (u[None, :] - 0.5)
+    d = np.stack([np.sin(th) * np.sin(ph), np.cos(th) * np.ones_like(ph), -np.sin(th) * np.cos(ph)], -1)
+    up = np.clip(d[..., 1], 0.0, 1.0)[..., None]
+    zenith = np.array([0.35, 0.55, 1.2])
+    horizon = np.array([1.3, 1.15, 1.0])
+    ground = np.array([0.25, 0.22, 0.2])
+    img = np.where(d[..., 1:2] >= 0, horizon + (zenith - horizon) * np.sqrt(up), ground)
+    for _ in range(3):
+        c = rng.normal(size=3)
+        c[1] = abs(c[1])
+        c /= np.linalg.norm(c)
+        k = rng.uniform(20.0, 200.0)
+        inten = rng.uniform(2.0, 10.0) * rng.uniform(0.6, 1.0, 3)
+        img = img + inten * np.exp(k * (d @ c - 1.0))[..., None]
+    return img.astype(np.float32)
 
 
 def config_scene(name: str) -> Scene:

@@ -399,3 +399,124 @@ def test_render_subset_and_threads_consistent():
     m = full["hit"] == 0
     assert m.any() and (full["depth"][m] == 0).all() and (full["rgb"][m] == 0).all()
     assert (full["status"][m] != O.HIT).all()
+
+
+# --------------------------------------------------------------------------
+# path tracing (Sec. 3.4.1: Lambertian path tracer)
+# --------------------------------------------------------------------------
+def test_philox_known_answers():
+    kat = json.load(open(os.path.join(GOLDEN, "philox_kat.json")))
+    for v in kat["vectors"]:
+        got = O.philox4x32_10([int(x, 16) for x in v["ctr"]], [int(x, 16) for x in v["key"]])
+        assert [int(x) for x in got] == [int(x, 16) for x in v["out"]]
+
+
+def test_onb_orthonormal():
+    rng = np.random.default_rng(0)
+    ns = [np.array([0, 0, 1.0]), np.array([0, 0, -1.0]), np.array([1.0, 0, 0]),
+          np.array([0, 1.0, 0])] + [v / np.linalg.norm(v) for v in rng.normal(size=(200, 3))]
+    for n in ns:
+        b1, b2 = O.onb(n)
+        M = np.stack([b1, b2, n])
+        np.testing.assert_allclose(M @ M.T, np.eye(3), atol=1e-12)
+        assert np.linalg.det(M) == pytest.approx(1.0, abs=1e-12)   # right-handed
+
+
+def test_cosine_sampling_distribution():
+    """Cosine-weighted directions: unit, in the hemisphere of n, and
+    E[cos] = 2/3, E[cos^2] = 1/2 (pdf cos/pi on the hemisphere)."""
+    rng = np.random.default_rng(1)
+    n = np.array([0.3, -0.5, 0.81])
+    n /= np.linalg.norm(n)
+    u = rng.random((20000, 2))
+    c = np.array([O.cosine_dir(n, a, b) @ n for a, b in u])
+    d = O.cosine_dir(n, 0.0, 0.0)
+    np.testing.assert_allclose(d, n, atol=1e-12)         # u1 = 0: along the normal
+    assert np.all(c >= 0)
+    assert abs(c.mean() - 2 / 3) < 0.01
+    assert abs((c ** 2).mean() - 0.5) < 0.01
+
+
+def test_env_lookup_bilinear_and_wrap():
+    """A map that is linear in the column index reads back that linear
+    function between texel centres; the seam wraps; the poles clamp."""
+    w, h = 16, 8
+    env = np.zeros((h, w, 3), np.float32)
+    env[..., 0] = np.arange(w)[None, :]
+    env[..., 1] = np.arange(h)[:, None]
+    env[..., 2] = 1.0
+
+    def direction(u, v):
+        th, ph = math.pi * v, 2 * math.pi * (u - 0.5)
+        return np.array([math.sin(th) * math.sin(ph), math.cos(th), -math.sin(th) * math.cos(ph)])
+
+    for u, v in [(0.3, 0.4), (0.55, 0.61), (0.8, 0.25)]:
+        got = O.env_lookup(env, direction(u, v))
+        np.testing.assert_allclose(got, [u * w - 0.5, v * h - 0.5, 1.0], atol=1e-9)
+    # across the seam: halfway between the last and the first column
+    got = O.env_lookup(env, direction(1.0 - 1e-12, 0.5))
+    assert got[0] == pytest.approx(0.5 * (w - 1), abs=1e-6)
+    # poles clamp to the first / last row
+    assert O.env_lookup(env, [0, 1.0, 0])[1] == pytest.approx(0.0)
+    assert O.env_lookup(env, [0, -1.0, 0])[1] == pytest.approx(h - 1.0)
+
+
+def test_path_trace_furnace_plane():
+    """Constant environment E and a plane of constant albedo a: a scattered
+    ray leaves the plane and cannot meet it again, so every hit pixel is
+    a E and every miss E, for any random numbers."""
+    n = np.array([0.2, 1.0, 0.1])
+    n /= np.linalg.norm(n)
+    a = np.array([0.6, 0.35, 0.8])
+    E = np.array([1.5, 2.0, 0.7], np.float32)
+    env = np.tile(E[None, None, :], (8, 16, 1))
+    sc = synth.constant_color_plane_scene(2, 32, n, -0.1, a, seed=3)
+    # the albedo the stored float32 logits encode
+    a = 1.0 / (1.0 + np.exp(-synth.unpack_col(sc.col[0])["bc2"].astype(np.float64)))
+    E = E.astype(np.float64)
+    os_ = O.OracleScene.from_scene(sc)
+    view = synth.View(eye=(0.4, 2.0, 1.5))
+    for spp, bounces in [(1, 1), (3, 3)]:
+        r = os_.path_trace(view, 24, 18, 128, 1e-4, spp, bounces, seed=5006, env=env)
+        hit = r["hit"] == 1
+        assert hit.sum() > 50 and (~hit).sum() > 20
+        # each sample contributes a E (hit) or E (miss): the pixel is
+        # (k a E + (spp - k) E) / spp for some k, k = spp where sample 0 and
+        # its jittered siblings all hit
+        mixes = np.stack([(k * a * E + (spp - k) * E) / spp for k in range(spp + 1)])
+        err = np.abs(r["rgb"][:, None, :] - mixes[None]).max(-1) / E.max()
+        k = err.argmin(1)
+        assert err.min(1).max() < 1e-12
+        assert np.mean(k[hit] == spp) > 0.9 and np.mean(k[~hit] == 0) > 0.9
+    # no bounces: a hit adds nothing
+    r = os_.path_trace(view, 24, 18, 128, 1e-4, 1, 0, seed=5006, env=env)
+    assert np.all(r["rgb"][r["hit"] == 1] == 0.0)
+
+
+def test_path_trace_plane_one_bounce_closed_form():
+    """One bounce off the plane under a varying environment: the pixel is
+    a * env(direction drawn from Philox(seed; pixel, 0, 1, 0)), computed
+    here from the primary hit's normal and the published generator."""
+    n = np.array([0.0, 1.0, 0.0])
+    a = np.array([0.5, 0.25, 0.75])
+    env = synth.env_map(64, 32, seed=5005)
+    sc = synth.constant_color_plane_scene(1, 32, n, -0.2, a, seed=4)
+    a = 1.0 / (1.0 + np.exp(-synth.unpack_col(sc.col[0])["bc2"].astype(np.float64)))
+    os_ = O.OracleScene.from_scene(sc)
+    view = synth.View(eye=(0.3, 1.8, 1.9))
+    W, H = 12, 9
+    r = os_.path_trace(view, W, H, 128, 1e-4, 1, 1, seed=77, env=env)
+    checked = 0
+    for p in range(W * H):
+        if r["hit"][p] != 1:
+            continue
+        x = O.philox4x32_10([p, 0, 1, 0], [77, 0])
+        u1, u2 = (x[0] >> 8) / 2.0 ** 24, (x[1] >> 8) / 2.0 ** 24
+        # basis of n = +y (Duff et al.): b1 = (1, 0, 0), b2 = (0, 1 - 1, -1) -> (0, 0, -1)
+        lx, ly, lz = math.sqrt(u1) * math.cos(2 * math.pi * u2), math.sqrt(u1) * math.sin(2 * math.pi * u2), \
+            math.sqrt(1 - u1)
+        d = np.array([lx, lz, -ly])
+        np.testing.assert_allclose(r["normal"][p], n, atol=1e-9)
+        np.testing.assert_allclose(r["rgb"][p], a * O.env_lookup(env, d), rtol=1e-9)
+        checked += 1
+    assert checked > 30
