@@ -158,7 +158,9 @@ def sphere_scene(N: int, H: int, radius: float, sigma: float, seed: int,
     o = sdf_offsets(H)
     centers = cell_centers(N)
     h = 1.0 / N                                   # half cell side in [-1,1]^3
-    sdf = np.empty((n_cells, P), np.float64)
+    # float64 values rounded once to float32 (assignment into the float32
+    # array); noise drawn in row chunks, the same stream as one draw
+    sdf = np.empty((n_cells, P), np.float32)
     # per-cell fold: W1[:, 0:3] <- h * W1b[:, 0:3],  b1 <- b1b + W1b[:, 0:3] @ c
     W1c = W1b.copy()
     W1c[:, 0:3] *= h
@@ -168,19 +170,25 @@ def sphere_scene(N: int, H: int, radius: float, sigma: float, seed: int,
     sdf[:, o["b2"][0]:o["b2"][0] + H] = b2b[None, :]
     sdf[:, o["W3"][0]:o["W3"][0] + o["W3"][1]] = W3b.ravel()[None, :]
     sdf[:, o["b3"][0]:o["b3"][0] + 1 + FEAT_DIM] = b3b[None, :]
-    sdf = sdf.astype(np.float32)
     if sigma > 0:
-        sdf += (sigma * rng.standard_normal((n_cells, P), dtype=np.float32))
+        rows = max(1, (1 << 22) // P)
+        buf = np.empty((rows, P), np.float32)
+        for r0 in range(0, n_cells, rows):
+            r1 = min(n_cells, r0 + rows)
+            nb = buf[:r1 - r0]
+            rng.standard_normal(out=nb, dtype=np.float32)
+            nb *= np.float32(sigma)
+            sdf[r0:r1] += nb
 
     Pc = col_block_size()
     oc = col_offsets()
     col = np.zeros((n_cells, Pc), np.float32)
-    col[:, oc["Wc1"][0]:oc["Wc1"][0] + COL_IN * COL_HIDDEN] = (
-        rng.standard_normal((n_cells, COL_IN * COL_HIDDEN), dtype=np.float32)
-        * np.float32(math.sqrt(2.0 / COL_IN)))
-    col[:, oc["Wc2"][0]:oc["Wc2"][0] + 3 * COL_HIDDEN] = (
-        rng.standard_normal((n_cells, 3 * COL_HIDDEN), dtype=np.float32)
-        * np.float32(math.sqrt(2.0 / COL_HIDDEN)))
+    w1 = col[:, oc["Wc1"][0]:oc["Wc1"][0] + COL_IN * COL_HIDDEN]
+    w1[...] = rng.standard_normal((n_cells, COL_IN * COL_HIDDEN), dtype=np.float32)
+    w1 *= np.float32(math.sqrt(2.0 / COL_IN))
+    w2 = col[:, oc["Wc2"][0]:oc["Wc2"][0] + 3 * COL_HIDDEN]
+    w2[...] = rng.standard_normal((n_cells, 3 * COL_HIDDEN), dtype=np.float32)
+    w2 *= np.float32(math.sqrt(2.0 / COL_HIDDEN))
     return Scene(N=N, H=H, sdf=sdf, col=col, name=name or f"sphere N={N} H={H}")
 
 
