@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -72,6 +74,11 @@ def parse():
     ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle time")
+    ap.add_argument("--serve", action="store_true",
+                    help="also run the serving workload (8 resident scenes, Poisson arrivals)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--pathtrace", action="store_true",
+                    help="also run the path-tracing workload (32^3, 4 spp, 3 bounces, FP8 vs BF16)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one plain float32 device copy of this many MiB "
                          "(a kernel of known HBM traffic, used to scale hardware byte counters)")
@@ -91,7 +98,7 @@ def timed_frames(ctx, sid, cams, out, steps, warmup, torch):
     for i in range(warmup):
         ctx.render_into(sid, cams[i % len(cams)], out)
     torch.cuda.synchronize()
-    gpu_ms, wall_ms, march_ms, launches, evals, hits = [], [], [], 0, 0, 0
+    gpu_ms, wall_ms, march_ms, launches, evals, hits, tiles, chunks, shade_ms = [], [], [], 0, 0, 0, 0, 0, []
     t0 = time.perf_counter()
     for i in range(steps):
         w0 = time.perf_counter()
@@ -102,10 +109,14 @@ def timed_frames(ctx, sid, cams, out, steps, warmup, torch):
         launches += st["march_launches"]
         evals += st["evals"]
         hits += st["hits"]
+        tiles += st["march_tiles"]
+        chunks += st["march_chunks"]
+        shade_ms.append(st["shade_ms"])
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     return dict(total_s=total, gpu_ms=gpu_ms, wall_ms=wall_ms, march_ms=sum(march_ms),
-                march_launches=launches, evals=evals, hits=hits)
+                march_launches=launches, evals=evals, hits=hits, tiles=tiles, chunks=chunks,
+                shade_ms=shade_ms)
 
 
 def cpu_baseline(scene, views, W, H, S, eps, target_s):
@@ -130,6 +141,107 @@ def cpu_baseline(scene, views, W, H, S, eps, target_s):
     return dict(value=total_px / total_t, unit="rays/s", cores=cores, kind="oracle",
                 sample=f"{total_px} seeded pixels ({n} per view) of the 8 C3 views, FP64, "
                        f"{total_t:.1f} s")
+
+
+def serve_bench(n_req: int, torch) -> dict:
+    """8 resident scenes (grids 16^3-32^3, H 32 / 64), requests at Poisson
+    arrivals of 200/s with seeded orbit views at resolutions drawn from
+    {256^2, 512^2, 800^2, 1920x1080}, 256 steps, bfloat16 march; 200 warm-up
+    requests, then n_req measured; latency = submission to completion."""
+    import threading
+    from paper_2206_10885_amd import kn, synth
+    Ns = [16, 16, 20, 24, 24, 28, 32, 32]
+    scenes = [synth.sphere_scene(Ns[k], 32 if k % 2 == 0 else 64, 0.5 + 0.02 * k, 0.02, 4000 + k)
+              for k in range(8)]
+    sizes = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+    ctx = kn.Context(0, hbm_budget_bytes=(sum(sc.sdf.nbytes for sc in scenes) * 3) + (16 << 30))
+    sids = [ctx.scene_create(sc, precisions=("bf16",)) for sc in scenes]
+    del scenes
+    warm = 200
+    total = warm + n_req
+    rng = np.random.default_rng(4004)
+    gaps = rng.exponential(1.0 / 200.0, total)
+    which = rng.integers(0, 8, total)
+    res = rng.integers(0, 4, total)
+    views = [synth.orbit_views(64, 4000 + k + 500) for k in range(8)]
+    ring = 40
+    outs = {i: [dict(rgb=torch.empty((h, w, 3), dtype=torch.float32, device="cuda")) for _ in range(ring)]
+            for i, (w, h) in enumerate(sizes)}
+    torch.cuda.synchronize()
+    ctx.serve_start(max_inflight=32, precision="bf16")
+    ids = [None] * total
+    submitted = threading.Semaphore(0)
+    t0 = time.perf_counter()
+    arrivals = t0 + np.cumsum(gaps)
+
+    def submitter():
+        for i in range(total):
+            dt = arrivals[i] - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            w, h = sizes[res[i]]
+            cam = kn.make_camera(views[which[i]][i % 64], w, h, 256, 1e-4, "bf16")
+            ids[i] = ctx.serve_submit(sids[which[i]], cam, outs[res[i]][i % ring])
+            submitted.release()
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, rays, done_t = [], 0, []
+    for i in range(total):
+        submitted.acquire()
+        st = ctx.serve_poll(ids[i], timeout_us=120_000_000)
+        if i >= warm:
+            lat.append(st["wall_ms"])
+            rays += st["rays"]
+            done_t.append(time.perf_counter())
+    th.join()
+    t_meas0 = arrivals[warm]
+    span = max(done_t) - t_meas0
+    ctx.serve_stop()
+    ctx.close()
+    return dict(requests=n_req, warmup=warm, arrival_rate=200.0, latency_ms_p50=pct(lat, 50),
+                latency_ms_p99=pct(lat, 99), latency_ms_max=max(lat), rays_per_s=rays / span,
+                offered_rays_per_s=rays / (arrivals[-1] - t_meas0), precision="bf16", max_steps=256,
+                scenes="8 resident: N=16,16,20,24,24,28,32,32; H=32 (even k) / 64 (odd k); r=0.5+0.02k")
+
+
+def pathtrace_bench(torch, frames: int = 3) -> dict:
+    """32^3 grid, H=64, 1920x1080, 4 spp, 3 Lambertian bounces, 512x256
+    environment; FP8 e4m3 march against bfloat16 (refinement and shading in
+    float32)."""
+    from paper_2206_10885_amd import kn, synth
+    c = synth.CONFIGS["c5"]
+    sc = synth.config_scene("c5")
+    env = torch.tensor(synth.env_map(512, 256, seed=c["env_seed"]), device="cuda")
+    view = synth.orbit_views(1, c["seed"] + 500)[0]
+    W, H = c["width"], c["height"]
+    ctx = kn.Context(0)
+    sid = ctx.scene_create(sc, precisions=("bf16", "fp8"))
+    del sc
+    out = ctx.alloc_frame(W, H)
+    res = {}
+    for prec in ("fp8", "bf16"):
+        cam = kn.make_camera(view, W, H, c["max_steps"], c["eps"], prec, spp=c["spp"],
+                             bounces=c["bounces"], seed=c["path_seed"], env=env)
+        ctx.render_into(sid, cam, out)
+        torch.cuda.synchronize()
+        ms, evals, hits = [], 0, 0
+        t = time.perf_counter()
+        for _ in range(frames):
+            st = ctx.render_into(sid, cam, out)
+            ms.append(st["gpu_ms"])
+            evals += st["evals"]
+            hits += st["hits"]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        paths = W * H * c["spp"] * frames
+        res[prec] = dict(paths_per_s=paths / dt, frame_ms_p50=pct(ms, 50), evals_per_path=evals / paths,
+                         hit_segments_per_path=hits / paths, segments_per_s=(hits + paths) / dt)
+    ctx.close()
+    res["fp8_over_bf16"] = res["fp8"]["paths_per_s"] / res["bf16"]["paths_per_s"]
+    res["workload"] = ("32^3 grid, SDF 39->2x64->16, 1920x1080, 4 spp, 3 bounces, 512x256 environment, "
+                       "256 steps; segments = primary paths + hit segments")
+    return res
 
 
 def main():
@@ -198,6 +310,11 @@ def main():
         "frame_wall_ms_p50": pct(r["wall_ms"], 50),
         "frame_wall_ms_p99": pct(r["wall_ms"], 99),
         "evals_per_ray": r["evals"] / (args.steps * rays),
+        "march_ms_per_frame": r["march_ms"] / args.steps,
+        "shade_ms_per_frame": sum(r["shade_ms"]) / args.steps,
+        "march_launches_per_frame": r["march_launches"] / args.steps,
+        "march_chunks_per_frame": r["chunks"] / args.steps,
+        "evals_per_tile_pair": r["evals"] / max(1, r["tiles"]),
         "hit_fraction": r["hits"] / (args.steps * rays),
         "roofline": roofline,
     }
@@ -221,6 +338,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.pathtrace:
+        line["pathtrace"] = pathtrace_bench(torch)
+    if args.serve:
+        line["serving"] = serve_bench(args.serve_requests, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, views, W, H, S, eps, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -47,7 +47,9 @@ typedef enum {
 typedef enum {
   KN_FP32 = 0,             /* march weights and activations in float32 */
   KN_BF16 = 1,             /* march in bfloat16 (RNE), float32 accumulate */
-  KN_FP8_E4M3 = 2          /* march in OCP fp8 e4m3 with per-(cell, layer) scales */
+  KN_FP8_E4M3 = 2          /* march in OCP fp8 e4m3: the two hidden layers' weights and
+                              inputs rounded (nearest even, saturating at 448) with
+                              power-of-two per-(cell, layer) scales; output row bf16 */
 } kn_precision;
 
 typedef struct kn_ctx kn_ctx;
@@ -130,15 +132,29 @@ typedef struct {
   float eye[3], look_at[3], up[3];
   float tan_half_diag;
   uint32_t width, height;
-  uint32_t spp;                    /* 1 (primary rays through pixel centers) */
-  uint32_t bounces;                /* 0 */
+  uint32_t spp;                    /* samples per pixel, 1..64; > 1 needs bounces >= 1 */
+  uint32_t bounces;                /* 0: primary rays through the pixel centres, rgb = the
+                                      hit's color (below); 1..16: path tracing, see below */
   uint32_t max_steps;              /* S, 1..1023 */
   float eps;                       /* hit threshold, > 0 */
   kn_precision precision;          /* weights used by the march */
   uint64_t seed;                   /* random stream for path tracing */
-  const float* env_rgb;            /* DEVICE [env_h][env_w][3] or NULL (black) */
+  const float* env_rgb;            /* DEVICE [env_h][env_w][3] or NULL (black); path tracing */
   uint32_t env_w, env_h;
 } kn_camera;
+/* Path tracing (bounces >= 1; Sec. 3.4.1: Lambertian surfaces, the color
+ * MLP output is the albedo).  Each pixel traces spp paths; sample s of pixel
+ * p is jittered inside the pixel by Philox-4x32-10 keyed by `seed` with
+ * counter (p, s, 0, 0) when spp > 1 (pixel centre otherwise).  At each hit
+ * the path scatters up to `bounces` times: throughput *= albedo, the new
+ * direction is cosine-weighted about the normal (uniforms from counter
+ * (p, s, k, 0) at the k-th scatter, basis of Duff et al. 2017), the new
+ * segment starts 1e-3 above the surface.  A path that leaves the grid adds
+ * throughput x env(direction) (equirectangular: u = 1/2 + atan2(d_x, -d_z)
+ * / 2 pi, v = acos(d_y) / pi, bilinear, wrapping in u, row 0 up); a hit
+ * after the last scatter adds nothing.  rgb = mean over the samples; depth,
+ * normal, hit, steps and trace describe sample 0's primary segment.  The
+ * serving loop renders primary rays only. */
 
 /* Per-pixel march record, for diagnostics and replay of a hit's shading:
  * t_march = ray parameter where the march stopped, t_entry = where the ray
@@ -176,7 +192,7 @@ typedef struct {
   uint32_t march_launches;         /* out (kernel_times): march launches */
   double march_ms;                 /* out (kernel_times): summed march kernel time */
   double shade_ms;                 /* out (kernel_times): shading kernel time */
-  uint64_t march_tiles;            /* out: 16-ray MFMA tiles evaluated by the march */
+  uint64_t march_tiles;            /* out: pairs of 16-ray MFMA tiles evaluated by the march */
   uint64_t march_chunks;           /* out: march work items (<= 256 rays of one cell) */
 } kn_stats;
 

@@ -20,6 +20,23 @@ __device__ __forceinline__ f32x4 mfma_bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// OCP fp8 e4m3 (gfx950): 16x16x32 product with the same lane layout as the
+// bfloat16 one (8 elements of K per lane).
+__device__ __forceinline__ f32x4 mfma_fp8(long a, long b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, c, 0, 0, 0);
+}
+
+constexpr float kE4m3MaxF = 448.0f;
+
+// eight float32 values (|x| <= 448) rounded to fp8 e4m3, nearest even
+__device__ __forceinline__ long fp8x8(float a, float b, float c, float d, float e, float f, float g, float h) {
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+  lo = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, lo, true);
+  int hi = __builtin_amdgcn_cvt_pk_fp8_f32(e, f, 0, false);
+  hi = __builtin_amdgcn_cvt_pk_fp8_f32(g, h, hi, true);
+  return (long)(((uint64_t)(uint32_t)hi << 32) | (uint64_t)(uint32_t)lo);
+}
+
 __device__ __forceinline__ int lane_id() { return threadIdx.x & 63; }
 
 // sin(2 pi r), cos(2 pi r) on the hardware units (input in revolutions).
@@ -142,6 +159,82 @@ __device__ __forceinline__ float quad_bcast(float v) {
   constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF,
                                                             0xF, false));
+}
+
+// ---------------------------------------------------------------------------
+// Path tracing helpers
+// ---------------------------------------------------------------------------
+// Philox-4x32-10 counter-based generator (Salmon et al., SC 2011): ten
+// rounds of two 32x32 -> 64-bit products on counter words 0 and 2, the high
+// halves xored into the other words with the key, the key stepped by the two
+// Weyl constants between rounds.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+  for (int round = 0; round < 10; ++round) {
+    if (round > 0) {
+      k.x += 0x9E3779B9u;
+      k.y += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
+    const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
+    c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+  }
+  return c;
+}
+
+// uniform in [0, 1) from the top 24 bits
+__device__ __forceinline__ float u01(uint32_t x) { return (float)(x >> 8) * (1.0f / 16777216.0f); }
+
+// the two uniforms of path (pixel, sample) at event k (0: pixel jitter,
+// k >= 1: the k-th scatter)
+__device__ __forceinline__ void path_uniforms(uint32_t seed_lo, uint32_t seed_hi, uint32_t pixel, uint32_t sample,
+                                              uint32_t k, float* a, float* b) {
+  const uint4 x = philox4x32_10(make_uint4(pixel, sample, k, 0u), make_uint2(seed_lo, seed_hi));
+  *a = u01(x.x);
+  *b = u01(x.y);
+}
+
+// cosine-weighted direction about the unit normal n, in the orthonormal
+// basis of Duff et al. (JCGT 2017)
+__device__ __forceinline__ void cosine_dir(const float n[3], float u1, float u2, float out[3]) {
+  const float sign = n[2] >= 0.0f ? 1.0f : -1.0f;
+  const float a = -1.0f / (sign + n[2]);
+  const float b = n[0] * n[1] * a;
+  const float b1[3] = {1.0f + sign * n[0] * n[0] * a, sign * b, -sign * n[0]};
+  const float b2[3] = {b, sign + n[1] * n[1] * a, -n[1]};
+  const float r = sqrtf(u1), phi = 6.283185307179586f * u2;
+  float sp, cp;
+  sincosf(phi, &sp, &cp);
+  const float lx = r * cp, ly = r * sp, lz = sqrtf(fmaxf(1.0f - u1, 0.0f));
+#pragma unroll
+  for (int k = 0; k < 3; ++k) out[k] = lx * b1[k] + ly * b2[k] + lz * n[k];
+}
+
+// equirectangular environment [h][w][3]: u = 1/2 + atan2(d_x, -d_z) / 2 pi,
+// v = acos(d_y) / pi; bilinear between texel centres, wrap in u, clamp in v
+__device__ __forceinline__ void env_lookup(const float* env, uint32_t w, uint32_t h, const float d[3],
+                                           float rgb[3]) {
+  if (!env) {
+    rgb[0] = rgb[1] = rgb[2] = 0.0f;
+    return;
+  }
+  const float u = 0.5f + atan2f(d[0], -d[2]) * 0.15915494309189535f;
+  const float v = acosf(fminf(fmaxf(d[1], -1.0f), 1.0f)) * 0.3183098861837907f;
+  const float x = u * (float)w - 0.5f, y = v * (float)h - 0.5f;
+  const float fx0 = floorf(x), fy0 = floorf(y);
+  const float fx = x - fx0, fy = y - fy0;
+  int x0 = (int)fx0 % (int)w;
+  if (x0 < 0) x0 += (int)w;
+  const int x1 = (x0 + 1) % (int)w;
+  const int y0 = min(max((int)fy0, 0), (int)h - 1), y1 = min(max((int)fy0 + 1, 0), (int)h - 1);
+  const float* r0 = env + (size_t)y0 * w * 3;
+  const float* r1 = env + (size_t)y1 * w * 3;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const float t0 = (1.0f - fx) * r0[3 * x0 + c] + fx * r0[3 * x1 + c];
+    const float t1 = (1.0f - fx) * r1[3 * x0 + c] + fx * r1[3 * x1 + c];
+    rgb[c] = (1.0f - fy) * t0 + fy * t1;
+  }
 }
 
 }  // namespace kn

@@ -56,10 +56,12 @@ __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t 
 }
 
 __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int steps, float t,
-                                           float t_entry, int32_t cell, int32_t status) {
-  o.rgb[3 * pix + 0] = o.bg[0];
-  o.rgb[3 * pix + 1] = o.bg[1];
-  o.rgb[3 * pix + 2] = o.bg[2];
+                                           float t_entry, int32_t cell, int32_t status, bool rgb = true) {
+  if (rgb) {
+    o.rgb[3 * pix + 0] = o.bg[0];
+    o.rgb[3 * pix + 1] = o.bg[1];
+    o.rgb[3 * pix + 2] = o.bg[2];
+  }
   if (o.depth) o.depth[pix] = 0.0f;
   if (o.normal) {
     o.normal[3 * pix + 0] = 0.0f;
@@ -85,6 +87,7 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
   float d[3] = {0, 0, 0};
   if (valid) {
     const int row = (int)(pix / (uint32_t)a.W), col = (int)(pix % (uint32_t)a.W);
+    const uint32_t rid = a.rid_base + pix;
     const float u = (2.0f * ((float)col + 0.5f) / (float)a.W - 1.0f) * a.tx;
     const float v = (1.0f - 2.0f * ((float)row + 0.5f) / (float)a.Hh) * a.ty;
     float n2 = 0.0f;
@@ -116,14 +119,98 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
         idx[k] = min(max(i, 0), sg.N - 1);
       }
       cell = sg.cell_base + (uint32_t)(idx[0] + sg.N * (idx[1] + sg.N * idx[2]));
-      a.rs[pix] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2], pix};
-      a.U[pix] = RayRec{t0, t0, cell, pix};
+      a.rs[rid] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2],
+                            (a.slot << kPixBits) | pix};
+      a.U[pix] = RayRec{t0, t0, cell, rid};
     } else {
-      a.U[pix] = RayRec{0.0f, 0.0f, kInvalidKey, pix};
+      a.U[pix] = RayRec{0.0f, 0.0f, kInvalidKey, rid};
       write_miss(a.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss);
     }
   }
   atomic_count_grouped(a.counts, cell, inbox);
+  atomic_count_grouped(a.miss_done, a.slot, valid && !inbox);
+}
+
+// Box clip of a ray (slab method); false when the ray misses the box.
+__device__ __forceinline__ bool slab(const SceneGeom& sg, const float o[3], const float d[3], float* t0, float* t1) {
+  float tn = -INFINITY, tf = INFINITY;
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] != 0.0f) {
+      const float a = (sg.bmin[k] - o[k]) / d[k], b = (sg.bmax[k] - o[k]) / d[k];
+      tn = fmaxf(tn, fminf(a, b));
+      tf = fminf(tf, fmaxf(a, b));
+    } else if (o[k] < sg.bmin[k] || o[k] > sg.bmax[k]) {
+      ok = false;
+    }
+  }
+  *t0 = fmaxf(tn, 0.0f);
+  *t1 = tf;
+  return ok && tn <= tf && tf > 0.0f;
+}
+
+__device__ __forceinline__ uint32_t entry_cell(const SceneGeom& sg, const float o[3], const float d[3], float t) {
+  int idx[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const int i = (int)floorf((o[k] + t * d[k] - sg.bmin[k]) * sg.inv_side[k]);
+    idx[k] = min(max(i, 0), sg.N - 1);
+  }
+  return sg.cell_base + (uint32_t)(idx[0] + sg.N * (idx[1] + sg.N * idx[2]));
+}
+
+// Path tracing: one thread per path (pixel, sample); pool ray id = path id.
+// Samples other than the pixel centre are jittered by Philox event 0.
+__global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
+  const uint32_t npath = (uint32_t)a.W * (uint32_t)a.Hh * a.spp;
+  const uint32_t id = blockIdx.x * 256u + threadIdx.x;
+  const bool valid = id < npath;
+  uint32_t cell = 0;
+  bool inbox = false;
+  if (valid) {
+    const uint32_t pix = id / a.spp, smp = id % a.spp;
+    const int row = (int)(pix / (uint32_t)a.W), col = (int)(pix % (uint32_t)a.W);
+    float xi1 = 0.5f, xi2 = 0.5f;
+    if (a.spp > 1) path_uniforms(a.seed_lo, a.seed_hi, pix, smp, 0u, &xi1, &xi2);
+    const float u = (2.0f * ((float)col + xi1) / (float)a.W - 1.0f) * a.tx;
+    const float v = (1.0f - 2.0f * ((float)row + xi2) / (float)a.Hh) * a.ty;
+    float d[3], n2 = 0.0f;
+    for (int k = 0; k < 3; ++k) {
+      d[k] = a.fwd[k] + u * a.right[k] + v * a.up[k];
+      n2 += d[k] * d[k];
+    }
+    const float inv = 1.0f / sqrtf(n2);
+    for (int k = 0; k < 3; ++k) d[k] *= inv;
+    float t0, tf;
+    inbox = slab(a.sg, a.eye, d, &t0, &tf);
+    PathRec pr{{1.0f, 1.0f, 1.0f}, {0.0f, 0.0f, 0.0f}, 0u, 0u};
+    if (inbox) {
+      cell = entry_cell(a.sg, a.eye, d, t0);
+      a.rs[id] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2], (a.slot << kPixBits) | pix};
+      a.U[id] = RayRec{t0, t0, cell, id};
+    } else {
+      a.U[id] = RayRec{0.0f, 0.0f, kInvalidKey, id};
+      env_lookup(a.env, a.env_w, a.env_h, d, pr.L);
+      if (smp == 0) write_miss(a.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss, false);
+    }
+    a.path[id] = pr;
+  }
+  atomic_count_grouped(a.counts, cell, inbox);
+  atomic_count_grouped(a.miss_done, a.slot, valid && !inbox);
+}
+
+// Path tracing: pixel = mean radiance of its samples, in sample order.
+__global__ __launch_bounds__(256) void k_resolve(ResolveArgs a) {
+  const uint32_t pix = blockIdx.x * 256u + threadIdx.x;
+  if (pix >= a.npix) return;
+  float L[3] = {0.0f, 0.0f, 0.0f};
+  for (uint32_t s = 0; s < a.spp; ++s) {
+    const PathRec& pr = a.path[(size_t)pix * a.spp + s];
+    for (int c = 0; c < 3; ++c) L[c] += pr.L[c];
+  }
+  const float inv = 1.0f / (float)a.spp;
+  for (int c = 0; c < 3; ++c) a.rgb[3 * pix + c] = L[c] * inv;
 }
 
 // ---------------------------------------------------------------------------
@@ -168,7 +255,7 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
     if (lane == 15) {
       *a.n_chunks = nch;
       if (a.zero_word) *a.zero_word = 0u;
-      if (a.total) *a.total = er + vr;
+      if (a.total) *a.total += er + vr;
     }
     if (lane < (uint32_t)kGroups) {
       const uint32_t g0 = (uint32_t)(((uint64_t)nch * lane) / kGroups);
@@ -216,6 +303,7 @@ __device__ __forceinline__ bool grab_batch(uint32_t* grab, uint32_t n, uint32_t 
 }
 
 // thread 0 of the shading and query kernels: next chunk into s[0..3]
+// (cell, start, count, valid), batch cursor in s[4], s[5]
 __device__ __forceinline__ void next_item(uint32_t* grab, uint32_t n, const uint2* chunks, uint32_t* s) {
   if (s[4] >= s[5]) {
     uint32_t first, last;
@@ -237,7 +325,7 @@ __device__ __forceinline__ void next_item(uint32_t* grab, uint32_t n, const uint
 // counting-sort scatter of a record list by cell
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
-  const uint32_t n = a.n;
+  const uint32_t n = a.n_dev ? *a.n_dev : a.n;
   for (uint32_t base = blockIdx.x * 256u; base < n; base += gridDim.x * 256u) {
     const uint32_t i = base + threadIdx.x;
     RayRec r = i < n ? a.in[i] : RayRec{0, 0, kInvalidKey, 0};
@@ -246,6 +334,13 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
     const uint32_t pos = atomic_slot_grouped(a.cursor, cell, valid);
     if (valid) a.out[pos] = r;
   }
+}
+
+// Index of the pool scene that owns global cell `cell`.
+__device__ __forceinline__ uint32_t scene_of(const PoolTabs& t, uint32_t cell) {
+  uint32_t k = 0;
+  while (k + 1u < t.n_scenes && cell >= t.scenes[k].cell_end) ++k;
+  return k;
 }
 
 // Neighbour of `cell` through face f = 2 * axis + (positive side); f = 6 is
@@ -277,7 +372,8 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterChunksArgs a) {
 #pragma unroll
     for (int f = 0; f < 7; ++f)
       if (lane == f) mine = faces[f];
-    if (lane < 7 && mine) dst = atomicAdd(&a.cursor[neighbor_cell(a.sg, cell, lane)], mine);
+    if (lane < 7 && mine)
+      dst = atomicAdd(&a.cursor[neighbor_cell(a.tabs.scenes[scene_of(a.tabs, cell)].sg, cell, lane)], mine);
     uint32_t off = 0;
 #pragma unroll
     for (int f = 0; f < 7; ++f) {
@@ -397,10 +493,16 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
   return f + vec[3 * H];
 }
 
-template <int H, bool BF>
+// fp8: one tile through the two-tile evaluator (used by the point query)
+template <int H>
+__device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int g, const float (&v)[kPeSlots],
+                                                SoftplusK k);
+
+template <int H, int P>
 __device__ __forceinline__ float march_eval(const float* blk, int lane, int g, const float (&v)[kPeSlots],
                                             SoftplusK k) {
-  if constexpr (BF) return march_eval_bf16<H>(blk, lane, g, v, k);
+  if constexpr (P == kPrecBf16) return march_eval_bf16<H>(blk, lane, g, v, k);
+  else if constexpr (P == kPrecFp8) return march_eval_fp8<H>(blk, lane, g, v, k);
   else return march_eval_f32<H>(blk, lane, g, v, k);
 }
 
@@ -528,10 +630,92 @@ __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int
   f1 = s1 + vec[3 * H];
 }
 
-template <int H, bool BF>
+// fp8 e4m3: A fragments ([frag][lane] x 8 bytes); layer inputs quantised
+// with power-of-two scales (encoding: 1; a1: 1 / vec[3H+3]), the products
+// accumulated in float32, then u = acc * scale + bias; softplus in float32;
+// the SDF output row as in the bfloat16 variant.
+template <int H>
+__device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
+                                                const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
+  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  const uint2* fr = reinterpret_cast<const uint2*>(blk);
+  const float* vec = blk + 2 * 64 * NF;
+  const float s1 = vec[3 * H + 1], s2 = vec[3 * H + 2], ia = vec[3 * H + 3];
+  const long e0[2] = {fp8x8(v0[0], v0[1], v0[2], v0[3], v0[4], v0[5], v0[6], v0[7]),
+                      fp8x8(v0[8], v0[9], 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f)};
+  const long e1[2] = {fp8x8(v1[0], v1[1], v1[2], v1[3], v1[4], v1[5], v1[6], v1[7]),
+                      fp8x8(v1[8], v1[9], 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f)};
+  f32x4 acc0[NB], acc1[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const long w = __builtin_bit_cast(long, fr[(2 * b + c) * 64 + lane]);
+      acc0[b] = mfma_fp8(w, e0[c], acc0[b]);
+      acc1[b] = mfma_fp8(w, e1[c], acc1[b]);
+    }
+  float q0[NB][4], q1[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      q0[b][r] = fminf(softplus(fmaf(acc0[b][r], s1, bias[r]), k) * ia, kE4m3MaxF);
+      q1[b][r] = fminf(softplus(fmaf(acc1[b][r], s1, bias[r]), k) * ia, kE4m3MaxF);
+    }
+  }
+  long x0[H / 32], x1[H / 32];
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c) {
+    x0[c] = fp8x8(q0[2 * c][0], q0[2 * c][1], q0[2 * c][2], q0[2 * c][3], q0[2 * c + 1][0], q0[2 * c + 1][1],
+                  q0[2 * c + 1][2], q0[2 * c + 1][3]);
+    x1[c] = fp8x8(q1[2 * c][0], q1[2 * c][1], q1[2 * c][2], q1[2 * c][3], q1[2 * c + 1][0], q1[2 * c + 1][1],
+                  q1[2 * c + 1][2], q1[2 * c + 1][3]);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const long w = __builtin_bit_cast(long, fr[(F1 + b * (H / 32) + c) * 64 + lane]);
+      acc0[b] = mfma_fp8(w, x0[c], acc0[b]);
+      acc1[b] = mfma_fp8(w, x1[c], acc1[b]);
+    }
+  float s0 = 0.0f, s1v = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      s0 = fmaf(w3[r], bf16_round(softplus(fmaf(acc0[b][r], s2, bias[r]), k)), s0);
+      s1v = fmaf(w3[r], bf16_round(softplus(fmaf(acc1[b][r], s2, bias[r]), k)), s1v);
+    }
+  }
+  s0 += __shfl_xor(s0, 16);
+  s1v += __shfl_xor(s1v, 16);
+  s0 += __shfl_xor(s0, 32);
+  s1v += __shfl_xor(s1v, 32);
+  f0 = s0 + vec[3 * H];
+  f1 = s1v + vec[3 * H];
+}
+
+template <int H>
+__device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int g, const float (&v)[kPeSlots],
+                                                SoftplusK k) {
+  float f0, f1;
+  march_eval2_fp8<H>(blk, lane, g, v, v, k, f0, f1);
+  return f0;
+}
+
+template <int H, int P>
 __device__ __forceinline__ void march_eval2(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
                                             const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
-  if constexpr (BF) march_eval2_bf16<H>(blk, lane, g, v0, v1, k, f0, f1);
+  if constexpr (P == kPrecBf16) march_eval2_bf16<H>(blk, lane, g, v0, v1, k, f0, f1);
+  else if constexpr (P == kPrecFp8) march_eval2_fp8<H>(blk, lane, g, v0, v1, k, f0, f1);
   else march_eval2_f32<H>(blk, lane, g, v0, v1, k, f0, f1);
 }
 
@@ -593,16 +777,16 @@ enum : uint32_t { kStay = 0, kOutHit = 1, kOutNext = 2, kOutExit = 3, kOutBudget
 // the march: one workgroup (4 waves) per chunk of <= kChunk rays of one cell
 // ---------------------------------------------------------------------------
 struct Job {
-  uint32_t cell, start, count, id;
+  uint32_t cell, start, count, id, scene;
   bool valid;
 };
 
 __device__ __forceinline__ Job read_job(const volatile uint32_t* s) {
-  return Job{s[0], s[1], s[2], s[3], s[4] != 0u};
+  return Job{s[0], s[1], s[2], s[3], s[5], s[4] != 0u};
 }
 
-// thread 0: next work item into s[0..4], from the batch [bat[0], bat[1]) or
-// a new batch
+// thread 0: next work item into s[0..5] (cell, start, count, id, valid,
+// scene), from the batch [bat[0], bat[1]) or a new batch
 __device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s, uint32_t* bat) {
   if (bat[0] >= bat[1]) {
     uint32_t first, last;
@@ -619,32 +803,47 @@ __device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s, uint32
   s[1] = c.y;
   s[2] = c.x >> kCellBits;
   s[3] = j;
+  s[5] = scene_of(a.tabs, s[0]);
   s[4] = 1u;
 }
 
-template <int H, bool BF>
+// Both MLP widths in one kernel when HM = 0 (pools mixing scenes of H = 32
+// and H = 64); the branch is uniform over the workgroup.
+template <int HM, int P>
+__device__ __forceinline__ void march_eval2_h(int H, const float* blk, int lane, int g,
+                                              const float (&v0)[kPeSlots], const float (&v1)[kPeSlots],
+                                              SoftplusK k, float& f0, float& f1) {
+  if constexpr (HM != 0) {
+    march_eval2<HM, P>(blk, lane, g, v0, v1, k, f0, f1);
+  } else {
+    if (H == 64) march_eval2<64, P>(blk, lane, g, v0, v1, k, f0, f1);
+    else march_eval2<32, P>(blk, lane, g, v0, v1, k, f0, f1);
+  }
+}
+
+// s_st word of a staged ray: steps | exit axis << 10 | status << 12 | step budget << 16
+template <int HM, int P>
 __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
-  extern __shared__ float s_dyn[];
-  float* s_w = s_dyn;
-  float* s_t = s_dyn + a.block_words;
+  extern __shared__ __align__(16) float s_dyn[];
+  float* s_t = s_dyn;
   float* s_te = s_t + kChunk;
   float* s_o = s_te + kChunk;        // [3][kChunk]
   float* s_d = s_o + 3 * kChunk;     // [3][kChunk]
   float* s_tf = s_d + 3 * kChunk;
   float* s_ce = s_tf + kChunk;
-  uint32_t* s_rid = reinterpret_cast<uint32_t*>(s_ce + kChunk);
+  float* s_eps = s_ce + kChunk;
+  uint32_t* s_rid = reinterpret_cast<uint32_t*>(s_eps + kChunk);
   uint32_t* s_pix = s_rid + kChunk;
-  uint32_t* s_st = s_pix + kChunk;   // steps | exit axis << 10 | status << 12
+  uint32_t* s_st = s_pix + kChunk;
   uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
-  __shared__ uint32_t s_job[5], s_jn[5];   // current / next work item: cell, start, count, id, valid
+  float* s_w = reinterpret_cast<float*>(s_act + 2 * kChunk);      // weight block (16-byte aligned)
+  __shared__ uint32_t s_job[6], s_jn[6];   // current / next work item: cell, start, count, id, valid, scene
   __shared__ uint32_t s_bat[2];            // thread 0's batch of work items
   __shared__ uint32_t s_nact[2], s_pair;
   __shared__ uint32_t s_face[7], s_foff[7];
-  __shared__ uint32_t s_nhit, s_evals, s_tiles;
+  __shared__ uint32_t s_nhit, s_hbase, s_evals, s_tiles;
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
-  const SceneGeom& sg = a.sg;
-  const int N = sg.N;
   unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
   uint32_t loaded = 0xFFFFFFFFu;
   // this chunk's ray record and static data, loaded ahead during the
@@ -671,15 +870,21 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
     const Job jb = read_job(s_job);
     if (!jb.valid) break;
     const uint32_t cell = jb.cell, start = jb.start, count = jb.count, job = jb.id;
+    const SceneEnt* se = a.tabs.scenes + __builtin_amdgcn_readfirstlane(jb.scene);
+    const SceneGeom sg = se->sg;
+    const SoftplusK spk = se->spk;
+    const int H = HM ? HM : sg.H;
+    const int N = sg.N;
     const uint32_t lc = cell - sg.cell_base;
     const CellBox cb = cell_box(sg, lc);
     if (cell != loaded) {
-      stage_block(s_w, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_block(s_w, se->march + (size_t)lc * se->march_words, se->march_words);
       loaded = cell;
     }
     if ((uint32_t)tid < count) {
       const RayRec r = pf_rec_ok ? pf_rec : a.S[start + tid];
       const RayStatic st = pf_st_ok ? pf_st : a.rs[r.rid];
+      const ReqEnt* q = a.tabs.reqs + (st.pix >> kPixBits);
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
       int eax;
       const float ce = cell_exit(sg, cb, o, d, &eax);
@@ -691,9 +896,10 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       }
       s_tf[tid] = st.t_far;
       s_ce[tid] = ce;
+      s_eps[tid] = q->eps;
       s_rid[tid] = r.rid;
       s_pix[tid] = st.pix;
-      s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10);
+      s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10) | (q->max_steps << 16);
       s_act[tid] = (uint16_t)tid;
     }
     pf_rec_ok = pf_st_ok = false;
@@ -738,7 +944,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
           pe_values(pl, xl[0], xl[1], xl[2], v[u]);
         }
         float f[2];
-        march_eval2<H, BF>(s_w, lane, g, v[0], v[1], a.spk, f[0], f[1]);
+        march_eval2_h<HM, P>(H, s_w, lane, g, v[0], v[1], spk, f[0], f[1]);
         ++wave_tiles;
         bool stay[2] = {false, false};
 #pragma unroll
@@ -750,7 +956,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
             const uint32_t steps = (stw & 1023u) + 1u, eax = (stw >> 10) & 3u;
             uint32_t status = kStay;
             float tt = t[u];
-            if (f[u] < a.eps) {
+            if (f[u] < s_eps[r_]) {
               status = kOutHit;
             } else {
               const float te = fmaxf(tt, s_ce[r_]);
@@ -762,10 +968,10 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
                 const int ni = (eax == 0 ? cb.ix : (eax == 1 ? cb.iy : cb.iz)) + sgn;
                 status = (ni < 0 || ni >= N || tt > s_tf[r_]) ? kOutExit : kOutNext;
               }
-              if ((status == kStay || status == kOutNext) && steps >= (uint32_t)a.max_steps) status = kOutBudget;
+              if ((status == kStay || status == kOutNext) && steps >= (stw >> 16)) status = kOutBudget;
             }
             s_t[r_] = tt;
-            s_st[r_] = steps | (eax << 10) | (status << 12);
+            s_st[r_] = steps | (eax << 10) | (status << 12) | (stw & 0xFFFF0000u);
             stay[u] = status == kStay;
           }
         }
@@ -805,14 +1011,15 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       atomicAdd(&s_tiles, wave_tiles);
     }
 
-    // results: misses written out, hits to the per-ray hit array, rays for
+    // results: misses written out, hits appended to the hit list, rays for
     // the next round into this chunk's range of U, grouped by exit face
     // (face 6: still in this cell after max_passes)
-    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0;
+    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0, slot = 0;
+    bool miss = false;
     float t = 0.0f, t_entry = 0.0f;
     if ((uint32_t)tid < count) {
       const uint32_t stw = s_st[tid];
-      status = stw >> 12;
+      status = (stw >> 12) & 7u;
       steps = stw & 1023u;
       t = s_t[tid];
       t_entry = s_te[tid];
@@ -822,13 +1029,29 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         if (status == kOutNext) t_entry = t;
         rank = atomicAdd(&s_face[face], 1u);
       } else if (status == kOutHit) {
-        a.HL[s_rid[tid]] = RayRec{t, s_te[tid], cell | (steps << kCellBits), s_rid[tid]};
-        atomicAdd(&s_nhit, 1u);
+        rank = atomicAdd(&s_nhit, 1u);
       } else {
-        write_miss(a.out, s_pix[tid], (int)steps, t, s_te[tid], (int32_t)cell,
-                   status == kOutExit ? kExitMiss : kBudgetMiss);
+        const uint32_t px = s_pix[tid];
+        slot = px >> kPixBits;
+        miss = true;
+        const ReqEnt& q = a.tabs.reqs[slot];
+        const int32_t mst = status == kOutExit ? kExitMiss : kBudgetMiss;
+        if (q.pt) {
+          // the path escapes: radiance += throughput x environment
+          const uint32_t rid = s_rid[tid];
+          PathRec& pr = a.tabs.path[rid];
+          const float d[3] = {s_d[tid], s_d[kChunk + tid], s_d[2 * kChunk + tid]};
+          float e[3];
+          env_lookup(q.env, q.env_w, q.env_h, d, e);
+          for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
+          if (pr.bounce == 0 && rid % q.spp == 0)
+            write_miss(q.out, px & kPixMask, (int)steps, t, t_entry, (int32_t)cell, mst, false);
+        } else {
+          write_miss(q.out, px & kPixMask, (int)steps, t, t_entry, (int32_t)cell, mst);
+        }
       }
     }
+    atomic_count_grouped(a.tabs.miss_done, slot, miss);
     __syncthreads();
     if (tid == 0) {
       uint32_t off = 0;
@@ -838,7 +1061,10 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       }
       a.chunk_out[2 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
       a.chunk_out[2 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
-      if (s_nhit) atomicAdd(&a.hit_count[cell], s_nhit);
+      if (s_nhit) {
+        atomicAdd(&a.hit_count[cell], s_nhit);
+        s_hbase = atomicAdd(a.n_hits, s_nhit);
+      }
       wg_evals += s_evals;
       wg_tiles += s_tiles;
       ++wg_chunks;
@@ -847,10 +1073,14 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       if (n) atomicAdd(&a.counts_next[neighbor_cell(sg, cell, tid - 1)], n);
     }
     __syncthreads();
-    if ((uint32_t)tid < count && (status == kOutNext || status == kStay))
-      a.U[start + s_foff[face] + rank] =
-          RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
-    if (tid < 5) s_job[tid] = s_jn[tid];
+    if ((uint32_t)tid < count) {
+      if (status == kOutNext || status == kStay)
+        a.U[start + s_foff[face] + rank] =
+            RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
+      else if (status == kOutHit)
+        a.hits[s_hbase + rank] = RayRec{t, t_entry, cell | (steps << kCellBits), s_rid[tid]};
+    }
+    if (tid < 6) s_job[tid] = s_jn[tid];
     __syncthreads();
   }
   if (tid == 0 && wg_chunks) {
@@ -930,34 +1160,51 @@ __device__ __forceinline__ float color_in_slot(int e, const float xl[3], const f
 // ---------------------------------------------------------------------------
 // shading: per chunk of a cell's hits; each wave shades 4 hits per tile
 // ---------------------------------------------------------------------------
-template <int H>
+template <int HM>
+__device__ __forceinline__ f32x4 sdf_full_h(int H, const float* blk, int lane, int g, bool value_col,
+                                            const float (&v)[kPeSlots], SoftplusK k) {
+  if constexpr (HM != 0) {
+    return sdf_full<HM>(blk, lane, g, value_col, v, k);
+  } else {
+    if (H == 64) return sdf_full<64>(blk, lane, g, value_col, v, k);
+    return sdf_full<32>(blk, lane, g, value_col, v, k);
+  }
+}
+
+// PT: path tracing; the hit scatters (Lambertian, albedo = color MLP) or
+// ends its path; otherwise the color is the pixel's rgb.
+template <int HM, bool PT>
 __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
-  extern __shared__ float s_mem[];
-  float* s_block = s_mem;
-  float* s_stage = s_mem + a.block_words;  // 4 waves x 4 hits x 48
-  __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
+  extern __shared__ __align__(16) float s_mem[];
+  float* s_stage = s_mem;                 // 4 waves x 4 hits x 48
+  float* s_block = s_mem + 4 * 4 * kColIn;
+  __shared__ uint32_t s_job[7];   // cell, start, count, valid, batch cursor, batch end, scene
   const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
   const int wave = threadIdx.x >> 6;
   const bool value_col = s == 0;
   const PeLane pl = make_pe_lane(g);
-  const SceneGeom& sg = a.sg;
-  const float* vec = nullptr;
   uint32_t loaded = 0xFFFFFFFFu;
   if (threadIdx.x == 0) s_job[4] = s_job[5] = 0u;
-  constexpr int NB = H / 16;
-  constexpr int SC1 = NB * kPeSlots + NB * (H / 4) + H / 4;  // first color fragment slot
   for (;;) {
-    if (threadIdx.x == 0) next_item(a.grab, *a.n_chunks, a.chunks, s_job);
+    if (threadIdx.x == 0) {
+      next_item(a.grab, *a.n_chunks, a.chunks, s_job);
+      if (s_job[3]) s_job[6] = scene_of(a.tabs, s_job[0]);
+    }
     __syncthreads();
     if (!s_job[3]) break;
     const uint32_t cell = s_job[0], start = s_job[1], count = s_job[2];
+    const SceneEnt* se = a.tabs.scenes + __builtin_amdgcn_readfirstlane(s_job[6]);
+    const SceneGeom sg = se->sg;
+    const SoftplusK spk = se->spk;
+    const int H = HM ? HM : sg.H;
     const uint32_t lc = cell - sg.cell_base;
     if (cell != loaded) {
-      stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_block(s_block, se->shade + (size_t)lc * se->shade_words, se->shade_words);
       __syncthreads();
       loaded = cell;
     }
-    vec = s_block + 64 * shade_frag_slots(H);
+    const float* vec = s_block + 64 * shade_frag_slots(H);
+    const int SC1 = (H / 16) * kPeSlots + (H / 16) * (H / 4) + H / 4;  // first color fragment slot
     const CellBox cb = cell_box(sg, lc);
     float* stage = s_stage + wave * 4 * kColIn;
     for (uint32_t base = (uint32_t)wave * 4u; base < count; base += 16u) {
@@ -979,8 +1226,9 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
 #pragma unroll
         for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(fmaf(t, d[k], o[k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
         float v[kPeSlots];
-        pe_values_tangent(pl, s, s ? sg.inv_half[s - 1] : 0.0f, xl[0], xl[1], xl[2], v);
-        y = sdf_full<H>(s_block, lane, g, value_col, v, a.spk);
+        const float ih = s == 1 ? sg.inv_half[0] : s == 2 ? sg.inv_half[1] : s == 3 ? sg.inv_half[2] : 0.0f;
+        pe_values_tangent(pl, s, ih, xl[0], xl[1], xl[2], v);
+        y = sdf_full_h<HM>(H, s_block, lane, g, value_col, v, spk);
         const int src = 4 * h;
         fval = __shfl(y[0], src);
         gr[0] = __shfl(y[0], src + 1);
@@ -1029,21 +1277,71 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         c2 = mfma_f32(s_block[(SC1 + 24 + q) * 64 + lane], fmaxf(c1[q / 4][q % 4], 0.0f), c2);
-      if (valid && g == 0 && value_col) {
-        const uint32_t px = st.pix;
-        a.out.rgb[3 * px + 0] = sigmoid(c2[0]);
-        a.out.rgb[3 * px + 1] = sigmoid(c2[1]);
-        a.out.rgb[3 * px + 2] = sigmoid(c2[2]);
-        if (a.out.depth) a.out.depth[px] = t;
-        if (a.out.normal) {
-          a.out.normal[3 * px + 0] = n[0];
-          a.out.normal[3 * px + 1] = n[1];
-          a.out.normal[3 * px + 2] = n[2];
+      const bool writer = valid && g == 0 && value_col;
+      const uint32_t slot = st.pix >> kPixBits;
+      bool done = writer, spawn = false;
+      uint32_t ncell = 0;
+      RayRec nrec{0, 0, 0, 0};
+      if (writer) {
+        const ReqEnt& q = a.tabs.reqs[slot];
+        const OutPtrs& out = q.out;
+        const uint32_t px = st.pix & kPixMask;
+        const float rgb[3] = {sigmoid(c2[0]), sigmoid(c2[1]), sigmoid(c2[2])};
+        bool aux = true;
+        PathRec pr;
+        uint32_t smp = 0;
+        if constexpr (PT) {
+          pr = a.tabs.path[r.rid];
+          smp = r.rid % q.spp;
+          aux = pr.bounce == 0 && smp == 0;
+        } else {
+          out.rgb[3 * px + 0] = rgb[0];
+          out.rgb[3 * px + 1] = rgb[1];
+          out.rgb[3 * px + 2] = rgb[2];
         }
-        if (a.out.hit) a.out.hit[px] = 1;
-        if (a.out.steps) a.out.steps[px] = (uint16_t)(r.key >> kCellBits);
-        if (a.out.trace) a.out.trace[px] = TraceRec{r.t, r.t_entry, (int32_t)cell, kHit};
+        if (aux) {
+          if (out.depth) out.depth[px] = t;
+          if (out.normal) {
+            out.normal[3 * px + 0] = n[0];
+            out.normal[3 * px + 1] = n[1];
+            out.normal[3 * px + 2] = n[2];
+          }
+          if (out.hit) out.hit[px] = 1;
+          if (out.steps) out.steps[px] = (uint16_t)(r.key >> kCellBits);
+          if (out.trace) out.trace[px] = TraceRec{r.t, r.t_entry, (int32_t)cell, kHit};
+        }
+        if constexpr (PT) {
+          if (pr.bounce < q.bounces) {
+            // scatter: cosine-weighted about n, throughput x albedo, the new
+            // segment starts 1e-3 off the surface
+            for (int c = 0; c < 3; ++c) pr.T[c] *= rgb[c];
+            float u1, u2, nd[3], no[3];
+            path_uniforms(q.seed_lo, q.seed_hi, px, smp, pr.bounce + 1u, &u1, &u2);
+            cosine_dir(n, u1, u2, nd);
+            for (int c = 0; c < 3; ++c) no[c] = o[c] + t * d[c] + 1e-3f * n[c];
+            ++pr.bounce;
+            float t0, tf;
+            if (slab(sg, no, nd, &t0, &tf)) {
+              ncell = entry_cell(sg, no, nd, t0);
+              a.rs[r.rid] = RayStatic{no[0], no[1], no[2], tf, nd[0], nd[1], nd[2], st.pix};
+              nrec = RayRec{t0, t0, ncell, r.rid};
+              spawn = true;
+              done = false;
+            } else {
+              float e[3];
+              env_lookup(q.env, q.env_w, q.env_h, nd, e);
+              for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
+            }
+          }
+          a.tabs.path[r.rid] = pr;
+        }
       }
+      if constexpr (PT) {
+        const uint32_t pos = atomic_slot_grouped(a.n_spawn, 0u, spawn);
+        atomic_count_grouped(a.counts_next, ncell, spawn);
+        if (spawn) a.spawn[pos] = nrec;
+      }
+      atomic_count_grouped(a.tabs.hit_done, slot, done);
     }
     __syncthreads();
   }
@@ -1068,9 +1366,9 @@ __global__ __launch_bounds__(256) void k_query_bin(QueryBinArgs a) {
   atomic_count_grouped(a.counts, cell, valid);
 }
 
-template <int H, bool BF>
+template <int H, int P>
 __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
-  extern __shared__ float s_block[];
+  extern __shared__ __align__(16) float s_block[];
   __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
   const int lane = lane_id(), g = lane >> 4, p = lane & 15, wave = threadIdx.x >> 6;
   const PeLane pl = make_pe_lane(g);
@@ -1098,7 +1396,7 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
       for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(a.pts[3 * (size_t)pi + k], sg.inv_half[k], cb.cs[k]) : 0.0f;
       float v[kPeSlots];
       pe_values(pl, xl[0], xl[1], xl[2], v);
-      const float f = march_eval<H, BF>(s_block, lane, g, v, a.spk);
+      const float f = march_eval<H, P>(s_block, lane, g, v, a.spk);
       if (valid && g == 0) a.d_out[pi] = f;
     }
     __syncthreads();
@@ -1107,7 +1405,7 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
 
 template <int H>
 __global__ __launch_bounds__(256) void k_query_full(QueryArgs a) {
-  extern __shared__ float s_block[];
+  extern __shared__ __align__(16) float s_block[];
   __shared__ uint32_t s_job[6];   // cell, start, count, valid, batch cursor, batch end
   const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
   const int wave = threadIdx.x >> 6;
@@ -1178,27 +1476,55 @@ hipError_t launch_scatter_chunks(const ScatterChunksArgs& a, uint32_t grid, hipS
 }
 
 size_t march_lds_bytes(uint32_t block_words) {
-  return (size_t)block_words * 4u + (size_t)kChunk * (13u * 4u + 2u * 2u);  // 13 words + 2 list slots per ray
+  return (size_t)block_words * 4u + (size_t)kChunk * (14u * 4u + 2u * 2u);  // 14 words + 2 list slots per ray
 }
 
-template <int H, bool BF>
-static hipError_t march_t(const MarchArgs& a, uint32_t grid, hipStream_t st) {
-  const size_t lds = march_lds_bytes(a.block_words);
-  hipLaunchKernelGGL((k_march<H, BF>), dim3(grid), dim3(256), lds, st, a);
+size_t shade_lds_bytes(uint32_t block_words) { return ((size_t)block_words + 4u * 4u * kColIn) * 4u; }
+
+template <int HM, int P>
+static hipError_t march_t(const MarchArgs& a, uint32_t block_words, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_march<HM, P>), dim3(grid), dim3(256), march_lds_bytes(block_words), st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_march(const MarchArgs& a, int H, int bf16, uint32_t grid, hipStream_t st) {
-  if (H == 32) return bf16 ? march_t<32, true>(a, grid, st) : march_t<32, false>(a, grid, st);
-  if (H == 64) return bf16 ? march_t<64, true>(a, grid, st) : march_t<64, false>(a, grid, st);
+template <int HM>
+static hipError_t march_p(const MarchArgs& a, int prec, uint32_t block_words, uint32_t grid, hipStream_t st) {
+  if (prec == kPrecF32) return march_t<HM, kPrecF32>(a, block_words, grid, st);
+  if (prec == kPrecBf16) return march_t<HM, kPrecBf16>(a, block_words, grid, st);
+  if (prec == kPrecFp8) return march_t<HM, kPrecFp8>(a, block_words, grid, st);
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_shade(const ShadeArgs& a, int H, uint32_t grid, hipStream_t st) {
-  const size_t lds = ((size_t)a.block_words + 4u * 4u * kColIn) * 4u;
-  if (H == 32) hipLaunchKernelGGL(k_shade<32>, dim3(grid), dim3(256), lds, st, a);
-  else if (H == 64) hipLaunchKernelGGL(k_shade<64>, dim3(grid), dim3(256), lds, st, a);
+hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_words, uint32_t grid,
+                        hipStream_t st) {
+  if (H == 32) return march_p<32>(a, prec, block_words, grid, st);
+  if (H == 64) return march_p<64>(a, prec, block_words, grid, st);
+  if (H == 0) return march_p<0>(a, prec, block_words, grid, st);
+  return hipErrorInvalidValue;
+}
+
+template <bool PT>
+static hipError_t shade_t(const ShadeArgs& a, int H, size_t lds, uint32_t grid, hipStream_t st) {
+  if (H == 32) hipLaunchKernelGGL((k_shade<32, PT>), dim3(grid), dim3(256), lds, st, a);
+  else if (H == 64) hipLaunchKernelGGL((k_shade<64, PT>), dim3(grid), dim3(256), lds, st, a);
+  else if (H == 0) hipLaunchKernelGGL((k_shade<0, PT>), dim3(grid), dim3(256), lds, st, a);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_shade(const ShadeArgs& a, int H, bool pt, uint32_t block_words, uint32_t grid, hipStream_t st) {
+  const size_t lds = shade_lds_bytes(block_words);
+  return pt ? shade_t<true>(a, H, lds, grid, st) : shade_t<false>(a, H, lds, grid, st);
+}
+
+hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st) {
+  const uint32_t n = (uint32_t)a.W * (uint32_t)a.Hh * a.spp;
+  hipLaunchKernelGGL(k_raygen_pt, dim3((n + 255u) / 256u), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_resolve, dim3((a.npix + 255u) / 256u), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
@@ -1207,18 +1533,20 @@ hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_query_d(const QueryArgs& a, int H, int bf16, uint32_t grid, hipStream_t st) {
-  const size_t lds = (size_t)a.block_words * 4u;
-  if (H == 32) {
-    if (bf16) hipLaunchKernelGGL((k_query_d<32, true>), dim3(grid), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_query_d<32, false>), dim3(grid), dim3(256), lds, st, a);
-  } else if (H == 64) {
-    if (bf16) hipLaunchKernelGGL((k_query_d<64, true>), dim3(grid), dim3(256), lds, st, a);
-    else hipLaunchKernelGGL((k_query_d<64, false>), dim3(grid), dim3(256), lds, st, a);
-  } else {
-    return hipErrorInvalidValue;
-  }
+template <int H>
+static hipError_t query_d_h(const QueryArgs& a, int prec, size_t lds, uint32_t grid, hipStream_t st) {
+  if (prec == kPrecF32) hipLaunchKernelGGL((k_query_d<H, kPrecF32>), dim3(grid), dim3(256), lds, st, a);
+  else if (prec == kPrecBf16) hipLaunchKernelGGL((k_query_d<H, kPrecBf16>), dim3(grid), dim3(256), lds, st, a);
+  else if (prec == kPrecFp8) hipLaunchKernelGGL((k_query_d<H, kPrecFp8>), dim3(grid), dim3(256), lds, st, a);
+  else return hipErrorInvalidValue;
   return hipGetLastError();
+}
+
+hipError_t launch_query_d(const QueryArgs& a, int H, int prec, uint32_t grid, hipStream_t st) {
+  const size_t lds = (size_t)a.block_words * 4u;
+  if (H == 32) return query_d_h<32>(a, prec, lds, grid, st);
+  if (H == 64) return query_d_h<64>(a, prec, lds, grid, st);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream_t st) {

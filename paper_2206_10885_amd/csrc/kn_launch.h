@@ -16,15 +16,77 @@ struct OutPtrs {
   float bg[3];
 };
 
+// One resident scene of a ray pool: its range of global cells and the
+// packed weights the kernels stage.
+struct SceneEnt {
+  SceneGeom sg;            // sg.cell_base = first global cell
+  uint32_t cell_end;       // cell_base + N^3
+  uint32_t march_words, shade_words;
+  const float* march;      // march blocks in the pool's precision
+  const float* shade;      // float32 shading blocks
+  SoftplusK spk;
+};
+
+// One request slot of a ray pool (a frame being rendered).
+struct ReqEnt {
+  OutPtrs out;
+  float eps;
+  uint32_t max_steps;
+  uint32_t npix;
+  uint32_t pt;             // 1: path tracing (paths = npix * spp; rgb resolved from them)
+  uint32_t spp, bounces;
+  uint32_t seed_lo, seed_hi;
+  const float* env;        // [env_h][env_w][3] or null (black)
+  uint32_t env_w, env_h;
+};
+
+// Tables shared by the kernels of a pool.
+struct PoolTabs {
+  const SceneEnt* scenes;  // sorted by cell_base, contiguous cell ranges
+  const ReqEnt* reqs;      // indexed by slot (RayStatic::pix >> kPixBits)
+  uint32_t n_scenes;
+  uint32_t* miss_done;     // [kMaxSlots]
+  uint32_t* hit_done;      // [kMaxSlots]
+  PathRec* path;           // per pool ray, path tracing only
+};
+
 struct RaygenArgs {
+  SceneGeom sg;            // the request's scene (global cell ids)
+  float eye[3], fwd[3], right[3], up[3];
+  float tx, ty;
+  int W, Hh;
+  uint32_t slot;           // request slot
+  uint32_t rid_base;       // first pool ray id of the request
+  RayStatic* rs;           // indexed by pool ray id
+  RayRec* U;               // this request's records (one per pixel)
+  uint32_t* counts;        // arrivals per global cell for the next round
+  uint32_t* miss_done;     // per slot
+  OutPtrs out;
+};
+
+// path tracing: one thread per path (pixel, sample)
+struct RaygenPtArgs {
   SceneGeom sg;
   float eye[3], fwd[3], right[3], up[3];
   float tx, ty;
   int W, Hh;
+  uint32_t spp;
+  uint32_t seed_lo, seed_hi;
+  const float* env;
+  uint32_t env_w, env_h;
+  uint32_t slot;
   RayStatic* rs;
-  RayRec* U;
+  RayRec* U;               // one record per path (index = pool ray id)
+  PathRec* path;
   uint32_t* counts;
+  uint32_t* miss_done;     // paths finished, per slot
   OutPtrs out;
+};
+
+struct ResolveArgs {
+  const PathRec* path;
+  uint32_t npix, spp;
+  float* rgb;
 };
 
 struct ScanArgs {
@@ -37,18 +99,19 @@ struct ScanArgs {
   uint32_t* grab;        // out: per-range work cursors (kGroups x kGroupStride words)
   uint32_t* grab0;       // out: a copy of the initial cursors (to restart a pass)
   uint32_t* zero_word;   // optional counter reset to 0
-  uint32_t* total;       // optional: receives the sum of the counts
+  uint32_t* total;       // optional: the sum of the counts is added to it
 };
 
 struct ScatterArgs {
   const RayRec* in;      // records (keys 0xFFFFFFFF are skipped)
   RayRec* out;
-  uint32_t n;
+  uint32_t n;            // number of records, or
+  const uint32_t* n_dev; // if not null: the number of records, read on the device
   uint32_t* cursor;
 };
 
 struct ScatterChunksArgs {
-  SceneGeom sg;
+  PoolTabs tabs;
   const uint2* chunks;        // previous round's chunks
   const uint4* chunk_out;     // their exit-face counts (2 x uint4 per chunk)
   const uint32_t* n_chunks;
@@ -58,9 +121,7 @@ struct ScatterChunksArgs {
 };
 
 struct MarchArgs {
-  SceneGeom sg;
-  const float* blocks;
-  uint32_t block_words;
+  PoolTabs tabs;
   const RayRec* S;
   const RayStatic* rs;
   const uint2* chunks;
@@ -69,27 +130,23 @@ struct MarchArgs {
   uint4* chunk_out;          // per chunk: rays leaving through each face / staying, hits
   RayRec* U;                 // next-round rays, in each chunk's own range
   uint32_t* counts_next;
-  RayRec* HL;                // hits, indexed by ray id
-  uint32_t* hit_count;
+  RayRec* hits;              // hit list (appended)
+  uint32_t* n_hits;          // its length
+  uint32_t* hit_count;       // hits per cell
   unsigned long long* evals;     // [0] evaluations, [1] tiles, [2] chunks
-  int max_steps;
   int max_passes;            // in-cell passes per chunk before the rest wait a round
-  float eps;
-  SoftplusK spk;
-  OutPtrs out;
 };
 
 struct ShadeArgs {
-  SceneGeom sg;
-  const float* blocks;
-  uint32_t block_words;
+  PoolTabs tabs;
   const RayRec* S;
-  const RayStatic* rs;
+  RayStatic* rs;         // path tracing: rewritten for the next segment
   const uint2* chunks;
   const uint32_t* n_chunks;
   uint32_t* grab;        // per-range work cursors set by the scan
-  SoftplusK spk;
-  OutPtrs out;
+  RayRec* spawn;         // path tracing: records of the next segments
+  uint32_t* n_spawn;     // their count
+  uint32_t* counts_next; // arrivals per cell for the next round
 };
 
 struct QueryBinArgs {
@@ -116,14 +173,21 @@ struct QueryArgs {
 };
 
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st);
+hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st);
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t st);
 hipError_t launch_scatter(const ScatterArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter_chunks(const ScatterChunksArgs& a, uint32_t grid, hipStream_t st);
 size_t march_lds_bytes(uint32_t block_words);
-hipError_t launch_march(const MarchArgs& a, int H, int bf16, uint32_t grid, hipStream_t st);
-hipError_t launch_shade(const ShadeArgs& a, int H, uint32_t grid, hipStream_t st);
+// H = 32 or 64 selects a kernel specialised for scenes of that width; H = 0
+// one that reads each scene's width from the table (mixed pools).
+// block_words = the largest block among the pool's scenes.
+size_t shade_lds_bytes(uint32_t block_words);
+hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_words, uint32_t grid,
+                        hipStream_t st);
+hipError_t launch_shade(const ShadeArgs& a, int H, bool pt, uint32_t block_words, uint32_t grid, hipStream_t st);
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st);
-hipError_t launch_query_d(const QueryArgs& a, int H, int bf16, uint32_t grid, hipStream_t st);
+hipError_t launch_query_d(const QueryArgs& a, int H, int prec, uint32_t grid, hipStream_t st);
 hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream_t st);
 
 }  // namespace kn

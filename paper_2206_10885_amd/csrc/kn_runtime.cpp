@@ -20,7 +20,7 @@
 
 #include "../../include/kn.h"
 #include "kn_launch.h"
-#include "kn_serve.h"
+#include "kn_quant.h"
 
 using namespace kn;
 
@@ -38,23 +38,8 @@ kn_status fail(kn_status s, const char* fmt, ...) {
   return s;
 }
 
-constexpr uint32_t kMarchChunk = 128;   // rays per march work item
 constexpr uint32_t kShadeChunk = 64;    // hits per shading work item
 constexpr uint32_t kQueryChunk = 256;   // points per query work item
-
-uint16_t bf16_bits(float x) {
-  uint32_t u;
-  memcpy(&u, &x, 4);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan
-  const uint32_t r = ((u >> 16) & 1u) + 0x7fffu;
-  return (uint16_t)((u + r) >> 16);
-}
-float bf16_value(float x) {
-  uint32_t u = (uint32_t)bf16_bits(x) << 16;
-  float y;
-  memcpy(&y, &u, 4);
-  return y;
-}
 
 }  // namespace
 
@@ -136,6 +121,58 @@ static void pack_march_bf16(const float* blk, int H, float* out_words) {
   vec[3 * H + 1] = vec[3 * H + 2] = vec[3 * H + 3] = 0.0f;
 }
 
+static double softplus_host(double u, double beta) {
+  return std::max(u, 0.0) + std::log1p(std::exp(-beta * std::fabs(u))) / beta;
+}
+
+// fp8 e4m3 march block: W1 and W2 scaled by power-of-two per-layer scales
+// (absmax / 448 rounded up); the layer-2 input scale from a bound on the
+// layer-1 activations over inputs with |e_k| <= 1:
+//   a1_j <= softplus(sum_k |W1[j][k]| + b1[j]).
+static void pack_march_fp8(const float* blk, int H, float beta, float* out_words) {
+  const SdfView w = sdf_view(blk, H);
+  const int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  double m1 = 0.0, m2 = 0.0, abound = 0.0;
+  for (int j = 0; j < H; ++j) {
+    double row = 0.0;
+    for (int k = 0; k < kSdfIn; ++k) {
+      m1 = std::max(m1, (double)std::fabs(w.W1[j * kSdfIn + k]));
+      row += std::fabs((double)w.W1[j * kSdfIn + k]);
+    }
+    abound = std::max(abound, softplus_host(row + w.b1[j], beta));
+    for (int k = 0; k < H; ++k) m2 = std::max(m2, (double)std::fabs(w.W2[j * H + k]));
+  }
+  const float s1 = pow2_scale(m1), s2 = pow2_scale(m2), sa = pow2_scale(abound * 1.01);
+  uint8_t* out = reinterpret_cast<uint8_t*>(out_words);
+  for (int f = 0; f < NF; ++f) {
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = lane % 16, g = lane / 16;
+      for (int i = 0; i < 8; ++i) {
+        float val;
+        if (f < F1) {
+          const int b = f / 2, c = f % 2, j = 8 * c + i;
+          const int idx = j < kPeSlots ? pe_index(j, g) : -1;
+          val = idx < 0 ? 0.0f : w.W1[(16 * b + m) * kSdfIn + idx] / s1;
+        } else {
+          const int f2 = f - F1, b = f2 / (H / 32), c = f2 % (H / 32);
+          val = w.W2[(16 * b + m) * H + unit_bf16(c, g, i)] / s2;
+        }
+        out[((size_t)f * 64 + lane) * 8 + i] = e4m3_bits(val);
+      }
+    }
+  }
+  float* vec = out_words + 2 * 64 * NF;
+  for (int j = 0; j < H; ++j) {
+    vec[j] = w.b1[j];
+    vec[H + j] = w.b2[j];
+    vec[2 * H + j] = bf16_value(w.W3[j]);
+  }
+  vec[3 * H] = w.b3[0];
+  vec[3 * H + 1] = s1;
+  vec[3 * H + 2] = s2 * sa;
+  vec[3 * H + 3] = 1.0f / sa;
+}
+
 static void pack_shade(const float* blk, const float* cblk, int H, float* out) {
   const SdfView w = sdf_view(blk, H);
   const float* Wc1 = cblk;
@@ -188,26 +225,44 @@ struct KnScene {
   int N = 0, H = 0;
   float* march_f32 = nullptr;
   float* march_bf16 = nullptr;
+  float* march_fp8 = nullptr;
   float* shade = nullptr;
-  uint32_t march_f32_words = 0, march_bf16_words = 0, shade_words = 0;
+  uint32_t march_f32_words = 0, march_bf16_words = 0, march_fp8_words = 0, shade_words = 0;
+
+  const float* march(int prec) const {
+    return prec == KN_BF16 ? march_bf16 : prec == KN_FP8_E4M3 ? march_fp8 : march_f32;
+  }
+  uint32_t march_words(int prec) const {
+    return prec == KN_BF16 ? march_bf16_words : prec == KN_FP8_E4M3 ? march_fp8_words : march_f32_words;
+  }
   size_t bytes = 0;
   std::atomic<int> refs{0};
 };
 
-struct Workspace {
-  size_t rays = 0, cells = 0, chunks = 0;
+// Device buffers of a ray pool: up to `cap` rays (ids 0..cap-1) over
+// `cells` global cells (record layouts in kn_internal.h).
+struct Pool {
+  size_t cap = 0, cells = 0, chunks = 0;
   RayStatic* rs = nullptr;
-  RayRec* U = nullptr;
-  RayRec* S = nullptr;
-  RayRec* HL = nullptr;
+  RayRec* U = nullptr;             // next-round records, in the ranges of the round's chunks
+  RayRec* S = nullptr;             // a round's records sorted by cell
+  RayRec* Uin = nullptr;           // records of newly generated rays
+  RayRec* HL = nullptr;            // hit list since the last shading pass
+  PathRec* path = nullptr;         // path tracing state (allocated on first use)
   uint32_t* counts = nullptr;      // [2][cells]
   uint32_t* hit_count = nullptr;   // [cells]
   uint32_t* cursor = nullptr;      // [cells]
-  uint2* chunk = nullptr;          // [2][chunks]
+  uint2* chunk = nullptr;          // [3][chunks]: rounds of parity 0 / 1, shading
   uint4* chunk_out = nullptr;      // [2][chunks][2]
   Ctrl* ctrl = nullptr;
+  SceneEnt* scenes = nullptr;      // [kMaxScenes]
+  ReqEnt* reqs = nullptr;          // [kMaxSlots]
   size_t bytes = 0;
 };
+
+namespace kn {
+class ServeLoop;
+}
 
 struct kn_ctx {
   int device = 0;
@@ -215,18 +270,21 @@ struct kn_ctx {
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
-  std::mutex mu;              // scenes map
+  std::mutex mu;              // scenes map, scene reference counts
   std::mutex render_mu;       // one render / query at a time on the workspace
+  std::mutex serve_mu;        // serving loop start / stop
   std::map<kn_scene_id, KnScene*> scenes;
   kn_scene_id next_id = 1;
   std::atomic<bool> poisoned{false};
-  Workspace ws;
+  Pool ws;                     // the workspace of kn_render and kn_query
   uint32_t* pinned = nullptr;  // round counters read back by the host
+  SceneEnt* h_scene = nullptr; // pinned staging of kn_render's tables
+  ReqEnt* h_req = nullptr;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   hipEvent_t ev_round[4] = {nullptr, nullptr, nullptr, nullptr};
   int max_passes = 4;          // in-cell passes of a march chunk per round
   std::vector<hipEvent_t> ev_kernel;  // pairs around timed kernel launches
-  std::unique_ptr<kn::ServeLoop> serve;
+  std::shared_ptr<kn::ServeLoop> serve;
 };
 
 namespace {
@@ -246,43 +304,54 @@ kn_status check_ctx(kn_ctx* ctx) {
   return KN_OK;
 }
 
-void free_ws(Workspace& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.HL, w.counts, w.hit_count, w.cursor, w.chunk, w.chunk_out, w.ctrl};
+void free_pool(Pool& w) {
+  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.hit_count, w.cursor, w.chunk,
+                  w.chunk_out, w.ctrl, w.scenes, w.reqs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
-  w = Workspace{};
+  w = Pool{};
 }
 
-// grow-only workspace for `rays` records over `cells` cells; work chunks of
-// at least `min_chunk` records
-kn_status ensure_ws(kn_ctx* ctx, size_t rays, size_t cells, uint32_t min_chunk) {
-  Workspace& w = ctx->ws;
-  const size_t chunks = rays / min_chunk + cells + 2;
-  if (w.rays >= rays && w.cells >= cells && w.chunks >= chunks && w.ctrl) return KN_OK;
-  const size_t R = std::max(w.rays, rays), C = std::max(w.cells, cells),
-               K = std::max(w.chunks, chunks);
-  const size_t bytes = R * (sizeof(RayStatic) + 3 * sizeof(RayRec)) + C * 4 * 4 + K * 2 * (8 + 32) +
-                       sizeof(Ctrl);
+constexpr size_t kRayBytes = sizeof(RayStatic) + 4 * sizeof(RayRec);
+
+size_t pool_bytes(size_t R, size_t C, size_t K) {
+  return R * kRayBytes + C * 4 * 4 + K * (3 * 8 + 2 * 32) + sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) +
+         kMaxSlots * sizeof(ReqEnt);
+}
+
+// grow-only pool for `rays` records over `cells` cells (with path state if
+// `paths`)
+kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool paths = false) {
+  const size_t chunks = rays / kShadeChunk + cells + 2;
+  if (w.ctrl && w.cap >= rays && w.cells >= cells && w.chunks >= chunks && (!paths || w.path)) return KN_OK;
+  const size_t R = std::max(w.cap, rays), C = std::max(w.cells, cells), K = std::max(w.chunks, chunks);
+  const bool P = paths || w.path;
+  const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0);
   const uint64_t other = ctx->used.load() - w.bytes;
   if (other + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "ray workspace of %zu bytes exceeds the HBM budget", bytes);
+  if (w.ctrl) KN_HIP(ctx, hipDeviceSynchronize());
   ctx->used -= w.bytes;
-  free_ws(w);
-  Workspace n;
-  n.rays = R;
+  free_pool(w);
+  Pool n;
+  n.cap = R;
   n.cells = C;
   n.chunks = K;
   n.bytes = bytes;
   KN_HIP(ctx, hipMalloc(&n.rs, R * sizeof(RayStatic)));
   KN_HIP(ctx, hipMalloc(&n.U, R * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.S, R * sizeof(RayRec)));
+  KN_HIP(ctx, hipMalloc(&n.Uin, R * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
+  if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * 4));
   KN_HIP(ctx, hipMalloc(&n.cursor, C * 4));
-  KN_HIP(ctx, hipMalloc(&n.chunk, 2 * K * 8));
+  KN_HIP(ctx, hipMalloc(&n.chunk, 3 * K * 8));
   KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 32));
   KN_HIP(ctx, hipMalloc(&n.ctrl, sizeof(Ctrl)));
+  KN_HIP(ctx, hipMalloc(&n.scenes, kMaxScenes * sizeof(SceneEnt)));
+  KN_HIP(ctx, hipMalloc(&n.reqs, kMaxSlots * sizeof(ReqEnt)));
   w = n;
   ctx->used += bytes;
   return KN_OK;
@@ -293,6 +362,135 @@ SoftplusK softplus_consts(float beta) {
 }
 
 uint32_t persistent_grid(kn_ctx* ctx, uint32_t per_cu) { return (uint32_t)ctx->num_cu * per_cu; }
+
+PoolTabs pool_tabs(const Pool& w, uint32_t n_scenes) {
+  return PoolTabs{w.scenes, w.reqs, n_scenes, &w.ctrl->miss_done[0], &w.ctrl->hit_done[0], w.path};
+}
+
+SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base) {
+  SceneEnt e{};
+  e.sg = s->geom;
+  e.sg.cell_base = cell_base;
+  e.cell_end = cell_base + (uint32_t)(s->N * s->N * s->N);
+  e.march = s->march(prec);
+  e.march_words = s->march_words(prec);
+  e.shade = s->shade;
+  e.shade_words = s->shade_words;
+  e.spk = softplus_consts(s->geom.beta);
+  return e;
+}
+
+OutPtrs out_ptrs(const kn_frame* fr) {
+  return OutPtrs{fr->rgb, fr->depth, fr->normal, fr->hit, fr->steps,
+                 reinterpret_cast<TraceRec*>(fr->trace), {0.0f, 0.0f, 0.0f}};
+}
+
+// What the kernels of one pool round need to know about its tables.
+struct RoundCfg {
+  int hmode;              // 32 or 64 when every scene has that width, else 0
+  int prec;               // march precision (kn_precision)
+  uint32_t n_scenes;
+  uint32_t march_words;   // largest march block of the scenes
+  uint32_t shade_words;   // largest shading block
+  uint32_t cells;         // global cells in use
+  int max_passes;
+};
+
+// Round r: bins the records arriving for it (the previous round's leavers,
+// still in U, and n_new new records in Uin) by cell, then marches them.
+// reset_hitlist empties the hit list (after a shading pass consumed it).
+kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t n_new, bool reset_hitlist,
+                        hipStream_t st, hipEvent_t e0, hipEvent_t e1, const uint32_t* n_new_dev = nullptr) {
+  const int par = r & 1;
+  const PoolTabs tabs = pool_tabs(w, c.n_scenes);
+  ScanArgs sa{};
+  sa.counts = w.counts + par * w.cells;
+  sa.C = c.cells;
+  sa.T = kChunk;
+  sa.zero_counts = 1;
+  sa.cursor = w.cursor;
+  sa.chunks = w.chunk + (size_t)par * w.chunks;
+  sa.n_chunks = &w.ctrl->n_chunks[par];
+  sa.grab = w.ctrl->grab;
+  sa.grab0 = w.ctrl->grab0;
+  sa.zero_word = reset_hitlist ? &w.ctrl->n_hitlist : nullptr;
+  sa.total = nullptr;
+  KN_HIP(ctx, launch_scan(sa, st));
+  if (r > 0) {
+    ScatterChunksArgs sc{tabs,
+                         w.chunk + (size_t)(par ^ 1) * w.chunks,
+                         w.chunk_out + (size_t)(par ^ 1) * w.chunks * 2,
+                         &w.ctrl->n_chunks[par ^ 1],
+                         w.U,
+                         w.S,
+                         w.cursor};
+    KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 4), st));
+  }
+  if (n_new) {
+    ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor};
+    KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_new + 255u) / 256u, 4096u), st));
+  }
+  if (n_new_dev) {
+    ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor};
+    KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
+  }
+  MarchArgs ma{};
+  ma.tabs = tabs;
+  ma.S = w.S;
+  ma.rs = w.rs;
+  ma.chunks = w.chunk + (size_t)par * w.chunks;
+  ma.n_chunks = &w.ctrl->n_chunks[par];
+  ma.grab = w.ctrl->grab;
+  ma.chunk_out = w.chunk_out + (size_t)par * w.chunks * 2;
+  ma.U = w.U;
+  ma.counts_next = w.counts + (par ^ 1) * w.cells;
+  ma.hits = w.HL;
+  ma.n_hits = &w.ctrl->n_hitlist;
+  ma.hit_count = w.hit_count;
+  ma.evals = &w.ctrl->evals;
+  ma.max_passes = c.max_passes;
+  if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
+  KN_HIP(ctx, launch_march(ma, c.hmode, c.prec, c.march_words, persistent_grid(ctx, 4), st));
+  if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
+  return KN_OK;
+}
+
+// Shading pass over the hit list: hits binned by cell, refined, shaded.
+// With path tracing, hits that scatter append their next segment to Uin
+// (count in ctrl->n_in, cleared first) for round `next_round`.
+kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, hipStream_t st, hipEvent_t e0,
+                        hipEvent_t e1, bool pt = false, int next_round = 0) {
+  uint2* chunks = w.chunk + 2 * w.chunks;
+  ScanArgs sa{};
+  sa.counts = w.hit_count;
+  sa.C = c.cells;
+  sa.T = kShadeChunk;
+  sa.zero_counts = 1;
+  sa.cursor = w.cursor;
+  sa.chunks = chunks;
+  sa.n_chunks = &w.ctrl->n_chunks[2];
+  sa.grab = w.ctrl->grab;
+  sa.grab0 = w.ctrl->grab0;
+  sa.zero_word = pt ? &w.ctrl->n_in : nullptr;
+  sa.total = &w.ctrl->n_hits;
+  KN_HIP(ctx, launch_scan(sa, st));
+  ScatterArgs sc{w.HL, w.S, 0u, &w.ctrl->n_hitlist, w.cursor};
+  KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
+  ShadeArgs sh{};
+  sh.tabs = pool_tabs(w, c.n_scenes);
+  sh.S = w.S;
+  sh.rs = w.rs;
+  sh.chunks = chunks;
+  sh.n_chunks = &w.ctrl->n_chunks[2];
+  sh.grab = w.ctrl->grab;
+  sh.spawn = w.Uin;
+  sh.n_spawn = &w.ctrl->n_in;
+  sh.counts_next = w.counts + (next_round & 1) * w.cells;
+  if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
+  KN_HIP(ctx, launch_shade(sh, c.hmode, pt, c.shade_words, persistent_grid(ctx, 2), st));
+  if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
+  return KN_OK;
+}
 
 }  // namespace
 
@@ -317,6 +515,8 @@ kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out)
   ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)freeb);
   KN_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault));
+  KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_scene, sizeof(SceneEnt), hipHostMallocDefault));
+  KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_req, sizeof(ReqEnt), hipHostMallocDefault));
   KN_HIP(ctx, hipEventCreate(&ctx->ev_start));
   KN_HIP(ctx, hipEventCreate(&ctx->ev_end));
   for (auto& e : ctx->ev_round) KN_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -333,11 +533,14 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
     KnScene* s = kv.second;
     if (s->march_f32) (void)hipFree(s->march_f32);
     if (s->march_bf16) (void)hipFree(s->march_bf16);
+    if (s->march_fp8) (void)hipFree(s->march_fp8);
     if (s->shade) (void)hipFree(s->shade);
     delete s;
   }
-  free_ws(ctx->ws);
+  free_pool(ctx->ws);
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->h_scene) (void)hipHostFree(ctx->h_scene);
+  if (ctx->h_req) (void)hipHostFree(ctx->h_req);
   if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
   if (ctx->ev_end) (void)hipEventDestroy(ctx->ev_end);
   for (auto& e : ctx->ev_round)
@@ -370,8 +573,6 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
     return fail(KN_E_INVALID, "softplus_beta must be positive and finite");
   if (d->precisions & ~((1u << KN_BF16) | (1u << KN_FP8_E4M3)))
     return fail(KN_E_INVALID, "unknown precision bits 0x%x", d->precisions);
-  if (d->precisions & (1u << KN_FP8_E4M3))
-    return fail(KN_E_UNSUPPORTED, "fp8 scene copies are not built yet");
 
   const int N = (int)d->grid_n, H = (int)d->sdf_hidden;
   const size_t cells = (size_t)N * N * N;
@@ -399,12 +600,15 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
     g.half[k] = (float)(0.5 * side);
     g.inv_half[k] = (float)(2.0 / side);
   }
-  s->march_f32_words = (uint32_t)march_block_words(H, 0);
-  s->march_bf16_words = (uint32_t)march_block_words(H, 1);
+  s->march_f32_words = (uint32_t)march_block_words(H, kPrecF32);
+  s->march_bf16_words = (uint32_t)march_block_words(H, kPrecBf16);
+  s->march_fp8_words = (uint32_t)march_block_words(H, kPrecFp8);
   s->shade_words = (uint32_t)shade_block_words(H);
   const bool want_bf16 = (d->precisions >> KN_BF16) & 1u;
+  const bool want_fp8 = (d->precisions >> KN_FP8_E4M3) & 1u;
   const size_t bytes = cells * 4 * ((size_t)s->march_f32_words + s->shade_words +
-                                    (want_bf16 ? s->march_bf16_words : 0));
+                                    (want_bf16 ? s->march_bf16_words : 0) +
+                                    (want_fp8 ? s->march_fp8_words : 0));
   if (ctx->used.load() + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "scene needs %zu bytes; budget %llu, in use %llu", bytes,
                 (unsigned long long)ctx->budget, (unsigned long long)ctx->used.load());
@@ -424,6 +628,12 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
   if (want_bf16) {
     st = upload(&s->march_bf16, s->march_bf16_words,
                 [&](size_t c, float* o) { pack_march_bf16(d->sdf_params + c * psdf, H, o); });
+    if (st != KN_OK) return st;
+  }
+  if (want_fp8) {
+    const float beta = d->softplus_beta;
+    st = upload(&s->march_fp8, s->march_fp8_words,
+                [&](size_t c, float* o) { pack_march_fp8(d->sdf_params + c * psdf, H, beta, o); });
     if (st != KN_OK) return st;
   }
   st = upload(&s->shade, s->shade_words, [&](size_t c, float* o) {
@@ -452,6 +662,7 @@ kn_status kn_scene_destroy(kn_ctx* ctx, kn_scene_id id) {
   (void)hipStreamSynchronize(ctx->stream);
   if (s->march_f32) (void)hipFree(s->march_f32);
   if (s->march_bf16) (void)hipFree(s->march_bf16);
+  if (s->march_fp8) (void)hipFree(s->march_fp8);
   if (s->shade) (void)hipFree(s->shade);
   ctx->used -= s->bytes;
   delete s;
@@ -472,21 +683,30 @@ KnScene* find_scene(kn_ctx* ctx, kn_scene_id id) {
   return it == ctx->scenes.end() ? nullptr : it->second;
 }
 
+constexpr int kMaxBounces = 16;
+constexpr int kMaxSpp = 64;
+
 kn_status validate_camera(const kn_camera* c, const KnScene* s) {
   if (!c) return fail(KN_E_INVALID, "camera is NULL");
   if (c->width == 0 || c->height == 0) return fail(KN_E_INVALID, "empty image %ux%u", c->width, c->height);
-  if ((uint64_t)c->width * c->height > (1ull << 28))
-    return fail(KN_E_INVALID, "image %ux%u too large", c->width, c->height);
+  if ((uint64_t)c->width * c->height > (uint64_t)kPixMask + 1u)
+    return fail(KN_E_INVALID, "image %ux%u has more than 2^24 pixels", c->width, c->height);
   if (c->max_steps < 1 || c->max_steps > (uint32_t)kMaxSteps)
     return fail(KN_E_INVALID, "max_steps %u not in 1..%d", c->max_steps, kMaxSteps);
   if (!(c->eps > 0.0f) || !std::isfinite(c->eps)) return fail(KN_E_INVALID, "eps must be positive");
-  if (c->spp != 1 || c->bounces != 0)
-    return fail(KN_E_UNSUPPORTED, "only spp = 1 primary casts are implemented (spp %u, bounces %u)",
-                c->spp, c->bounces);
-  if (c->precision == KN_BF16 && !s->march_bf16)
-    return fail(KN_E_INVALID, "scene has no bf16 copy (set precisions bit KN_BF16)");
-  if (c->precision != KN_FP32 && c->precision != KN_BF16)
-    return fail(KN_E_UNSUPPORTED, "precision %d not available", (int)c->precision);
+  if (c->bounces > kMaxBounces) return fail(KN_E_INVALID, "bounces %u above %d", c->bounces, kMaxBounces);
+  if (c->spp < 1 || c->spp > kMaxSpp) return fail(KN_E_INVALID, "spp %u not in 1..%d", c->spp, kMaxSpp);
+  if (c->bounces == 0 && (c->spp != 1 || c->env_rgb))
+    return fail(KN_E_UNSUPPORTED, "spp > 1 and environment maps need path tracing (bounces >= 1)");
+  if ((uint64_t)c->width * c->height * c->spp > ((uint64_t)1 << 30))
+    return fail(KN_E_INVALID, "%ux%u x %u spp paths exceed 2^30", c->width, c->height, c->spp);
+  if (c->env_rgb && (c->env_w == 0 || c->env_h == 0))
+    return fail(KN_E_INVALID, "environment map of size %ux%u", c->env_w, c->env_h);
+  if (c->precision != KN_FP32 && c->precision != KN_BF16 && c->precision != KN_FP8_E4M3)
+    return fail(KN_E_INVALID, "unknown precision %d", (int)c->precision);
+  if (!s->march(c->precision))
+    return fail(KN_E_INVALID, "scene has no copy in precision %d (set its bit in precisions)",
+                (int)c->precision);
   if (c->tan_half_diag < 0.0f || !std::isfinite(c->tan_half_diag))
     return fail(KN_E_INVALID, "tan_half_diag must be >= 0");
   double f[3], dist2 = 0;
@@ -533,150 +753,163 @@ void camera_basis(const kn_camera* c, RaygenArgs& a) {
 
 namespace kn {
 
-// Enqueues and runs one frame on `stream`; the caller holds render_mu.
+// Enqueues and runs one frame on `stream` as a one-request pool; the caller
+// holds render_mu.  bounces > 0 path-traces spp paths per pixel.
 kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_frame* fr,
                        hipStream_t stream, kn_stats* stats) {
   const auto wall0 = std::chrono::steady_clock::now();
-  const size_t rays = (size_t)c->width * c->height;
+  const bool pt = c->bounces > 0;
+  const uint32_t spp = pt ? c->spp : 1u;
+  const size_t npix = (size_t)c->width * c->height;
+  const size_t rays = npix * spp;
   const size_t cells = (size_t)s->N * s->N * s->N;
-  kn_status st = ensure_ws(ctx, rays, cells, std::min(kMarchChunk, kShadeChunk));
+  kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt);
   if (st != KN_OK) return st;
-  Workspace& w = ctx->ws;
-  OutPtrs out{fr->rgb, fr->depth, fr->normal, fr->hit, fr->steps,
-              reinterpret_cast<TraceRec*>(fr->trace), {0.0f, 0.0f, 0.0f}};
-  const bool bf = c->precision == KN_BF16;
-  const SoftplusK spk = softplus_consts(s->geom.beta);
+  Pool& w = ctx->ws;
+  *ctx->h_scene = scene_entry(s, (int)c->precision, 0u);
+  ReqEnt q{};
+  q.out = out_ptrs(fr);
+  q.eps = c->eps;
+  q.max_steps = c->max_steps;
+  q.npix = (uint32_t)npix;
+  q.pt = pt ? 1u : 0u;
+  q.spp = spp;
+  q.bounces = c->bounces;
+  q.seed_lo = (uint32_t)c->seed;
+  q.seed_hi = (uint32_t)(c->seed >> 32);
+  q.env = c->env_rgb;
+  q.env_w = c->env_w;
+  q.env_h = c->env_h;
+  *ctx->h_req = q;
+  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, s->shade_words, (uint32_t)cells,
+                     ctx->max_passes};
 
   const bool timed = stats && stats->kernel_times;
-  const size_t need_ev = 2 * ((size_t)c->max_steps + 3);
-  while (timed && ctx->ev_kernel.size() < need_ev) {
-    hipEvent_t e;
-    KN_HIP(ctx, hipEventCreate(&e));
-    ctx->ev_kernel.push_back(e);
-  }
+  std::vector<std::pair<int, int>> march_ev, shade_ev;   // event index pairs
+  size_t next_ev = 0;
+  auto ev = [&](hipEvent_t* e) -> kn_status {
+    if (!timed) {
+      *e = nullptr;
+      return KN_OK;
+    }
+    if (next_ev == ctx->ev_kernel.size()) {
+      hipEvent_t x;
+      KN_HIP(ctx, hipEventCreate(&x));
+      ctx->ev_kernel.push_back(x);
+    }
+    *e = ctx->ev_kernel[next_ev++];
+    return KN_OK;
+  };
+  hipEvent_t e0, e1;
+
   KN_HIP(ctx, hipEventRecord(ctx->ev_start, stream));
+  KN_HIP(ctx, hipMemcpyAsync(w.scenes, ctx->h_scene, sizeof(SceneEnt), hipMemcpyHostToDevice, stream));
+  KN_HIP(ctx, hipMemcpyAsync(w.reqs, ctx->h_req, sizeof(ReqEnt), hipMemcpyHostToDevice, stream));
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
-  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * cells * 4, stream));
-  KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, cells * 4, stream));
-  KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
+  // both parities of the per-cell counts ([2][w.cells]) and the hit counts
+  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * 4, stream));
 
   RaygenArgs rg{};
-  rg.sg = s->geom;
+  rg.sg = ctx->h_scene->sg;
   camera_basis(c, rg);
-  rg.W = (int)c->width;
-  rg.Hh = (int)c->height;
-  rg.rs = w.rs;
-  rg.U = w.U;
-  rg.counts = w.counts;
-  rg.out = out;
-  KN_HIP(ctx, launch_raygen(rg, stream));
-
-  const uint32_t scatter_grid = (uint32_t)std::min<size_t>((rays + 255) / 256, 4096);
-  const uint32_t march_grid = persistent_grid(ctx, 4);
-  // every round takes at least one SDF evaluation of every live ray
-  const int max_rounds = (int)c->max_steps + 2;
   int rounds = 0;
-  for (int r = 0; r < max_rounds; ++r) {
-    const int par = r & 1;
-    uint2* chunks = w.chunk + (size_t)par * w.chunks;
-    uint4* chunk_out = w.chunk_out + (size_t)par * w.chunks * 2;
-    ScanArgs sa{};
-    sa.counts = w.counts + par * cells;
-    sa.C = (uint32_t)cells;
-    sa.T = kChunk;
-    sa.zero_counts = 1;
-    sa.cursor = w.cursor;
-    sa.chunks = chunks;
-    sa.n_chunks = &w.ctrl->n_chunks[par];
-    sa.grab = w.ctrl->grab;
-    sa.grab0 = w.ctrl->grab0;
-    sa.zero_word = nullptr;
-    KN_HIP(ctx, launch_scan(sa, stream));
-    if (r == 0) {
-      ScatterArgs sc{w.U, w.S, (uint32_t)rays, w.cursor};
-      KN_HIP(ctx, launch_scatter(sc, scatter_grid, stream));
-    } else {
-      ScatterChunksArgs sc{s->geom,
-                           w.chunk + (size_t)(par ^ 1) * w.chunks,
-                           w.chunk_out + (size_t)(par ^ 1) * w.chunks * 2,
-                           &w.ctrl->n_chunks[par ^ 1],
-                           w.U,
-                           w.S,
-                           w.cursor};
-      KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 4), stream));
-    }
-    MarchArgs ma{};
-    ma.sg = s->geom;
-    ma.blocks = bf ? s->march_bf16 : s->march_f32;
-    ma.block_words = bf ? s->march_bf16_words : s->march_f32_words;
-    ma.S = w.S;
-    ma.rs = w.rs;
-    ma.chunks = chunks;
-    ma.n_chunks = &w.ctrl->n_chunks[par];
-    ma.grab = w.ctrl->grab;
-    ma.chunk_out = chunk_out;
-    ma.U = w.U;
-    ma.counts_next = w.counts + (par ^ 1) * cells;
-    ma.HL = w.HL;
-    ma.hit_count = w.hit_count;
-    ma.evals = &w.ctrl->evals;
-    ma.max_steps = (int)c->max_steps;
-    ma.max_passes = ctx->max_passes;
-    ma.eps = c->eps;
-    ma.spk = spk;
-    ma.out = out;
-    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[2 * r], stream));
-    KN_HIP(ctx, launch_march(ma, s->H, bf ? 1 : 0, march_grid, stream));
-    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[2 * r + 1], stream));
-    ++rounds;
-    // every kReadback rounds, read back how many chunks the round had; stop
-    // once an earlier readback shows an empty round (rounds enqueued after
-    // it find no work and return at once)
-    constexpr int kReadback = 4;
-    if (r % kReadback == kReadback - 1) {
-      const int slot = (r / kReadback) & 3;
-      KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[slot], &w.ctrl->n_chunks[par], 4, hipMemcpyDeviceToHost,
-                                 stream));
-      KN_HIP(ctx, hipEventRecord(ctx->ev_round[slot], stream));
-      if (r >= 2 * kReadback - 1) {
-        const int prev = ((r / kReadback) - 1) & 3;
-        KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[prev]));
-        if (ctx->pinned[prev] == 0) break;
+  if (!pt) {
+    rg.W = (int)c->width;
+    rg.Hh = (int)c->height;
+    rg.slot = 0;
+    rg.rid_base = 0;
+    rg.rs = w.rs;
+    rg.U = w.Uin;
+    rg.counts = w.counts;
+    rg.miss_done = &w.ctrl->miss_done[0];
+    rg.out = q.out;
+    KN_HIP(ctx, launch_raygen(rg, stream));
+    // every round takes at least one SDF evaluation of every live ray
+    const int max_rounds = (int)c->max_steps + 2;
+    for (int r = 0; r < max_rounds; ++r) {
+      if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+      if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+      st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, false, stream, e0, e1);
+      if (st != KN_OK) return st;
+      ++rounds;
+      // every kReadback rounds, read back how many chunks the round had; stop
+      // once an earlier readback shows an empty round (rounds enqueued after
+      // it find no work and return at once)
+      constexpr int kReadback = 4;
+      if (r % kReadback == kReadback - 1) {
+        const int slot = (r / kReadback) & 3;
+        KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[slot], &w.ctrl->n_chunks[r & 1], 4, hipMemcpyDeviceToHost,
+                                   stream));
+        KN_HIP(ctx, hipEventRecord(ctx->ev_round[slot], stream));
+        if (r >= 2 * kReadback - 1) {
+          const int prev = ((r / kReadback) - 1) & 3;
+          KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[prev]));
+          if (ctx->pinned[prev] == 0) break;
+        }
       }
     }
-  }
-
-  // shade the hits, binned by cell
-  {
-    ScanArgs sa{};
-    sa.counts = w.hit_count;
-    sa.C = (uint32_t)cells;
-    sa.T = kShadeChunk;
-    sa.zero_counts = 0;
-    sa.cursor = w.cursor;
-    sa.chunks = w.chunk;
-    sa.n_chunks = &w.ctrl->n_chunks[2];
-    sa.grab = w.ctrl->grab;
-    sa.grab0 = w.ctrl->grab0;
-    sa.zero_word = nullptr;
-    sa.total = &w.ctrl->n_hits;
-    KN_HIP(ctx, launch_scan(sa, stream));
-    ScatterArgs sc{w.HL, w.S, (uint32_t)rays, w.cursor};
-    KN_HIP(ctx, launch_scatter(sc, scatter_grid, stream));
-    ShadeArgs sh{};
-    sh.sg = s->geom;
-    sh.blocks = s->shade;
-    sh.block_words = s->shade_words;
-    sh.S = w.S;
-    sh.rs = w.rs;
-    sh.chunks = w.chunk;
-    sh.n_chunks = &w.ctrl->n_chunks[2];
-    sh.grab = w.ctrl->grab;
-    sh.spk = spk;
-    sh.out = out;
-    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[need_ev - 2], stream));
-    KN_HIP(ctx, launch_shade(sh, s->H, persistent_grid(ctx, 2), stream));
-    if (timed) KN_HIP(ctx, hipEventRecord(ctx->ev_kernel[need_ev - 1], stream));
+    if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+    if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+    st = enqueue_shade(ctx, w, cfg, stream, e0, e1);
+    if (st != KN_OK) return st;
+  } else {
+    RaygenPtArgs rp{};
+    rp.sg = rg.sg;
+    for (int k = 0; k < 3; ++k) {
+      rp.eye[k] = rg.eye[k];
+      rp.fwd[k] = rg.fwd[k];
+      rp.right[k] = rg.right[k];
+      rp.up[k] = rg.up[k];
+    }
+    rp.tx = rg.tx;
+    rp.ty = rg.ty;
+    rp.W = (int)c->width;
+    rp.Hh = (int)c->height;
+    rp.spp = spp;
+    rp.seed_lo = q.seed_lo;
+    rp.seed_hi = q.seed_hi;
+    rp.env = q.env;
+    rp.env_w = q.env_w;
+    rp.env_h = q.env_h;
+    rp.slot = 0;
+    rp.rs = w.rs;
+    rp.U = w.Uin;
+    rp.path = w.path;
+    rp.counts = w.counts;
+    rp.miss_done = &w.ctrl->miss_done[0];
+    rp.out = q.out;
+    KN_HIP(ctx, launch_raygen_pt(rp, stream));
+    // groups of rounds, each followed by a shading pass that scatters the
+    // hits into the next segments; stop when a round marched nothing and the
+    // shading spawned nothing
+    constexpr int kGroup = 4;
+    const int max_groups = (int)((c->bounces + 1) * (c->max_steps + 2)) / kGroup + 4;
+    int r = 0;
+    for (int gi = 0;; ++gi) {
+      if (gi >= max_groups) return fail(KN_E_DEVICE, "path tracing did not finish in %d round groups", gi);
+      for (int k = 0; k < kGroup; ++k, ++r) {
+        if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+        if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+        const bool after_shade = k == 0 && r > 0;
+        st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, after_shade, stream, e0, e1,
+                           after_shade ? &w.ctrl->n_in : nullptr);
+        if (st != KN_OK) return st;
+        ++rounds;
+      }
+      if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+      if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+      st = enqueue_shade(ctx, w, cfg, stream, e0, e1, true, r);
+      if (st != KN_OK) return st;
+      KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[0], &w.ctrl->n_chunks[(r - 1) & 1], 4, hipMemcpyDeviceToHost,
+                                 stream));
+      KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[1], &w.ctrl->n_in, 4, hipMemcpyDeviceToHost, stream));
+      KN_HIP(ctx, hipEventRecord(ctx->ev_round[0], stream));
+      KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[0]));
+      if (ctx->pinned[0] == 0 && ctx->pinned[1] == 0) break;
+    }
+    ResolveArgs ra{w.path, (uint32_t)npix, spp, fr->rgb};
+    KN_HIP(ctx, launch_resolve(ra, stream));
   }
   KN_HIP(ctx, hipEventRecord(ctx->ev_end, stream));
   KN_HIP(ctx, hipEventSynchronize(ctx->ev_end));
@@ -697,15 +930,17 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     stats->march_launches = 0;
     stats->march_ms = stats->shade_ms = 0.0;
     if (timed) {
-      for (int r = 0; r < rounds; ++r) {
+      for (auto& pr : march_ev) {
         float kms = 0.0f;
-        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[2 * r], ctx->ev_kernel[2 * r + 1]));
+        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[pr.first], ctx->ev_kernel[pr.second]));
         stats->march_ms += kms;
       }
-      stats->march_launches = (uint32_t)rounds;
-      float kms = 0.0f;
-      KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[need_ev - 2], ctx->ev_kernel[need_ev - 1]));
-      stats->shade_ms = kms;
+      for (auto& pr : shade_ev) {
+        float kms = 0.0f;
+        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[pr.first], ctx->ev_kernel[pr.second]));
+        stats->shade_ms += kms;
+      }
+      stats->march_launches = (uint32_t)march_ev.size();
     }
   }
   return KN_OK;
@@ -724,7 +959,6 @@ kn_status kn_render(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const 
   st = validate_camera(cam, s);
   if (st != KN_OK) return st;
   if (!frame || !frame->rgb) return fail(KN_E_INVALID, "frame or frame->rgb is NULL");
-  if (cam->env_rgb) return fail(KN_E_UNSUPPORTED, "environment maps are used by path tracing only");
   std::lock_guard<std::mutex> lk(ctx->render_mu);
   KN_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t stream = frame->hip_stream ? (hipStream_t)frame->hip_stream : ctx->stream;
@@ -743,16 +977,16 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   if (n == 0) return KN_OK;
   if (!points) return fail(KN_E_INVALID, "points is NULL");
   if (n > (1ull << 28)) return fail(KN_E_INVALID, "too many points (%llu)", (unsigned long long)n);
-  if (precision != KN_FP32 && precision != KN_BF16)
-    return fail(KN_E_UNSUPPORTED, "precision %d not available", (int)precision);
-  if (precision == KN_BF16 && !s->march_bf16) return fail(KN_E_INVALID, "scene has no bf16 copy");
+  if (precision != KN_FP32 && precision != KN_BF16 && precision != KN_FP8_E4M3)
+    return fail(KN_E_INVALID, "unknown precision %d", (int)precision);
+  if (!s->march(precision)) return fail(KN_E_INVALID, "scene has no copy in precision %d", (int)precision);
   std::lock_guard<std::mutex> lk(ctx->render_mu);
   KN_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
   const size_t cells = (size_t)s->N * s->N * s->N;
-  st = ensure_ws(ctx, n, cells, 16);
+  st = ensure_pool(ctx, ctx->ws, n, cells);
   if (st != KN_OK) return st;
-  Workspace& w = ctx->ws;
+  Pool& w = ctx->ws;
   const SoftplusK spk = softplus_consts(s->geom.beta);
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
   KN_HIP(ctx, hipMemsetAsync(w.counts, 0, cells * 4, stream));
@@ -767,10 +1001,10 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.chunks = w.chunk;
   sa.n_chunks = &w.ctrl->n_chunks[0];
   sa.grab = w.ctrl->grab;
-    sa.grab0 = w.ctrl->grab0;
+  sa.grab0 = w.ctrl->grab0;
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
-  ScatterArgs sc{w.U, w.S, (uint32_t)n, w.cursor};
+  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor};
   KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), stream));
   QueryArgs qa{};
   qa.sg = s->geom;
@@ -781,11 +1015,10 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   qa.grab = w.ctrl->grab;
   qa.spk = spk;
   if (d_out) {
-    const bool bf = precision == KN_BF16;
-    qa.blocks = bf ? s->march_bf16 : s->march_f32;
-    qa.block_words = bf ? s->march_bf16_words : s->march_f32_words;
+    qa.blocks = s->march(precision);
+    qa.block_words = s->march_words(precision);
     qa.d_out = d_out;
-    KN_HIP(ctx, launch_query_d(qa, s->H, bf ? 1 : 0, persistent_grid(ctx, 2), stream));
+    KN_HIP(ctx, launch_query_d(qa, s->H, (int)precision, persistent_grid(ctx, 2), stream));
   }
   if (grad_out || z_out) {
     KN_HIP(ctx, hipMemcpyAsync(w.ctrl->grab, w.ctrl->grab0, sizeof(w.ctrl->grab), hipMemcpyDeviceToDevice,
@@ -804,32 +1037,455 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// serving (continuous batching) -- not built yet
+// serving: continuous batching of render requests in one shared ray pool
 // ---------------------------------------------------------------------------
 namespace kn {
-class ServeLoop {};
+
+struct Request {
+  enum State { kQueued, kRunning, kDone, kFailed };
+  kn_request_id id = 0;
+  KnScene* scene = nullptr;
+  kn_camera cam{};
+  OutPtrs out{};
+  uint32_t npix = 0;
+  int slot = -1;
+  size_t base = 0;          // first pool ray id
+  int64_t admit_group = -1; // round group whose rays started it
+  State state = kQueued;
+  uint32_t hits = 0;
+  uint64_t rounds = 0;
+  std::chrono::steady_clock::time_point t_submit, t_admit, t_done;
+};
+
+// The loop thread owns the pool, its stream and the tables.  Between groups
+// of kGroupRounds rounds it admits queued requests in arrival order while a
+// request slot and a contiguous range of pool ray ids are free (the pool is
+// the HBM budget of ray state), generates their rays into the next round,
+// runs the rounds and a shading pass over the pool, and retires requests
+// whose rays have all finished (per-slot miss and hit counters, read back
+// one group late so the host never waits on the group in flight).
+class ServeLoop {
+ public:
+  static constexpr int kGroupRounds = 4;
+
+  ServeLoop(kn_ctx* c, uint32_t mi, kn_precision p) : ctx(c), max_inflight(mi), prec(p) {}
+  kn_precision precision() const { return prec; }
+
+  kn_status start(size_t cap, size_t cell_cap) {
+    KN_HIP(ctx, hipSetDevice(ctx->device));
+    kn_status st = ensure_pool(ctx, pool, cap, cell_cap);
+    if (st != KN_OK) return st;
+    this->cell_cap = cell_cap;
+    KN_HIP(ctx, hipStreamCreateWithFlags(&stream, hipStreamNonBlocking));
+    for (auto& e : ev) KN_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    KN_HIP(ctx, hipHostMalloc((void**)&head, 4 * (size_t)kCtrlHead, hipHostMallocDefault));
+    KN_HIP(ctx, hipHostMalloc((void**)&h_scenes, kMaxScenes * sizeof(SceneEnt), hipHostMallocDefault));
+    KN_HIP(ctx, hipHostMalloc((void**)&h_reqs, kMaxSlots * sizeof(ReqEnt), hipHostMallocDefault));
+    KN_HIP(ctx, hipMemsetAsync(pool.ctrl, 0, sizeof(Ctrl), stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.counts, 0, 2 * pool.cells * 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.hit_count, 0, pool.cells * 4, stream));
+    KN_HIP(ctx, hipStreamSynchronize(stream));
+    free_ranges[0] = pool.cap;
+    th = std::thread([this] { run(); });
+    return KN_OK;
+  }
+
+  // drains every submitted request, then stops the thread and frees the pool
+  void stop() {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      stopping = true;
+    }
+    cv_work.notify_all();
+    if (th.joinable()) th.join();
+    (void)hipSetDevice(ctx->device);
+    if (stream) (void)hipStreamSynchronize(stream);
+    ctx->used -= pool.bytes;
+    free_pool(pool);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (stream) (void)hipStreamDestroy(stream);
+    if (head) (void)hipHostFree(head);
+    if (h_scenes) (void)hipHostFree(h_scenes);
+    if (h_reqs) (void)hipHostFree(h_reqs);
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& kv : reqs)
+      if (kv.second->state == Request::kQueued || kv.second->state == Request::kRunning) {
+        kv.second->state = Request::kFailed;
+        kv.second->scene->refs--;
+      }
+    cv_done.notify_all();
+  }
+
+  kn_status submit(KnScene* s, const kn_camera* cam, const kn_frame* fr, kn_request_id* out) {
+    const uint32_t npix = cam->width * cam->height;
+    if (npix > pool.cap)
+      return fail(KN_E_NOMEM, "request of %u rays exceeds the serving pool (%zu rays)", npix, pool.cap);
+    std::unique_ptr<Request> q(new Request());
+    q->scene = s;
+    q->cam = *cam;
+    q->out = out_ptrs(fr);
+    q->npix = npix;
+    q->t_submit = std::chrono::steady_clock::now();
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      if (stopping || failed) return fail(KN_E_SHUTDOWN, "serving loop is stopping");
+      q->id = next_id++;
+      *out = q->id;
+      queue.push_back(q.get());
+      reqs[q->id] = std::move(q);
+    }
+    cv_work.notify_all();
+    return KN_OK;
+  }
+
+  kn_status poll(kn_request_id id, int64_t timeout_us, kn_stats* stats) {
+    std::unique_lock<std::mutex> lk(mu);
+    auto it = reqs.find(id);
+    if (it == reqs.end()) return fail(KN_E_NOT_FOUND, "request %llu not found", (unsigned long long)id);
+    Request* q = it->second.get();
+    auto finished = [q] { return q->state == Request::kDone || q->state == Request::kFailed; };
+    if (!finished()) {
+      if (timeout_us == 0) return KN_PENDING;
+      if (timeout_us < 0) cv_done.wait(lk, finished);
+      else if (!cv_done.wait_for(lk, std::chrono::microseconds(timeout_us), finished))
+        return fail(KN_E_TIMEOUT, "request %llu not finished", (unsigned long long)id);
+    }
+    if (q->state == Request::kFailed) {
+      reqs.erase(it);
+      return fail(KN_E_DEVICE, "request failed: %s", fail_msg.empty() ? "serving stopped" : fail_msg.c_str());
+    }
+    if (stats) {
+      const uint32_t keep = stats->kernel_times;
+      *stats = kn_stats{};
+      stats->kernel_times = keep;
+      stats->wall_ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_submit).count();
+      stats->gpu_ms = std::chrono::duration<double, std::milli>(q->t_done - q->t_admit).count();
+      stats->rays = q->npix;
+      stats->hits = q->hits;
+      stats->rounds = q->rounds;
+    }
+    reqs.erase(it);
+    return KN_OK;
+  }
+
+ private:
+  struct TabEnt {
+    kn_scene_id id;
+    uint32_t base, cells, march_words, shade_words;
+    int H;
+  };
+
+  kn_ctx* ctx;
+  uint32_t max_inflight;
+  kn_precision prec;
+  Pool pool;
+  size_t cell_cap = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  uint8_t* head = nullptr;       // pinned readback of the Ctrl head, one slot per group (mod 4)
+  SceneEnt* h_scenes = nullptr;  // pinned staging of the tables
+  ReqEnt* h_reqs = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request*> queue;
+  std::map<kn_request_id, std::unique_ptr<Request>> reqs;
+  Request* slots[kMaxSlots] = {};
+  uint32_t inflight = 0;
+  std::map<size_t, size_t> free_ranges;  // begin -> end of free pool ray ids
+  kn_request_id next_id = 1;
+  bool stopping = false, failed = false;
+  std::string fail_msg;
+  std::vector<TabEnt> table;     // loop thread only
+  uint32_t cells_used = 0;       // loop thread only
+
+  bool alloc_range(size_t n, size_t* base) {
+    for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+      if (it->second - it->first >= n) {
+        *base = it->first;
+        const size_t end = it->second;
+        free_ranges.erase(it);
+        if (*base + n < end) free_ranges[*base + n] = end;
+        return true;
+      }
+    }
+    return false;
+  }
+
+  void free_range(size_t base, size_t n) {
+    size_t b = base, e = base + n;
+    auto it = free_ranges.lower_bound(b);
+    if (it != free_ranges.end() && it->first == e) {
+      e = it->second;
+      it = free_ranges.erase(it);
+    }
+    if (it != free_ranges.begin()) {
+      auto pv = std::prev(it);
+      if (pv->second == b) {
+        b = pv->first;
+        free_ranges.erase(pv);
+      }
+    }
+    free_ranges[b] = e;
+  }
+
+  // table index of a scene, adding it (and uploading its entry) if needed;
+  // -1 when the table is full
+  int table_index(KnScene* s) {
+    for (size_t k = 0; k < table.size(); ++k)
+      if (table[k].id == s->id) return (int)k;
+    const uint32_t cells = (uint32_t)(s->N * s->N * s->N);
+    if (table.size() >= (size_t)kMaxScenes || (size_t)cells_used + cells > cell_cap) return -1;
+    const int k = (int)table.size();
+    h_scenes[k] = scene_entry(s, (int)prec, cells_used);
+    if (hipMemcpyAsync(pool.scenes + k, h_scenes + k, sizeof(SceneEnt), hipMemcpyHostToDevice, stream) !=
+        hipSuccess)
+      return -2;
+    table.push_back(TabEnt{s->id, cells_used, cells, h_scenes[k].march_words, s->shade_words, s->H});
+    cells_used += cells;
+    return k;
+  }
+
+  RoundCfg round_cfg() const {
+    RoundCfg c{};
+    c.hmode = table.empty() ? 32 : table[0].H;
+    for (const TabEnt& e : table) {
+      if (e.H != c.hmode) c.hmode = 0;
+      c.march_words = std::max(c.march_words, e.march_words);
+      c.shade_words = std::max(c.shade_words, e.shade_words);
+    }
+    c.prec = (int)prec;
+    c.n_scenes = (uint32_t)table.size();
+    c.cells = cells_used;
+    c.max_passes = ctx->max_passes;
+    return c;
+  }
+
+  // admits requests in arrival order; returns them (caller enqueues their rays)
+  std::vector<Request*> admit(int64_t group) {
+    std::vector<Request*> adm;
+    while (!queue.empty() && inflight < max_inflight) {
+      Request* q = queue.front();
+      int slot = -1;
+      for (int i = 0; i < kMaxSlots; ++i)
+        if (!slots[i]) {
+          slot = i;
+          break;
+        }
+      if (slot < 0) break;
+      size_t base = 0;
+      if (!alloc_range(q->npix, &base)) break;
+      int k = table_index(q->scene);
+      if (k == -1 && inflight == 0 && adm.empty()) {
+        // idle pool with a full scene table: start a fresh table
+        (void)hipStreamSynchronize(stream);
+        table.clear();
+        cells_used = 0;
+        k = table_index(q->scene);
+      }
+      if (k < 0) {
+        free_range(base, q->npix);
+        break;
+      }
+      q->slot = slot;
+      q->base = base;
+      q->admit_group = group;
+      q->state = Request::kRunning;
+      q->t_admit = std::chrono::steady_clock::now();
+      slots[slot] = q;
+      ++inflight;
+      queue.pop_front();
+      adm.push_back(q);
+    }
+    return adm;
+  }
+
+  // enqueues the rays of an admitted request into Uin at offset *n_new
+  kn_status start_request(Request* q, int r, uint32_t* n_new) {
+    const int k = table_index(q->scene);
+    if (k < 0) return fail(KN_E_DEVICE, "scene table lookup failed");
+    h_reqs[q->slot] = ReqEnt{q->out, q->cam.eps, q->cam.max_steps, q->npix, 0u};
+    KN_HIP(ctx, hipMemcpyAsync(pool.reqs + q->slot, h_reqs + q->slot, sizeof(ReqEnt), hipMemcpyHostToDevice,
+                               stream));
+    KN_HIP(ctx, hipMemsetAsync(&pool.ctrl->miss_done[q->slot], 0, 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(&pool.ctrl->hit_done[q->slot], 0, 4, stream));
+    RaygenArgs rg{};
+    rg.sg = h_scenes[k].sg;
+    camera_basis(&q->cam, rg);
+    rg.W = (int)q->cam.width;
+    rg.Hh = (int)q->cam.height;
+    rg.slot = (uint32_t)q->slot;
+    rg.rid_base = (uint32_t)q->base;
+    rg.rs = pool.rs;
+    rg.U = pool.Uin + *n_new;
+    rg.counts = pool.counts + (r & 1) * pool.cells;
+    rg.miss_done = &pool.ctrl->miss_done[0];
+    rg.out = q->out;
+    KN_HIP(ctx, launch_raygen(rg, stream));
+    *n_new += q->npix;
+    return KN_OK;
+  }
+
+  // retires the requests that group `g`'s readback shows finished
+  void retire(int64_t g) {
+    const Ctrl* h = reinterpret_cast<const Ctrl*>(head + (size_t)(g & 3) * kCtrlHead);
+    const auto now = std::chrono::steady_clock::now();
+    bool any = false;
+    std::lock_guard<std::mutex> lk(mu);
+    for (int i = 0; i < kMaxSlots; ++i) {
+      Request* q = slots[i];
+      if (!q || q->admit_group > g) continue;
+      if ((uint64_t)h->miss_done[i] + h->hit_done[i] >= q->npix) {
+        q->hits = h->hit_done[i];
+        q->rounds = (uint64_t)(g - q->admit_group + 1) * kGroupRounds;
+        q->t_done = now;
+        q->state = Request::kDone;
+        slots[i] = nullptr;
+        free_range(q->base, q->npix);
+        --inflight;
+        q->scene->refs--;
+        any = true;
+      }
+    }
+    if (any) cv_done.notify_all();
+  }
+
+  kn_status loop() {
+    KN_HIP(ctx, hipSetDevice(ctx->device));
+    int r = 0;
+    int64_t group = 0;
+    bool shaded = false;
+    for (;;) {
+      std::vector<Request*> adm;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv_work.wait(lk, [this] { return stopping || !queue.empty() || inflight > 0; });
+        if (stopping && queue.empty() && inflight == 0) break;
+        adm = admit(group);
+      }
+      uint32_t n_new = 0;
+      for (Request* q : adm) {
+        kn_status st = start_request(q, r, &n_new);
+        if (st != KN_OK) return st;
+      }
+      const RoundCfg cfg = round_cfg();
+      for (int k = 0; k < kGroupRounds; ++k, ++r) {
+        kn_status st = enqueue_round(ctx, pool, cfg, r, k == 0 ? n_new : 0u, k == 0 && shaded, stream,
+                                     nullptr, nullptr);
+        if (st != KN_OK) return st;
+      }
+      kn_status st = enqueue_shade(ctx, pool, cfg, stream, nullptr, nullptr);
+      if (st != KN_OK) return st;
+      shaded = true;
+      KN_HIP(ctx, hipMemcpyAsync(head + (size_t)(group & 3) * kCtrlHead, pool.ctrl, kCtrlHead,
+                                 hipMemcpyDeviceToHost, stream));
+      KN_HIP(ctx, hipEventRecord(ev[group & 3], stream));
+      if (group > 0) {
+        KN_HIP(ctx, hipEventSynchronize(ev[(group - 1) & 3]));
+        retire(group - 1);
+      }
+      ++group;
+    }
+    return KN_OK;
+  }
+
+  void run() {
+    const kn_status st = loop();
+    if (st != KN_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      failed = true;
+      fail_msg = kn_last_error();
+      for (auto& kv : reqs)
+        if (kv.second->state == Request::kQueued || kv.second->state == Request::kRunning) {
+          kv.second->state = Request::kFailed;
+          kv.second->scene->refs--;
+        }
+      for (auto& q : slots) q = nullptr;
+      queue.clear();
+      inflight = 0;
+      cv_done.notify_all();
+    }
+  }
+};
+
 }  // namespace kn
 
 extern "C" {
 
-kn_status kn_serve_start(kn_ctx* ctx, uint32_t, kn_precision) {
+kn_status kn_serve_start(kn_ctx* ctx, uint32_t max_inflight, kn_precision precision) {
   kn_status st = check_ctx(ctx);
   if (st != KN_OK) return st;
-  return fail(KN_E_UNSUPPORTED, "serving loop not built yet");
+  if (max_inflight < 1 || max_inflight > (uint32_t)kMaxSlots)
+    return fail(KN_E_INVALID, "max_inflight %u not in 1..%d", max_inflight, kMaxSlots);
+  if (precision != KN_FP32 && precision != KN_BF16 && precision != KN_FP8_E4M3)
+    return fail(KN_E_INVALID, "unknown precision %d", (int)precision);
+  std::lock_guard<std::mutex> lk(ctx->serve_mu);
+  if (ctx->serve) return fail(KN_E_BUSY, "serving loop already running");
+  // ray state: what the budget leaves, at most 32 M rays
+  const uint64_t used = ctx->used.load();
+  const uint64_t avail = ctx->budget > used ? ctx->budget - used : 0;
+  const size_t cell_cap = (size_t)1 << 18;
+  const size_t fixed = pool_bytes(0, cell_cap, cell_cap);
+  if (avail < fixed + ((size_t)1 << 20) * (kRayBytes + 2))
+    return fail(KN_E_NOMEM, "HBM budget leaves no room for a serving pool");
+  const size_t cap = std::min<size_t>((avail - fixed) / (kRayBytes + 2), (size_t)32 << 20);
+  std::shared_ptr<kn::ServeLoop> loop(new kn::ServeLoop(ctx, max_inflight, precision));
+  st = loop->start(cap, cell_cap);
+  if (st != KN_OK) {
+    loop->stop();
+    return st;
+  }
+  ctx->serve = std::move(loop);
+  return KN_OK;
 }
-kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id, const kn_camera*, const kn_frame*, kn_request_id*) {
+
+kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const kn_frame* frame,
+                          kn_request_id* out) {
   kn_status st = check_ctx(ctx);
   if (st != KN_OK) return st;
-  return fail(KN_E_SHUTDOWN, "serving loop not running");
+  if (!out) return fail(KN_E_INVALID, "out is NULL");
+  if (!frame || !frame->rgb) return fail(KN_E_INVALID, "frame or frame->rgb is NULL");
+  std::lock_guard<std::mutex> sk(ctx->serve_mu);
+  if (!ctx->serve) return fail(KN_E_SHUTDOWN, "serving loop not running");
+  KnScene* s;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->scenes.find(scene);
+    if (it == ctx->scenes.end()) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
+    s = it->second;
+    st = validate_camera(cam, s);
+    if (st != KN_OK) return st;
+    if (cam->bounces != 0) return fail(KN_E_UNSUPPORTED, "the serving loop renders primary rays (bounces 0)");
+    if (cam->precision != ctx->serve->precision())
+      return fail(KN_E_INVALID, "camera precision %d differs from the serving loop's %d", (int)cam->precision,
+                  (int)ctx->serve->precision());
+    s->refs++;
+  }
+  st = ctx->serve->submit(s, cam, frame, out);
+  if (st != KN_OK) s->refs--;
+  return st;
 }
-kn_status kn_serve_poll(kn_ctx* ctx, kn_request_id, int64_t, kn_stats*) {
-  kn_status st = check_ctx(ctx);
-  if (st != KN_OK) return st;
-  return fail(KN_E_SHUTDOWN, "serving loop not running");
+
+kn_status kn_serve_poll(kn_ctx* ctx, kn_request_id req, int64_t timeout_us, kn_stats* stats_opt) {
+  if (!ctx) return fail(KN_E_INVALID, "ctx is NULL");
+  std::shared_ptr<kn::ServeLoop> loop;
+  {
+    std::lock_guard<std::mutex> sk(ctx->serve_mu);
+    if (!ctx->serve) return fail(KN_E_SHUTDOWN, "serving loop not running");
+    loop = ctx->serve;
+  }
+  return loop->poll(req, timeout_us, stats_opt);
 }
+
 kn_status kn_serve_stop(kn_ctx* ctx) {
   if (!ctx) return fail(KN_E_INVALID, "ctx is NULL");
-  ctx->serve.reset();
+  std::shared_ptr<kn::ServeLoop> loop;
+  {
+    std::lock_guard<std::mutex> sk(ctx->serve_mu);
+    loop = std::move(ctx->serve);
+  }
+  if (loop) loop->stop();
   return KN_OK;
 }
 

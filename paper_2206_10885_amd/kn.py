@@ -198,6 +198,28 @@ class Context:
         out["stats"] = self.render_into(sid, cam, out)
         return out
 
+    # -- serving ------------------------------------------------------------
+    def serve_start(self, max_inflight: int = 16, precision: str = "bf16"):
+        check(lib().kn_serve_start(self.h, max_inflight, PRECISIONS[precision]))
+
+    def serve_submit(self, sid: int, cam: Camera, out: dict) -> int:
+        """Queues a frame; `out` (from alloc_frame) must stay alive until
+        serve_poll reports it finished."""
+        fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
+                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")), None)
+        rid = C.c_uint64()
+        check(lib().kn_serve_submit(self.h, sid, C.byref(cam), C.byref(fr), C.byref(rid)))
+        return rid.value
+
+    def serve_poll(self, req: int, timeout_us: int = -1):
+        """Stats of a finished request, or None while it is still pending."""
+        st = Stats()
+        r = check(lib().kn_serve_poll(self.h, req, timeout_us, C.byref(st)))
+        return None if r == KN_PENDING else st.as_dict()
+
+    def serve_stop(self):
+        check(lib().kn_serve_stop(self.h))
+
     def query(self, sid: int, points, precision: str = "fp32", grad: bool = False,
               feat: bool = False, stream=None) -> dict:
         import torch

@@ -101,6 +101,27 @@ def test_query_bf16_matches_emulation(ctx):
     ctx.scene_destroy(sid)
 
 
+@pytest.mark.parametrize("H", [32, 64])
+def test_query_fp8_matches_emulation(ctx, H):
+    """fp8 e4m3 march MLP (per-(cell, layer) power-of-two scales) against its
+    float32 CPU emulation."""
+    from oracle import quant
+    sc = synth.sphere_scene(8, H, 0.6, 0.02, seed=70 + H)
+    sid = ctx.scene_create(sc, precisions=("fp8",))
+    pts = _query_points(sc, 4000, seed=4)
+    d = ctx.query(sid, torch.tensor(pts, device="cuda"), "fp8")["d"].cpu().numpy()
+    ref = quant.sdf_fp8(sc, pts)
+    err = np.abs(d - ref)
+    full = quant.sdf_fp8(sc, pts, quantize=False)
+    log(f"fp8 query H={H}: median {np.median(err):.2e} p99.9 {np.percentile(err, 99.9):.2e} "
+        f"max {err.max():.2e}; fp8 vs fp32 median {np.median(np.abs(ref - full)):.2e}")
+    # an e4m3 ulp is 2^-3 relative; float32 sums in another order flip a
+    # rounding of a layer-2 input on a few points
+    assert np.median(err) < 1e-5
+    assert np.percentile(err, 99) < 1e-3
+    ctx.scene_destroy(sid)
+
+
 def _render(ctx, sid, view, W, H, S, eps=1e-4, precision="fp32"):
     return ctx.render(sid, view, W, H, S, eps, precision, with_trace=True)
 
@@ -196,18 +217,28 @@ def test_render_full_size_sampled(ctx, cfg, views, samples):
     ctx.scene_destroy(sid)
 
 
-def test_render_bf16_vs_fp32_report(ctx):
-    """BF16 march (FP32 refinement and shading) against the FP32 path on the
-    same inputs: reported; the masks must largely agree."""
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_render_lowp_vs_fp32_report(ctx, precision):
+    """BF16 or FP8 march (FP32 refinement and shading) against the FP32 path
+    on the same inputs, and the FP64 oracle on sampled pixels: reported; the
+    masks must largely agree."""
     sc = synth.sphere_scene(16, 64, 0.6, 0.02, seed=3000)
-    sid = ctx.scene_create(sc, precisions=("bf16",))
+    sid = ctx.scene_create(sc, precisions=(precision,))
     view = synth.config_views("c3")[0]
     a = P.gpu_arrays(_render(ctx, sid, view, 480, 270, 128))
-    b = P.gpu_arrays(_render(ctx, sid, view, 480, 270, 128, precision="bf16"))
+    out = _render(ctx, sid, view, 480, 270, 128, precision=precision)
+    b = P.gpu_arrays(out)
     agree = float(np.mean(a["hit"] == b["hit"]))
     both = (a["hit"] == 1) & (b["hit"] == 1)
     dd = np.abs(a["depth"] - b["depth"])[both]
-    log(f"bf16 vs fp32: mask agreement {agree:.4f}, depth p50 {np.median(dd):.2e} p99 {np.percentile(dd, 99):.2e}")
+    an = P.angle_deg(a["normal"][both], b["normal"][both])
+    dc = np.abs(a["rgb"] - b["rgb"]).max(axis=1)
+    log(f"{precision} vs fp32: mask agreement {agree:.4f}, depth p50 {np.median(dd):.2e} "
+        f"p99 {np.percentile(dd, 99):.2e} max {dd.max():.2e}; normal p50 {np.median(an):.2e} "
+        f"p99 {np.percentile(an, 99):.2e} deg; rgb p50 {np.median(dc):.2e} p99 {np.percentile(dc, 99):.2e}")
+    pix = synth.sample_pixels(480, 270, 1500, seed=9)
+    rep = P.compare(sc, view, 480, 270, 128, 1e-4, P.gpu_arrays(out, pix), pixels=pix)
+    log(f"{precision} vs FP64 oracle (1500 pixels):", rep.as_dict())
     assert agree > 0.95
     ctx.scene_destroy(sid)
 
