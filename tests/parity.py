@@ -165,7 +165,7 @@ def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None) -> Report:
     sb = stable & both
 
     os_ = O.OracleScene.from_scene(scene)
-    pert = [O.OracleScene.from_scene(perturbed(scene, 1e-6, 300 + k)) for k in range(3)]
+    pert = [O.OracleScene.from_scene(perturbed(scene, 1e-6, 300 + k)) for k in range(6)]
     rng = np.random.default_rng(400)
     pix = np.arange(W * H) if pixels is None else np.asarray(pixels)
     N = scene.N
