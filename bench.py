@@ -154,9 +154,11 @@ def serve_bench(n_req: int, torch) -> dict:
     scenes = [synth.sphere_scene(Ns[k], 32 if k % 2 == 0 else 64, 0.5 + 0.02 * k, 0.02, 4000 + k)
               for k in range(8)]
     sizes = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+    print("serving: scenes generated", file=sys.stderr, flush=True)
     ctx = kn.Context(0, hbm_budget_bytes=(sum(sc.sdf.nbytes for sc in scenes) * 3) + (16 << 30))
     sids = [ctx.scene_create(sc, precisions=("bf16",)) for sc in scenes]
     del scenes
+    print("serving: scenes resident", file=sys.stderr, flush=True)
     warm = 200
     total = warm + n_req
     rng = np.random.default_rng(4004)
@@ -190,6 +192,8 @@ def serve_bench(n_req: int, torch) -> dict:
     for i in range(total):
         submitted.acquire()
         st = ctx.serve_poll(ids[i], timeout_us=120_000_000)
+        if i % 500 == 499:
+            print(f"serving: {i + 1} requests done", file=sys.stderr, flush=True)
         if i >= warm:
             lat.append(st["wall_ms"])
             rays += st["rays"]
@@ -218,6 +222,7 @@ def pathtrace_bench(torch, frames: int = 3) -> dict:
     ctx = kn.Context(0)
     sid = ctx.scene_create(sc, precisions=("bf16", "fp8"))
     del sc
+    print("pathtrace: scene resident", file=sys.stderr, flush=True)
     out = ctx.alloc_frame(W, H)
     res = {}
     for prec in ("fp8", "bf16"):
@@ -235,6 +240,7 @@ def pathtrace_bench(torch, frames: int = 3) -> dict:
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         paths = W * H * c["spp"] * frames
+        print(f"pathtrace: {prec} done", file=sys.stderr, flush=True)
         res[prec] = dict(paths_per_s=paths / dt, frame_ms_p50=pct(ms, 50), evals_per_path=evals / paths,
                          hit_segments_per_path=hits / paths, segments_per_s=(hits + paths) / dt)
     ctx.close()

@@ -141,6 +141,30 @@ __device__ __forceinline__ void pe_values_tangent(const PeLane& L, int s, float 
   }
 }
 
+// Encoding values of a value column (value == true) or of the derivative
+// along a direction whose local-coordinate rates are (tx, ty, tz) per axis.
+__device__ __forceinline__ void pe_values_dir(const PeLane& L, bool value, float tx, float ty, float tz,
+                                              float x, float y, float z, float (&v)[kPeSlots]) {
+#pragma unroll
+  for (int j = 0; j < kPeSlots; ++j) {
+    uint32_t ax = (L.axes >> (2 * j)) & 3u;
+    float xa = pick(ax, x, y, z);
+    float r = xa * L.scale[j];
+    float sn = sin_rev(r), cs = cos_rev(r);
+    bool raw = (j == 0 && L.g < 3);
+    bool pad = (j == 9 && L.g == 3);
+    bool is_sin = (j == 0 && L.g == 3) || (j >= 1 && j <= 4) || (j == 9 && L.g == 0);
+    float val;
+    if (value) {
+      val = raw ? xa : (pad ? 0.0f : (is_sin ? sn : cs));
+    } else {
+      float dv = raw ? 1.0f : (pad ? 0.0f : (is_sin ? cs * L.dscale[j] : -sn * L.dscale[j]));
+      val = pad ? 0.0f : dv * pick(ax, tx, ty, tz);
+    }
+    v[j] = val;
+  }
+}
+
 // LDS visibility between lanes of one wave (no workgroup barrier).
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -159,6 +183,20 @@ __device__ __forceinline__ float quad_bcast(float v) {
   constexpr int ctrl = SRC | (SRC << 2) | (SRC << 4) | (SRC << 6);
   return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF,
                                                             0xF, false));
+}
+
+// value of the even lane of each lane pair
+__device__ __forceinline__ float pair_bcast(float v) {
+  constexpr int ctrl = 0 | (0 << 2) | (2 << 4) | (2 << 6);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF,
+                                                            0xF, false));
+}
+
+// forward-mode groups: C columns per point, the value column first
+template <int C>
+__device__ __forceinline__ float group_bcast(float v) {
+  if constexpr (C == 4) return quad_bcast<0>(v);
+  else return pair_bcast(v);
 }
 
 // ---------------------------------------------------------------------------

@@ -1095,7 +1095,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
 // world-axis tangents, forward mode): returns the output rows 4g..4g+3 of
 // this lane's column.  Weights are read from the LDS block as MFMA fragments.
 // ---------------------------------------------------------------------------
-template <int H>
+template <int H, int C = 4>
 __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, bool value_col,
                                           const float (&v)[kPeSlots], SoftplusK k) {
   constexpr int NB = H / 16, S1 = NB * kPeSlots, S2 = S1 + NB * (H / 4);
@@ -1115,7 +1115,7 @@ __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, boo
     for (int r = 0; r < 4; ++r) {
       float ds;
       const float sp = softplus_d(acc[b][r], k, &ds);
-      const float dv = quad_bcast<0>(ds);
+      const float dv = group_bcast<C>(ds);
       a1[b][r] = value_col ? sp : dv * acc[b][r];
     }
   f32x4 acc2[NB];
@@ -1134,7 +1134,7 @@ __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, boo
     for (int r = 0; r < 4; ++r) {
       float ds;
       const float sp = softplus_d(acc2[b][r], k, &ds);
-      const float dv = quad_bcast<0>(ds);
+      const float dv = group_bcast<C>(ds);
       a2[b][r] = value_col ? sp : dv * acc2[b][r];
     }
   f32x4 y = value_col ? *reinterpret_cast<const f32x4*>(vec + 2 * H + 4 * g) : f32x4{0, 0, 0, 0};
@@ -1160,14 +1160,14 @@ __device__ __forceinline__ float color_in_slot(int e, const float xl[3], const f
 // ---------------------------------------------------------------------------
 // shading: per chunk of a cell's hits; each wave shades 4 hits per tile
 // ---------------------------------------------------------------------------
-template <int HM>
+template <int HM, int C = 4>
 __device__ __forceinline__ f32x4 sdf_full_h(int H, const float* blk, int lane, int g, bool value_col,
                                             const float (&v)[kPeSlots], SoftplusK k) {
   if constexpr (HM != 0) {
-    return sdf_full<HM>(blk, lane, g, value_col, v, k);
+    return sdf_full<HM, C>(blk, lane, g, value_col, v, k);
   } else {
-    if (H == 64) return sdf_full<64>(blk, lane, g, value_col, v, k);
-    return sdf_full<32>(blk, lane, g, value_col, v, k);
+    if (H == 64) return sdf_full<64, C>(blk, lane, g, value_col, v, k);
+    return sdf_full<32, C>(blk, lane, g, value_col, v, k);
   }
 }
 
@@ -1207,21 +1207,48 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     const int SC1 = (H / 16) * kPeSlots + (H / 16) * (H / 4) + H / 4;  // first color fragment slot
     const CellBox cb = cell_box(sg, lc);
     float* stage = s_stage + wave * 4 * kColIn;
-    for (uint32_t base = (uint32_t)wave * 4u; base < count; base += 16u) {
-      const uint32_t idx = base + (uint32_t)h;
+    // each wave takes 8 hits: two 2-column passes (value and derivative
+    // along the ray) give the two Newton steps of all 8, then a 4-column pass
+    // per 4 hits (value and world gradient) at the refined point gives the
+    // normal, the feature and the color
+    const int hA = col >> 1, sA = col & 1;
+    for (uint32_t base = (uint32_t)wave * 8u; base < count; base += 32u) {
+      float tA;
+      {
+        const uint32_t idx = base + (uint32_t)hA;
+        const bool valid = idx < count;
+        const RayRec r = valid ? a.S[start + idx] : RayRec{0, 0, cell, 0};
+        const RayStatic st = valid ? a.rs[r.rid] : RayStatic{0, 0, 0, 0, 0, 0, 1, 0};
+        const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
+        int eax;
+        const float ce = cell_exit(sg, cb, o, d, &eax);
+        tA = r.t;
+#pragma unroll 1
+        for (int it = 0; it < 2; ++it) {
+          asm volatile("" ::: "memory");
+          float xl[3];
+#pragma unroll
+          for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(fmaf(tA, d[k], o[k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
+          float v[kPeSlots];
+          pe_values_dir(pl, sA == 0, d[0] * sg.inv_half[0], d[1] * sg.inv_half[1], d[2] * sg.inv_half[2],
+                        xl[0], xl[1], xl[2], v);
+          const f32x4 y = sdf_full_h<HM, 2>(H, s_block, lane, g, sA == 0, v, spk);
+          const float f0 = __shfl(y[0], 2 * hA), gd = __shfl(y[0], 2 * hA + 1);
+          if (gd < -1e-3f) tA = fminf(fmaxf(tA - f0 / gd, r.t_entry), ce);
+        }
+      }
+#pragma unroll 1
+      for (int half = 0; half < 2; ++half) {
+      const uint32_t hh = 4u * (uint32_t)half + (uint32_t)h;   // hit of this half
+      const uint32_t idx = base + hh;
       const bool valid = idx < count;
+      const float t = __shfl(tA, 2 * (int)hh);
       RayRec r = valid ? a.S[start + idx] : RayRec{0, 0, cell, 0};
       const RayStatic st = valid ? a.rs[r.rid] : RayStatic{0, 0, 0, 0, 0, 0, 1, 0};
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
-      int eax;
-      const float ce = cell_exit(sg, cb, o, d, &eax);
-      float t = r.t;
-      float xl[3], gr[3], fval = 0.0f;
+      float xl[3], gr[3];
       f32x4 y;
-#pragma unroll 1
-      for (int it = 0; it < 3; ++it) {
-        // weights stay in LDS: reload fragments each evaluation instead of
-        // keeping ~150 of them live in registers across the Newton steps
+      {
         asm volatile("" ::: "memory");
 #pragma unroll
         for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(fmaf(t, d[k], o[k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
@@ -1230,14 +1257,9 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         pe_values_tangent(pl, s, ih, xl[0], xl[1], xl[2], v);
         y = sdf_full_h<HM>(H, s_block, lane, g, value_col, v, spk);
         const int src = 4 * h;
-        fval = __shfl(y[0], src);
         gr[0] = __shfl(y[0], src + 1);
         gr[1] = __shfl(y[0], src + 2);
         gr[2] = __shfl(y[0], src + 3);
-        if (it < 2) {
-          const float gd = gr[0] * d[0] + gr[1] * d[1] + gr[2] * d[2];
-          if (gd < -1e-3f) t = fminf(fmaxf(t - fval / gd, r.t_entry), ce);
-        }
       }
       const float gn2 = gr[0] * gr[0] + gr[1] * gr[1] + gr[2] * gr[2];
       float n[3];
@@ -1342,6 +1364,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         if (spawn) a.spawn[pos] = nrec;
       }
       atomic_count_grouped(a.tabs.hit_done, slot, done);
+      }
     }
     __syncthreads();
   }
