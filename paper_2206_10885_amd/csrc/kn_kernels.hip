@@ -55,6 +55,18 @@ __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t 
   return pos;
 }
 
+// Adds the workgroup's count of `flag` to *counter with one global atomic
+// (a single hot address must not take one atomic per wave).  Called by
+// every thread of the workgroup.
+__device__ __forceinline__ void wg_count(uint32_t* counter, bool flag, uint32_t* s_tmp) {
+  if (threadIdx.x == 0) *s_tmp = 0u;
+  __syncthreads();
+  const uint64_t m = __ballot(flag);
+  if (lane_id() == 0 && m) atomicAdd(s_tmp, (uint32_t)__popcll(m));
+  __syncthreads();
+  if (threadIdx.x == 0 && *s_tmp) atomicAdd(counter, *s_tmp);
+}
+
 __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int steps, float t,
                                            float t_entry, int32_t cell, int32_t status, bool rgb = true) {
   if (rgb) {
@@ -128,7 +140,8 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
     }
   }
   atomic_count_grouped(a.counts, cell, inbox);
-  atomic_count_grouped(a.miss_done, a.slot, valid && !inbox);
+  __shared__ uint32_t s_cnt;
+  wg_count(&a.miss_done[a.slot], valid && !inbox, &s_cnt);
 }
 
 // Box clip of a ray (slab method); false when the ray misses the box.
@@ -197,7 +210,8 @@ __global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
     a.path[id] = pr;
   }
   atomic_count_grouped(a.counts, cell, inbox);
-  atomic_count_grouped(a.miss_done, a.slot, valid && !inbox);
+  __shared__ uint32_t s_cnt;
+  wg_count(&a.miss_done[a.slot], valid && !inbox, &s_cnt);
 }
 
 // Path tracing: pixel = mean radiance of its samples, in sample order.
@@ -332,7 +346,10 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
     const bool valid = r.key != kInvalidKey;
     const uint32_t cell = r.key & kCellMask;
     const uint32_t pos = atomic_slot_grouped(a.cursor, cell, valid);
-    if (valid) a.out[pos] = r;
+    if (valid) {
+      a.out[pos] = r;
+      if (a.clear_in) a.in[i].key = kInvalidKey;
+    }
   }
 }
 
@@ -821,9 +838,18 @@ __device__ __forceinline__ void march_eval2_h(int H, const float* blk, int lane,
   }
 }
 
-// s_st word of a staged ray: steps | exit axis << 10 | status << 12 | step budget << 16
 template <int HM, int P>
-__global__ __launch_bounds__(256) void k_march(MarchArgs a) {
+__device__ __forceinline__ float march_eval_h(int H, const float* blk, int lane, int g, const float (&v)[kPeSlots],
+                                              SoftplusK k) {
+  if constexpr (HM != 0) return march_eval<HM, P>(blk, lane, g, v, k);
+  else return H == 64 ? march_eval<64, P>(blk, lane, g, v, k) : march_eval<32, P>(blk, lane, g, v, k);
+}
+
+// s_st word of a staged ray: steps | exit axis << 10 | status << 12 | step budget << 16
+// PAIR: each wave evaluates two 16-ray tiles per step (shared weight reads,
+// two independent chains); otherwise one tile with more waves per SIMD (WPE).
+template <int HM, int P, bool PAIR, int WPE>
+__global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   extern __shared__ __align__(16) float s_dyn[];
   float* s_t = s_dyn;
   float* s_te = s_t + kChunk;
@@ -841,7 +867,8 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   __shared__ uint32_t s_bat[2];            // thread 0's batch of work items
   __shared__ uint32_t s_nact[2], s_pair;
   __shared__ uint32_t s_face[7], s_foff[7];
-  __shared__ uint32_t s_nhit, s_hbase, s_evals, s_tiles;
+  __shared__ uint32_t s_nhit, s_evals, s_tiles;
+  __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
   unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
@@ -851,6 +878,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
   RayRec pf_rec = {0, 0, 0, 0};
   RayStatic pf_st = {0, 0, 0, 0, 0, 0, 1, 0};
   bool pf_rec_ok = false, pf_st_ok = false;
+  if (tid < kMaxSlots) s_miss[tid] = 0u;
   if (tid == 0) {
     s_bat[0] = s_bat[1] = 0u;
     grab_job(a, s_job, s_bat);
@@ -920,7 +948,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       // tile pairs handed out through an LDS counter
       for (;;) {
         uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&s_pair, 2u);
+        if (lane == 0) tile = atomicAdd(&s_pair, PAIR ? 2u : 1u);
         tile = __shfl(tile, 0);
         if (tile >= ntiles) break;
         uint32_t ri[2];
@@ -928,7 +956,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         float t[2], o[2][3], d[2][3], v[2][kPeSlots];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-          const uint32_t idx = (tile + (uint32_t)u) * 16u + (uint32_t)p;
+          const uint32_t idx = (PAIR || u == 0) ? (tile + (uint32_t)u) * 16u + (uint32_t)p : 0xFFFFFFFFu;
           valid[u] = idx < nact;
           ri[u] = valid[u] ? act_in[idx] : 0u;
           t[u] = s_t[ri[u]];
@@ -944,7 +972,12 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
           pe_values(pl, xl[0], xl[1], xl[2], v[u]);
         }
         float f[2];
-        march_eval2_h<HM, P>(H, s_w, lane, g, v[0], v[1], spk, f[0], f[1]);
+        if constexpr (PAIR) {
+          march_eval2_h<HM, P>(H, s_w, lane, g, v[0], v[1], spk, f[0], f[1]);
+        } else {
+          f[0] = march_eval_h<HM, P>(H, s_w, lane, g, v[0], spk);
+          f[1] = 0.0f;
+        }
         ++wave_tiles;
         bool stay[2] = {false, false};
 #pragma unroll
@@ -1029,7 +1062,8 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         if (status == kOutNext) t_entry = t;
         rank = atomicAdd(&s_face[face], 1u);
       } else if (status == kOutHit) {
-        rank = atomicAdd(&s_nhit, 1u);
+        a.hits[s_rid[tid]] = RayRec{t, t_entry, cell | (steps << kCellBits), s_rid[tid]};
+        atomicAdd(&s_nhit, 1u);
       } else {
         const uint32_t px = s_pix[tid];
         slot = px >> kPixBits;
@@ -1051,7 +1085,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
         }
       }
     }
-    atomic_count_grouped(a.tabs.miss_done, slot, miss);
+    if (miss) atomicAdd(&s_miss[slot], 1u);
     __syncthreads();
     if (tid == 0) {
       uint32_t off = 0;
@@ -1061,10 +1095,7 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       }
       a.chunk_out[2 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
       a.chunk_out[2 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
-      if (s_nhit) {
-        atomicAdd(&a.hit_count[cell], s_nhit);
-        s_hbase = atomicAdd(a.n_hits, s_nhit);
-      }
+      if (s_nhit) atomicAdd(&a.hit_count[cell], s_nhit);
       wg_evals += s_evals;
       wg_tiles += s_tiles;
       ++wg_chunks;
@@ -1077,12 +1108,11 @@ __global__ __launch_bounds__(256) void k_march(MarchArgs a) {
       if (status == kOutNext || status == kStay)
         a.U[start + s_foff[face] + rank] =
             RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
-      else if (status == kOutHit)
-        a.hits[s_hbase + rank] = RayRec{t, t_entry, cell | (steps << kCellBits), s_rid[tid]};
     }
     if (tid < 6) s_job[tid] = s_jn[tid];
     __syncthreads();
   }
+  if (tid < kMaxSlots && s_miss[tid]) atomicAdd(&a.tabs.miss_done[tid], s_miss[tid]);
   if (tid == 0 && wg_chunks) {
     atomicAdd(&a.evals[0], wg_evals);
     atomicAdd(&a.evals[1], wg_tiles);
@@ -1173,17 +1203,23 @@ __device__ __forceinline__ f32x4 sdf_full_h(int H, const float* blk, int lane, i
 
 // PT: path tracing; the hit scatters (Lambertian, albedo = color MLP) or
 // ends its path; otherwise the color is the pixel's rgb.
+// 3 waves per SIMD: the shading chain (MFMA -> softplus -> MFMA) is
+// latency-bound, and 3 waves fit in the register file without spills
 template <int HM, bool PT>
-__global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
+__global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
   extern __shared__ __align__(16) float s_mem[];
   float* s_stage = s_mem;                 // 4 waves x 4 hits x 48
   float* s_block = s_mem + 4 * 4 * kColIn;
   __shared__ uint32_t s_job[7];   // cell, start, count, valid, batch cursor, batch end, scene
+  __shared__ uint32_t s_done[kMaxSlots];   // paths / rays finished here, per request slot
   const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
   const int wave = threadIdx.x >> 6;
   const bool value_col = s == 0;
   const PeLane pl = make_pe_lane(g);
   uint32_t loaded = 0xFFFFFFFFu;
+  // this wave's block of the spawn list [sp_cur, sp_end) (path tracing)
+  uint32_t sp_cur = 0, sp_end = 0;
+  if (threadIdx.x < kMaxSlots) s_done[threadIdx.x] = 0u;
   if (threadIdx.x == 0) s_job[4] = s_job[5] = 0u;
   for (;;) {
     if (threadIdx.x == 0) {
@@ -1214,11 +1250,15 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     const int hA = col >> 1, sA = col & 1;
     for (uint32_t base = (uint32_t)wave * 8u; base < count; base += 32u) {
       float tA;
+      RayRec rA;
+      RayStatic sA_;
       {
         const uint32_t idx = base + (uint32_t)hA;
         const bool valid = idx < count;
-        const RayRec r = valid ? a.S[start + idx] : RayRec{0, 0, cell, 0};
-        const RayStatic st = valid ? a.rs[r.rid] : RayStatic{0, 0, 0, 0, 0, 0, 1, 0};
+        rA = valid ? a.S[start + idx] : RayRec{0, 0, cell, 0};
+        sA_ = valid ? a.rs[rA.rid] : RayStatic{0, 0, 0, 0, 0, 0, 1, 0};
+        const RayRec& r = rA;
+        const RayStatic& st = sA_;
         const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
         int eax;
         const float ce = cell_exit(sg, cb, o, d, &eax);
@@ -1242,9 +1282,14 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
       const uint32_t hh = 4u * (uint32_t)half + (uint32_t)h;   // hit of this half
       const uint32_t idx = base + hh;
       const bool valid = idx < count;
-      const float t = __shfl(tA, 2 * (int)hh);
-      RayRec r = valid ? a.S[start + idx] : RayRec{0, 0, cell, 0};
-      const RayStatic st = valid ? a.rs[r.rid] : RayStatic{0, 0, 0, 0, 0, 0, 1, 0};
+      // this hit's records, from the lanes that held it in the Newton passes
+      const int src = 2 * (int)hh;
+      const float t = __shfl(tA, src);
+      const RayRec r{__shfl(rA.t, src), __shfl(rA.t_entry, src), (uint32_t)__shfl((int)rA.key, src),
+                     (uint32_t)__shfl((int)rA.rid, src)};
+      const RayStatic st{__shfl(sA_.ox, src), __shfl(sA_.oy, src), __shfl(sA_.oz, src), __shfl(sA_.t_far, src),
+                         __shfl(sA_.dx, src), __shfl(sA_.dy, src), __shfl(sA_.dz, src),
+                         (uint32_t)__shfl((int)sA_.pix, src)};
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
       float xl[3], gr[3];
       f32x4 y;
@@ -1359,15 +1404,31 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         }
       }
       if constexpr (PT) {
-        const uint32_t pos = atomic_slot_grouped(a.n_spawn, 0u, spawn);
+        const uint64_t sm = __ballot(spawn);
+        const uint32_t ns = (uint32_t)__popcll(sm);
+        if (ns) {
+          if (sp_cur + ns > sp_end) {
+            // close the block (fill its rest with invalid records), take a new one
+            for (uint32_t i = sp_cur + (uint32_t)lane; i < sp_end; i += 64u) a.spawn[i] = RayRec{0, 0, kInvalidKey, 0};
+            uint32_t b = 0;
+            if (lane == 0) b = atomicAdd(a.n_spawn, kSpawnBlock);
+            sp_cur = __shfl(b, 0);
+            sp_end = sp_cur + kSpawnBlock;
+          }
+          if (spawn) a.spawn[sp_cur + (uint32_t)__popcll(sm & lanemask_lt())] = nrec;
+          sp_cur += ns;
+        }
         atomic_count_grouped(a.counts_next, ncell, spawn);
-        if (spawn) a.spawn[pos] = nrec;
       }
-      atomic_count_grouped(a.tabs.hit_done, slot, done);
+      if (done) atomicAdd(&s_done[slot], 1u);
       }
     }
     __syncthreads();
   }
+  if constexpr (PT) {
+    for (uint32_t i = sp_cur + (uint32_t)lane; i < sp_end; i += 64u) a.spawn[i] = RayRec{0, 0, kInvalidKey, 0};
+  }
+  if (threadIdx.x < kMaxSlots && s_done[threadIdx.x]) atomicAdd(&a.tabs.hit_done[threadIdx.x], s_done[threadIdx.x]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1504,17 +1565,19 @@ size_t march_lds_bytes(uint32_t block_words) {
 
 size_t shade_lds_bytes(uint32_t block_words) { return ((size_t)block_words + 4u * 4u * kColIn) * 4u; }
 
-template <int HM, int P>
+template <int HM, int P, bool PAIR, int WPE>
 static hipError_t march_t(const MarchArgs& a, uint32_t block_words, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_march<HM, P>), dim3(grid), dim3(256), march_lds_bytes(block_words), st, a);
+  hipLaunchKernelGGL((k_march<HM, P, PAIR, WPE>), dim3(grid), dim3(256), march_lds_bytes(block_words), st, a);
   return hipGetLastError();
 }
 
+// Per precision: tile pairing and waves per SIMD (measured on 1080p frames of
+// a 16^3, H=64 scene; the chosen forms compile without register spills).
 template <int HM>
 static hipError_t march_p(const MarchArgs& a, int prec, uint32_t block_words, uint32_t grid, hipStream_t st) {
-  if (prec == kPrecF32) return march_t<HM, kPrecF32>(a, block_words, grid, st);
-  if (prec == kPrecBf16) return march_t<HM, kPrecBf16>(a, block_words, grid, st);
-  if (prec == kPrecFp8) return march_t<HM, kPrecFp8>(a, block_words, grid, st);
+  if (prec == kPrecF32) return march_t<HM, kPrecF32, true, 1>(a, block_words, grid, st);
+  if (prec == kPrecBf16) return march_t<HM, kPrecBf16, false, 3>(a, block_words, grid, st);
+  if (prec == kPrecFp8) return march_t<HM, kPrecFp8, true, 1>(a, block_words, grid, st);
   return hipErrorInvalidValue;
 }
 

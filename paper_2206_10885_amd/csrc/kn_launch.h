@@ -103,11 +103,12 @@ struct ScanArgs {
 };
 
 struct ScatterArgs {
-  const RayRec* in;      // records (keys 0xFFFFFFFF are skipped)
+  RayRec* in;            // records (keys 0xFFFFFFFF are skipped)
   RayRec* out;
   uint32_t n;            // number of records, or
   const uint32_t* n_dev; // if not null: the number of records, read on the device
   uint32_t* cursor;
+  int clear_in;          // mark each record taken as invalid (hits indexed by ray id)
 };
 
 struct ScatterChunksArgs {
@@ -130,8 +131,7 @@ struct MarchArgs {
   uint4* chunk_out;          // per chunk: rays leaving through each face / staying, hits
   RayRec* U;                 // next-round rays, in each chunk's own range
   uint32_t* counts_next;
-  RayRec* hits;              // hit list (appended)
-  uint32_t* n_hits;          // its length
+  RayRec* hits;              // hits, indexed by pool ray id (invalid key: none)
   uint32_t* hit_count;       // hits per cell
   unsigned long long* evals;     // [0] evaluations, [1] tiles, [2] chunks
   int max_passes;            // in-cell passes per chunk before the rest wait a round

@@ -314,9 +314,11 @@ void free_pool(Pool& w) {
 
 constexpr size_t kRayBytes = sizeof(RayStatic) + 4 * sizeof(RayRec);
 
+size_t uin_entries(size_t R) { return R + R / 8 + kListSlack; }
+
 size_t pool_bytes(size_t R, size_t C, size_t K) {
-  return R * kRayBytes + C * 4 * 4 + K * (3 * 8 + 2 * 32) + sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) +
-         kMaxSlots * sizeof(ReqEnt);
+  return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * 4 + K * (3 * 8 + 2 * 32) +
+         sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) + kMaxSlots * sizeof(ReqEnt);
 }
 
 // grow-only pool for `rays` records over `cells` cells (with path state if
@@ -341,7 +343,10 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.rs, R * sizeof(RayStatic)));
   KN_HIP(ctx, hipMalloc(&n.U, R * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.S, R * sizeof(RayRec)));
-  KN_HIP(ctx, hipMalloc(&n.Uin, R * sizeof(RayRec)));
+  // Uin also takes path-tracing spawns in per-wave blocks: a block is
+  // re-reserved only when a half-tile's <= 4 spawns do not fit (<= 3 of 64
+  // entries lost), plus one partial block per wave at the end of a pass
+  KN_HIP(ctx, hipMalloc(&n.Uin, uin_entries(R) * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
   if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * 4));
@@ -350,6 +355,7 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.chunk, 3 * K * 8));
   KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 32));
   KN_HIP(ctx, hipMalloc(&n.ctrl, sizeof(Ctrl)));
+  KN_HIP(ctx, hipMemset(n.HL, 0xFF, R * sizeof(RayRec)));   // no hits
   KN_HIP(ctx, hipMalloc(&n.scenes, kMaxScenes * sizeof(SceneEnt)));
   KN_HIP(ctx, hipMalloc(&n.reqs, kMaxSlots * sizeof(ReqEnt)));
   w = n;
@@ -361,7 +367,12 @@ SoftplusK softplus_consts(float beta) {
   return SoftplusK{(float)(-(double)beta / std::log(2.0)), (float)(std::log(2.0) / (double)beta)};
 }
 
-uint32_t persistent_grid(kn_ctx* ctx, uint32_t per_cu) { return (uint32_t)ctx->num_cu * per_cu; }
+// at most 4096 workgroups: the spawn list holds kListSlack entries for
+// partly used blocks (kSpawnBlock per wave of a shading pass)
+uint32_t persistent_grid(kn_ctx* ctx, uint32_t per_cu) {
+  static_assert((size_t)4096 * 4 * kSpawnBlock <= kListSlack, "list slack too small for the largest grid");
+  return std::min<uint32_t>((uint32_t)ctx->num_cu * per_cu, 4096u);
+}
 
 PoolTabs pool_tabs(const Pool& w, uint32_t n_scenes) {
   return PoolTabs{w.scenes, w.reqs, n_scenes, &w.ctrl->miss_done[0], &w.ctrl->hit_done[0], w.path};
@@ -397,10 +408,10 @@ struct RoundCfg {
 };
 
 // Round r: bins the records arriving for it (the previous round's leavers,
-// still in U, and n_new new records in Uin) by cell, then marches them.
-// reset_hitlist empties the hit list (after a shading pass consumed it).
-kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t n_new, bool reset_hitlist,
-                        hipStream_t st, hipEvent_t e0, hipEvent_t e1, const uint32_t* n_new_dev = nullptr) {
+// still in U, and n_new new records in Uin, or *n_new_dev of them) by cell,
+// then marches them.  Hits go to HL[ray id].
+kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t n_new, hipStream_t st,
+                        hipEvent_t e0, hipEvent_t e1, const uint32_t* n_new_dev = nullptr) {
   const int par = r & 1;
   const PoolTabs tabs = pool_tabs(w, c.n_scenes);
   ScanArgs sa{};
@@ -413,7 +424,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   sa.n_chunks = &w.ctrl->n_chunks[par];
   sa.grab = w.ctrl->grab;
   sa.grab0 = w.ctrl->grab0;
-  sa.zero_word = reset_hitlist ? &w.ctrl->n_hitlist : nullptr;
+  sa.zero_word = nullptr;
   sa.total = nullptr;
   KN_HIP(ctx, launch_scan(sa, st));
   if (r > 0) {
@@ -427,11 +438,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
     KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 4), st));
   }
   if (n_new) {
-    ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor};
+    ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor, 0};
     KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_new + 255u) / 256u, 4096u), st));
   }
   if (n_new_dev) {
-    ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor};
+    ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor, 0};
     KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
   }
   MarchArgs ma{};
@@ -445,7 +456,6 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.U = w.U;
   ma.counts_next = w.counts + (par ^ 1) * w.cells;
   ma.hits = w.HL;
-  ma.n_hits = &w.ctrl->n_hitlist;
   ma.hit_count = w.hit_count;
   ma.evals = &w.ctrl->evals;
   ma.max_passes = c.max_passes;
@@ -455,10 +465,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   return KN_OK;
 }
 
-// Shading pass over the hit list: hits binned by cell, refined, shaded.
-// With path tracing, hits that scatter append their next segment to Uin
-// (count in ctrl->n_in, cleared first) for round `next_round`.
-kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, hipStream_t st, hipEvent_t e0,
+// Shading pass over the hits of ray ids [0, n_ids): binned by cell (the
+// scatter clears each hit it takes), refined, shaded.  With path tracing,
+// hits that scatter append their next segment to Uin (count in ctrl->n_in,
+// cleared first) for round `next_round`.
+kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids, hipStream_t st, hipEvent_t e0,
                         hipEvent_t e1, bool pt = false, int next_round = 0) {
   uint2* chunks = w.chunk + 2 * w.chunks;
   ScanArgs sa{};
@@ -474,8 +485,8 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, hipStream_t st,
   sa.zero_word = pt ? &w.ctrl->n_in : nullptr;
   sa.total = &w.ctrl->n_hits;
   KN_HIP(ctx, launch_scan(sa, st));
-  ScatterArgs sc{w.HL, w.S, 0u, &w.ctrl->n_hitlist, w.cursor};
-  KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
+  ScatterArgs sc{w.HL, w.S, n_ids, nullptr, w.cursor, 1};
+  KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_ids + 255u) / 256u, 4096u), st));
   ShadeArgs sh{};
   sh.tabs = pool_tabs(w, c.n_scenes);
   sh.S = w.S;
@@ -487,7 +498,7 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, hipStream_t st,
   sh.n_spawn = &w.ctrl->n_in;
   sh.counts_next = w.counts + (next_round & 1) * w.cells;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
-  KN_HIP(ctx, launch_shade(sh, c.hmode, pt, c.shade_words, persistent_grid(ctx, 2), st));
+  KN_HIP(ctx, launch_shade(sh, c.hmode, pt, c.shade_words, persistent_grid(ctx, 3), st));
   if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
   return KN_OK;
 }
@@ -809,6 +820,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   // both parities of the per-cell counts ([2][w.cells]) and the hit counts
   KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
 
   RaygenArgs rg{};
   rg.sg = ctx->h_scene->sg;
@@ -830,7 +842,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     for (int r = 0; r < max_rounds; ++r) {
       if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
       if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
-      st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, false, stream, e0, e1);
+      st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, stream, e0, e1);
       if (st != KN_OK) return st;
       ++rounds;
       // every kReadback rounds, read back how many chunks the round had; stop
@@ -851,7 +863,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     }
     if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
     if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
-    st = enqueue_shade(ctx, w, cfg, stream, e0, e1);
+    st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, e0, e1);
     if (st != KN_OK) return st;
   } else {
     RaygenPtArgs rp{};
@@ -892,14 +904,14 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
         if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
         if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
         const bool after_shade = k == 0 && r > 0;
-        st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, after_shade, stream, e0, e1,
+        st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, stream, e0, e1,
                            after_shade ? &w.ctrl->n_in : nullptr);
         if (st != KN_OK) return st;
         ++rounds;
       }
       if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
       if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
-      st = enqueue_shade(ctx, w, cfg, stream, e0, e1, true, r);
+      st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, e0, e1, true, r);
       if (st != KN_OK) return st;
       KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[0], &w.ctrl->n_chunks[(r - 1) & 1], 4, hipMemcpyDeviceToHost,
                                  stream));
@@ -1004,7 +1016,7 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.grab0 = w.ctrl->grab0;
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
-  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor};
+  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0};
   KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), stream));
   QueryArgs qa{};
   qa.sg = s->geom;
@@ -1247,6 +1259,16 @@ class ServeLoop {
     return k;
   }
 
+  // end of the highest pool ray-id range in use (the hits the shading pass
+  // looks at); ranges of retired requests hold no hits
+  uint32_t ray_extent() {
+    std::lock_guard<std::mutex> lk(mu);
+    size_t e = 0;
+    for (Request* q : slots)
+      if (q) e = std::max(e, q->base + q->npix);
+    return (uint32_t)e;
+  }
+
   RoundCfg round_cfg() const {
     RoundCfg c{};
     c.hmode = table.empty() ? 32 : table[0].H;
@@ -1355,7 +1377,6 @@ class ServeLoop {
     KN_HIP(ctx, hipSetDevice(ctx->device));
     int r = 0;
     int64_t group = 0;
-    bool shaded = false;
     for (;;) {
       std::vector<Request*> adm;
       {
@@ -1371,13 +1392,11 @@ class ServeLoop {
       }
       const RoundCfg cfg = round_cfg();
       for (int k = 0; k < kGroupRounds; ++k, ++r) {
-        kn_status st = enqueue_round(ctx, pool, cfg, r, k == 0 ? n_new : 0u, k == 0 && shaded, stream,
-                                     nullptr, nullptr);
+        kn_status st = enqueue_round(ctx, pool, cfg, r, k == 0 ? n_new : 0u, stream, nullptr, nullptr);
         if (st != KN_OK) return st;
       }
-      kn_status st = enqueue_shade(ctx, pool, cfg, stream, nullptr, nullptr);
+      kn_status st = enqueue_shade(ctx, pool, cfg, ray_extent(), stream, nullptr, nullptr);
       if (st != KN_OK) return st;
-      shaded = true;
       KN_HIP(ctx, hipMemcpyAsync(head + (size_t)(group & 3) * kCtrlHead, pool.ctrl, kCtrlHead,
                                  hipMemcpyDeviceToHost, stream));
       KN_HIP(ctx, hipEventRecord(ev[group & 3], stream));
@@ -1426,10 +1445,12 @@ kn_status kn_serve_start(kn_ctx* ctx, uint32_t max_inflight, kn_precision precis
   const uint64_t used = ctx->used.load();
   const uint64_t avail = ctx->budget > used ? ctx->budget - used : 0;
   const size_t cell_cap = (size_t)1 << 18;
-  const size_t fixed = pool_bytes(0, cell_cap, cell_cap);
-  if (avail < fixed + ((size_t)1 << 20) * (kRayBytes + 2))
-    return fail(KN_E_NOMEM, "HBM budget leaves no room for a serving pool");
-  const size_t cap = std::min<size_t>((avail - fixed) / (kRayBytes + 2), (size_t)32 << 20);
+  const size_t fixed = pool_bytes(0, cell_cap, cell_cap + 2);
+  // bytes per pool ray, from the pool's own size formula (rounded up)
+  const size_t probe = (size_t)1 << 20;
+  const size_t per_ray = (pool_bytes(probe, cell_cap, probe / kShadeChunk + cell_cap + 2) - fixed) / probe + 1;
+  if (avail < fixed + probe * per_ray) return fail(KN_E_NOMEM, "HBM budget leaves no room for a serving pool");
+  const size_t cap = std::min<size_t>((avail - fixed) / per_ray, (size_t)32 << 20);
   std::shared_ptr<kn::ServeLoop> loop(new kn::ServeLoop(ctx, max_inflight, precision));
   st = loop->start(cap, cell_cap);
   if (st != KN_OK) {
