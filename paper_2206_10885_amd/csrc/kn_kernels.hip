@@ -247,6 +247,7 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
   const uint32_t per = (a.C + 1023u) / 1024u;
   const uint32_t c0 = min(a.C, tid * per), c1 = min(a.C, c0 + per);
   uint32_t sr = 0, sk = 0;
+#pragma unroll 4
   for (uint32_t c = c0; c < c1; ++c) {
     const uint32_t n = a.counts[c];
     sr += n;
@@ -279,6 +280,7 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
   }
   __syncthreads();
   uint32_t R = s_wr[wave] + ir - sr, K = s_wk[wave] + ik - sk;
+#pragma unroll 4
   for (uint32_t c = c0; c < c1; ++c) {
     const uint32_t n = a.counts[c];
     a.cursor[c] = R;
@@ -723,9 +725,48 @@ __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int 
 template <int H>
 __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int g, const float (&v)[kPeSlots],
                                                 SoftplusK k) {
-  float f0, f1;
-  march_eval2_fp8<H>(blk, lane, g, v, v, k, f0, f1);
-  return f0;
+  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  const uint2* fr = reinterpret_cast<const uint2*>(blk);
+  const float* vec = blk + 2 * 64 * NF;
+  const float s1 = vec[3 * H + 1], s2 = vec[3 * H + 2], ia = vec[3 * H + 3];
+  const long e[2] = {fp8x8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]),
+                     fp8x8(v[8], v[9], 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f)};
+  f32x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) acc[b] = mfma_fp8(__builtin_bit_cast(long, fr[(2 * b + c) * 64 + lane]), e[c], acc[b]);
+  long x[H / 32];
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c) {
+    float q[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int b = 2 * c + i / 4, r = i % 4;
+      q[i] = fminf(softplus(fmaf(acc[b][r], s1, vec[16 * b + 4 * g + r]), k) * ia, kE4m3MaxF);
+    }
+    x[c] = fp8x8(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]);
+  }
+#pragma unroll
+  for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c)
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+      acc[b] = mfma_fp8(__builtin_bit_cast(long, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc[b]);
+  float f = 0.0f;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
+    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], bf16_round(softplus(fmaf(acc[b][r], s2, bias[r]), k)), f);
+  }
+  f += __shfl_xor(f, 16);
+  f += __shfl_xor(f, 32);
+  return f + vec[3 * H];
 }
 
 template <int H, int P>
@@ -1577,7 +1618,7 @@ template <int HM>
 static hipError_t march_p(const MarchArgs& a, int prec, uint32_t block_words, uint32_t grid, hipStream_t st) {
   if (prec == kPrecF32) return march_t<HM, kPrecF32, true, 1>(a, block_words, grid, st);
   if (prec == kPrecBf16) return march_t<HM, kPrecBf16, false, 3>(a, block_words, grid, st);
-  if (prec == kPrecFp8) return march_t<HM, kPrecFp8, true, 1>(a, block_words, grid, st);
+  if (prec == kPrecFp8) return march_t<HM, kPrecFp8, false, 3>(a, block_words, grid, st);
   return hipErrorInvalidValue;
 }
 
