@@ -47,6 +47,13 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 // max(u,0) + log2(1 + 2^(-beta log2e |u|)) * ln2 / beta.
 // max(u, 0) is written as (u + |u|) / 2, which is exact and avoids the NaN
 // canonicalisation the compiler adds in front of v_max_f32.
+// 2 softplus(u) = (u + |u|) + 2 ln(1 + e^(-beta |u|)) / beta
+// (bit for bit twice softplus(): the factor 2 is exact in every step)
+__device__ __forceinline__ float softplus_x2(float u, SoftplusK k) {
+  float e = __builtin_amdgcn_exp2f(k.nbl2e * fabsf(u));
+  return fmaf(__builtin_amdgcn_logf(1.0f + e), 2.0f * k.ln2b, u + fabsf(u));
+}
+
 __device__ __forceinline__ float softplus(float u, SoftplusK k) {
   float e = __builtin_amdgcn_exp2f(k.nbl2e * fabsf(u));
   return fmaf(__builtin_amdgcn_logf(1.0f + e), k.ln2b, 0.5f * (u + fabsf(u)));

@@ -436,7 +436,7 @@ __device__ __forceinline__ float march_eval_f32(const float* blk, int lane, int 
 #pragma unroll
   for (int b = 0; b < NB; ++b)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) a1[b][r] = softplus(acc[b][r], k);
+    for (int r = 0; r < 4; ++r) a1[b][r] = softplus_x2(acc[b][r], k);
   f32x4 acc2[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -457,7 +457,7 @@ __device__ __forceinline__ float march_eval_f32(const float* blk, int lane, int 
   for (int b = 0; b < NB; ++b) {
     const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], softplus(acc2[b][r], k), f);
+    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], softplus_x2(acc2[b][r], k), f);
   }
   f += __shfl_xor(f, 16);
   f += __shfl_xor(f, 32);
@@ -467,9 +467,9 @@ __device__ __forceinline__ float march_eval_f32(const float* blk, int lane, int 
 // bfloat16: A fragments ([frag][lane] x 8 bf16) from the LDS block; every
 // layer input rounded to bfloat16, float32 accumulation, bias and softplus
 template <int H>
-__device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int g,
-                                                 const float (&v)[kPeSlots], SoftplusK k) {
-  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+__device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int g, const float (&v)[kPeSlots],
+                                                 SoftplusK k) {
+  constexpr int NB = H / 16, F1 = NB * 2, F2 = F1 + NB * (H / 32), NF = F2 + H / 32;
   const uint4* fr = reinterpret_cast<const uint4*>(blk);
   const float* vec = blk + 64 * 4 * NF;
   bf16x8 e0, e1;
@@ -491,7 +491,7 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
 #pragma unroll
   for (int c = 0; c < H / 32; ++c)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus(acc[2 * c + i / 4][i % 4], k);
+    for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus_x2(acc[2 * c + i / 4][i % 4], k);
   f32x4 acc2[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -500,16 +500,16 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       acc2[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc2[b]);
-  float f = 0.0f;
+  // SDF output row on MFMA: row 0 of the product, in lane group 0
+  f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+  for (int c = 0; c < H / 32; ++c) {
+    bf16x8 x2;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], bf16_round(softplus(acc2[b][r], k)), f);
+    for (int i = 0; i < 8; ++i) x2[i] = (__bf16)softplus_x2(acc2[2 * c + i / 4][i % 4], k);
+    y = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(F2 + c) * 64 + lane]), x2, y);
   }
-  f += __shfl_xor(f, 16);
-  f += __shfl_xor(f, 32);
-  return f + vec[3 * H];
+  return y[0] + vec[3 * H];
 }
 
 // fp8: one tile through the two-tile evaluator (used by the point query)
@@ -551,8 +551,8 @@ __device__ __forceinline__ void march_eval2_f32(const float* blk, int lane, int 
   for (int b = 0; b < NB; ++b)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      a0[b][r] = softplus(acc0[b][r], k);
-      a1[b][r] = softplus(acc1[b][r], k);
+      a0[b][r] = softplus_x2(acc0[b][r], k);
+      a1[b][r] = softplus_x2(acc1[b][r], k);
     }
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -572,8 +572,8 @@ __device__ __forceinline__ void march_eval2_f32(const float* blk, int lane, int 
     const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      s0 = fmaf(w3[r], softplus(acc0[b][r], k), s0);
-      s1 = fmaf(w3[r], softplus(acc1[b][r], k), s1);
+      s0 = fmaf(w3[r], softplus_x2(acc0[b][r], k), s0);
+      s1 = fmaf(w3[r], softplus_x2(acc1[b][r], k), s1);
     }
   }
   s0 += __shfl_xor(s0, 16);
@@ -587,7 +587,7 @@ __device__ __forceinline__ void march_eval2_f32(const float* blk, int lane, int 
 template <int H>
 __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
                                                  const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
-  constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
+  constexpr int NB = H / 16, F1 = NB * 2, F2 = F1 + NB * (H / 32), NF = F2 + H / 32;
   const uint4* fr = reinterpret_cast<const uint4*>(blk);
   const float* vec = blk + 64 * 4 * NF;
   bf16x8 e0[2], e1[2];
@@ -618,8 +618,8 @@ __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int
   for (int c = 0; c < H / 32; ++c)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      x0[c][i] = (__bf16)softplus(acc0[2 * c + i / 4][i % 4], k);
-      x1[c][i] = (__bf16)softplus(acc1[2 * c + i / 4][i % 4], k);
+      x0[c][i] = (__bf16)softplus_x2(acc0[2 * c + i / 4][i % 4], k);
+      x1[c][i] = (__bf16)softplus_x2(acc1[2 * c + i / 4][i % 4], k);
     }
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -631,34 +631,38 @@ __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int
       acc0[b] = mfma_bf16(w, x0[c], acc0[b]);
       acc1[b] = mfma_bf16(w, x1[c], acc1[b]);
     }
-  float s0 = 0.0f, s1 = 0.0f;
+  f32x4 y0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, y1 = y0;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+  for (int c = 0; c < H / 32; ++c) {
+    bf16x8 z0, z1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      s0 = fmaf(w3[r], bf16_round(softplus(acc0[b][r], k)), s0);
-      s1 = fmaf(w3[r], bf16_round(softplus(acc1[b][r], k)), s1);
+    for (int i = 0; i < 8; ++i) {
+      z0[i] = (__bf16)softplus_x2(acc0[2 * c + i / 4][i % 4], k);
+      z1[i] = (__bf16)softplus_x2(acc1[2 * c + i / 4][i % 4], k);
     }
+    const bf16x8 w = __builtin_bit_cast(bf16x8, fr[(F2 + c) * 64 + lane]);
+    y0 = mfma_bf16(w, z0, y0);
+    y1 = mfma_bf16(w, z1, y1);
   }
-  s0 += __shfl_xor(s0, 16);
-  s1 += __shfl_xor(s1, 16);
-  s0 += __shfl_xor(s0, 32);
-  s1 += __shfl_xor(s1, 32);
-  f0 = s0 + vec[3 * H];
-  f1 = s1 + vec[3 * H];
+  f0 = y0[0] + vec[3 * H];
+  f1 = y1[0] + vec[3 * H];
 }
 
 // fp8 e4m3: A fragments ([frag][lane] x 8 bytes); layer inputs quantised
 // with power-of-two scales (encoding: 1; a1: 1 / vec[3H+3]), the products
 // accumulated in float32, then u = acc * scale + bias; softplus in float32;
 // the SDF output row as in the bfloat16 variant.
+// fp8 e4m3: A fragments ([frag][lane] x 8 bytes); layer inputs quantised
+// with power-of-two scales (encoding: 1; a1: vec[3H+3] applied to 2 a1),
+// the products accumulated in float32, then u = acc * scale + bias; softplus
+// in float32; the SDF output row on bfloat16 MFMA as in the bfloat16 variant.
 template <int H>
 __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
                                                 const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
   constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
   const uint2* fr = reinterpret_cast<const uint2*>(blk);
-  const float* vec = blk + 2 * 64 * NF;
+  const uint4* f3 = reinterpret_cast<const uint4*>(blk + 2 * 64 * NF);
+  const float* vec = blk + 2 * 64 * NF + 4 * 64 * (H / 32);
   const float s1 = vec[3 * H + 1], s2 = vec[3 * H + 2], ia = vec[3 * H + 3];
   const long e0[2] = {fp8x8(v0[0], v0[1], v0[2], v0[3], v0[4], v0[5], v0[6], v0[7]),
                       fp8x8(v0[8], v0[9], 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f)};
@@ -675,23 +679,19 @@ __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int 
       acc0[b] = mfma_fp8(w, e0[c], acc0[b]);
       acc1[b] = mfma_fp8(w, e1[c], acc1[b]);
     }
-  float q0[NB][4], q1[NB][4];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      q0[b][r] = fminf(softplus(fmaf(acc0[b][r], s1, bias[r]), k) * ia, kE4m3MaxF);
-      q1[b][r] = fminf(softplus(fmaf(acc1[b][r], s1, bias[r]), k) * ia, kE4m3MaxF);
-    }
-  }
   long x0[H / 32], x1[H / 32];
 #pragma unroll
   for (int c = 0; c < H / 32; ++c) {
-    x0[c] = fp8x8(q0[2 * c][0], q0[2 * c][1], q0[2 * c][2], q0[2 * c][3], q0[2 * c + 1][0], q0[2 * c + 1][1],
-                  q0[2 * c + 1][2], q0[2 * c + 1][3]);
-    x1[c] = fp8x8(q1[2 * c][0], q1[2 * c][1], q1[2 * c][2], q1[2 * c][3], q1[2 * c + 1][0], q1[2 * c + 1][1],
-                  q1[2 * c + 1][2], q1[2 * c + 1][3]);
+    float q0[8], q1[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int b = 2 * c + i / 4, r = i % 4;
+      const float bias = vec[16 * b + 4 * g + r];
+      q0[i] = fminf(softplus_x2(fmaf(acc0[b][r], s1, bias), k) * ia, kE4m3MaxF);
+      q1[i] = fminf(softplus_x2(fmaf(acc1[b][r], s1, bias), k) * ia, kE4m3MaxF);
+    }
+    x0[c] = fp8x8(q0[0], q0[1], q0[2], q0[3], q0[4], q0[5], q0[6], q0[7]);
+    x1[c] = fp8x8(q1[0], q1[1], q1[2], q1[3], q1[4], q1[5], q1[6], q1[7]);
   }
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -703,23 +703,23 @@ __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int 
       acc0[b] = mfma_fp8(w, x0[c], acc0[b]);
       acc1[b] = mfma_fp8(w, x1[c], acc1[b]);
     }
-  float s0 = 0.0f, s1v = 0.0f;
+  f32x4 y0 = f32x4{0.0f, 0.0f, 0.0f, 0.0f}, y1 = y0;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
-    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+  for (int c = 0; c < H / 32; ++c) {
+    bf16x8 z0, z1;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      s0 = fmaf(w3[r], bf16_round(softplus(fmaf(acc0[b][r], s2, bias[r]), k)), s0);
-      s1v = fmaf(w3[r], bf16_round(softplus(fmaf(acc1[b][r], s2, bias[r]), k)), s1v);
+    for (int i = 0; i < 8; ++i) {
+      const int b = 2 * c + i / 4, r = i % 4;
+      const float bias = vec[H + 16 * b + 4 * g + r];
+      z0[i] = (__bf16)softplus_x2(fmaf(acc0[b][r], s2, bias), k);
+      z1[i] = (__bf16)softplus_x2(fmaf(acc1[b][r], s2, bias), k);
     }
+    const bf16x8 w = __builtin_bit_cast(bf16x8, f3[c * 64 + lane]);
+    y0 = mfma_bf16(w, z0, y0);
+    y1 = mfma_bf16(w, z1, y1);
   }
-  s0 += __shfl_xor(s0, 16);
-  s1v += __shfl_xor(s1v, 16);
-  s0 += __shfl_xor(s0, 32);
-  s1v += __shfl_xor(s1v, 32);
-  f0 = s0 + vec[3 * H];
-  f1 = s1v + vec[3 * H];
+  f0 = y0[0] + vec[3 * H];
+  f1 = y1[0] + vec[3 * H];
 }
 
 template <int H>
@@ -727,7 +727,8 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
                                                 SoftplusK k) {
   constexpr int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
   const uint2* fr = reinterpret_cast<const uint2*>(blk);
-  const float* vec = blk + 2 * 64 * NF;
+  const uint4* f3 = reinterpret_cast<const uint4*>(blk + 2 * 64 * NF);
+  const float* vec = blk + 2 * 64 * NF + 4 * 64 * (H / 32);
   const float s1 = vec[3 * H + 1], s2 = vec[3 * H + 2], ia = vec[3 * H + 3];
   const long e[2] = {fp8x8(v[0], v[1], v[2], v[3], v[4], v[5], v[6], v[7]),
                      fp8x8(v[8], v[9], 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f)};
@@ -745,7 +746,7 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = 2 * c + i / 4, r = i % 4;
-      q[i] = fminf(softplus(fmaf(acc[b][r], s1, vec[16 * b + 4 * g + r]), k) * ia, kE4m3MaxF);
+      q[i] = fminf(softplus_x2(fmaf(acc[b][r], s1, vec[16 * b + 4 * g + r]), k) * ia, kE4m3MaxF);
     }
     x[c] = fp8x8(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]);
   }
@@ -756,17 +757,18 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
 #pragma unroll
     for (int b = 0; b < NB; ++b)
       acc[b] = mfma_fp8(__builtin_bit_cast(long, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc[b]);
-  float f = 0.0f;
+  f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    const f32x4 bias = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
-    const f32x4 w3 = *reinterpret_cast<const f32x4*>(vec + 2 * H + 16 * b + 4 * g);
+  for (int c = 0; c < H / 32; ++c) {
+    bf16x8 z;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) f = fmaf(w3[r], bf16_round(softplus(fmaf(acc[b][r], s2, bias[r]), k)), f);
+    for (int i = 0; i < 8; ++i) {
+      const int b = 2 * c + i / 4, r = i % 4;
+      z[i] = (__bf16)softplus_x2(fmaf(acc[b][r], s2, vec[H + 16 * b + 4 * g + r]), k);
+    }
+    y = mfma_bf16(__builtin_bit_cast(bf16x8, f3[c * 64 + lane]), z, y);
   }
-  f += __shfl_xor(f, 16);
-  f += __shfl_xor(f, 32);
-  return f + vec[3 * H];
+  return y[0] + vec[3 * H];
 }
 
 template <int H, int P>

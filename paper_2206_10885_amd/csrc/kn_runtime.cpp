@@ -75,7 +75,7 @@ static void pack_march_f32(const float* blk, int H, float* out) {
         val = idx < 0 ? 0.0f : w.W1[(16 * b + m) * kSdfIn + idx];
       } else {
         const int s2 = s - S1, b = s2 / (H / 4), q = s2 % (H / 4);
-        val = w.W2[(16 * b + m) * H + unit_f32(q, g)];
+        val = 0.5f * w.W2[(16 * b + m) * H + unit_f32(q, g)];   // layer 1 hands on 2 softplus
       }
       out[(s / 4) * 256 + lane * 4 + (s % 4)] = val;
     }
@@ -84,10 +84,21 @@ static void pack_march_f32(const float* blk, int H, float* out) {
   for (int j = 0; j < H; ++j) {
     vec[j] = w.b1[j];
     vec[H + j] = w.b2[j];
-    vec[2 * H + j] = w.W3[j];
+    vec[2 * H + j] = 0.5f * w.W3[j];
   }
   vec[3 * H] = w.b3[0];
   vec[3 * H + 1] = vec[3 * H + 2] = vec[3 * H + 3] = 0.0f;
+}
+
+// SDF output row as bfloat16 MFMA A fragments (row 0 = the row, halved;
+// rows 1..15 zero), K order of the layer-2 outputs
+static void pack_w3_bf16(const SdfView& w, int H, uint16_t* out) {
+  for (int c = 0; c < H / 32; ++c)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = lane % 16, g = lane / 16;
+      for (int i = 0; i < 8; ++i)
+        out[((size_t)c * 64 + lane) * 8 + i] = bf16_bits(m == 0 ? 0.5f * w.W3[unit_bf16(c, g, i)] : 0.0f);
+    }
 }
 
 static void pack_march_bf16(const float* blk, int H, float* out_words) {
@@ -105,13 +116,15 @@ static void pack_march_bf16(const float* blk, int H, float* out_words) {
           val = idx < 0 ? 0.0f : w.W1[(16 * b + m) * kSdfIn + idx];
         } else {
           const int f2 = f - F1, b = f2 / (H / 32), c = f2 % (H / 32);
-          val = w.W2[(16 * b + m) * H + unit_bf16(c, g, i)];
+          val = 0.5f * w.W2[(16 * b + m) * H + unit_bf16(c, g, i)];   // layer 1 hands on 2 softplus
         }
         out[((size_t)f * 64 + lane) * 8 + i] = bf16_bits(val);
       }
     }
   }
-  float* vec = out_words + 64 * 4 * NF;
+  pack_w3_bf16(w, H, out + (size_t)NF * 64 * 8);
+  const int NFW = NF + H / 32;
+  float* vec = out_words + 64 * 4 * NFW;
   for (int j = 0; j < H; ++j) {
     vec[j] = w.b1[j];
     vec[H + j] = w.b2[j];
@@ -161,7 +174,8 @@ static void pack_march_fp8(const float* blk, int H, float beta, float* out_words
       }
     }
   }
-  float* vec = out_words + 2 * 64 * NF;
+  pack_w3_bf16(w, H, reinterpret_cast<uint16_t*>(out_words + 2 * 64 * NF));
+  float* vec = out_words + 2 * 64 * NF + 4 * 64 * (H / 32);
   for (int j = 0; j < H; ++j) {
     vec[j] = w.b1[j];
     vec[H + j] = w.b2[j];
@@ -170,7 +184,7 @@ static void pack_march_fp8(const float* blk, int H, float beta, float* out_words
   vec[3 * H] = w.b3[0];
   vec[3 * H + 1] = s1;
   vec[3 * H + 2] = s2 * sa;
-  vec[3 * H + 3] = 1.0f / sa;
+  vec[3 * H + 3] = 0.5f / sa;   // layer 1 hands on 2 softplus
 }
 
 static void pack_shade(const float* blk, const float* cblk, int H, float* out) {
