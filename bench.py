@@ -9,7 +9,8 @@ through every stage: ray generation and box clip, per-round cell binning,
 the march (bfloat16 MLP on MFMA), hit binning, refinement and shading.
 The same frames are then timed with the float32 march for the ratio.
 
-Prints one JSON line (see the design doc for the field definitions).
+Prints one JSON line: metric, value, unit, timing, dtype, config, the
+roofline of the dominant kernel and the oracle's CPU rate.
 """
 from __future__ import annotations
 
@@ -253,8 +254,8 @@ def pathtrace_bench(torch, frames: int = 3) -> dict:
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the ray "
-                                   "sharding across GPUs is described in DESIGN.md)"}))
+        print(json.dumps({"error": "the renderer runs on one GPU per process; "
+                                   "--gpus must be 1"}))
         sys.exit(2)
     import torch
 

@@ -4,19 +4,21 @@
 //   k_raygen   pinhole rays, box clip (Sec. 3.4.1), entry cell, box misses
 //   per round: k_scan    per-cell exclusive scan -> bin starts, work chunks
 //              k_scatter counting sort of the round's rays by global cell
-//                        (round 0: per ray; later rounds: per chunk and exit
-//                        face, six atomics per chunk)
-//              k_march   one workgroup per chunk (<= 256 rays) of a cell's
-//                        bin: the cell's MLP weights (MFMA A fragments) and
-//                        the rays are staged in LDS; the four waves step
-//                        16-ray tiles in passes over an LDS active list while
-//                        rays stay in the cell; rays leaving for a neighbour
-//                        cell are written to the chunk's own output range,
-//                        grouped by exit face (no global list counter)
+//                        (first round: per ray; later rounds: per chunk and
+//                        exit face)
+//              k_march   one work item per chunk (<= 256 rays) of a cell's
+//                        bin: the cell's MLP weights (MFMA fragments) and the
+//                        rays are staged in LDS; the waves step 16-ray tiles
+//                        in passes over an LDS active list while rays stay in
+//                        the cell; rays leaving for a neighbour cell are
+//                        written to the chunk's own output range, grouped by
+//                        exit face (no global list counter); hits are written
+//                        to a list indexed by ray id
 //   after the rounds: hits are binned by cell the same way, then k_shade
-//              refines each hit with two Newton steps, takes the normalised
-//              analytic gradient (forward-mode: value + 3 tangent columns per
-//              hit in one MFMA tile) and runs the color MLP (Sec. 3.1 eq. 4).
+//              refines each hit with two Newton steps (value and the
+//              directional derivative along the ray), takes the normalised
+//              analytic gradient (value + 3 tangent columns per hit) and runs
+//              the color MLP (Sec. 3.1 eq. 4).
 #include "kn_device.h"
 #include "kn_launch.h"
 
@@ -230,47 +232,84 @@ __global__ __launch_bounds__(256) void k_resolve(ResolveArgs a) {
 // ---------------------------------------------------------------------------
 // per-round scan (one workgroup): bin starts, scatter cursors, work chunks
 // ---------------------------------------------------------------------------
-// inclusive prefix sum over the 64 lanes of a wave
+// Inclusive prefix sum over the 64 lanes of a wave on DPP: four row shifts
+// build the sums inside each row of 16 lanes, then the last lane of row 0 is
+// broadcast into row 1 (and of row 2 into row 3), and the last lane of row 1
+// into rows 2 and 3.  Lanes whose source lies outside the row read 0.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-  const int lane = lane_id();
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+__device__ __forceinline__ uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
+
+typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
+
+// counts of 32 steps of 64 cells from b on (lane's cell of each step; 0 past e)
+__device__ __forceinline__ u32x32 load_steps(const uint32_t* counts, uint32_t b, uint32_t e, uint32_t lane) {
+  u32x32 v;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t u = __shfl_up(v, off);
-    if (lane >= off) v += u;
+  for (int q = 0; q < 32; ++q) {
+    const uint32_t c = b + 64u * (uint32_t)q + lane;
+    v[q] = c < e ? counts[c] : 0u;
   }
   return v;
 }
 
+// One workgroup of 16 waves.  Wave w owns the contiguous strip of cells
+// [w*S, (w+1)*S), S a multiple of 64, and walks it 64 cells at a time with one
+// cell per lane, so that every load and store of a wave covers consecutive
+// words; counts are loaded 32 steps at a time (the first 32 stay in registers
+// for the second sweep).  The first sweep sums the strip; the strip offsets
+// come from a scan of the 16 wave sums; the second sweep scans each step of
+// 64 cells across the lanes and carries the step total to the next.  Cells
+// are visited in increasing order, so bins and chunks are laid out in cell
+// order.  Empty cells are not written: their cursor is never read and their
+// count is already zero.  T is a power of two.
 __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
   __shared__ uint32_t s_wr[16], s_wk[16];
   const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id(), wave = tid >> 6;
-  const uint32_t per = (a.C + 1023u) / 1024u;
-  const uint32_t c0 = min(a.C, tid * per), c1 = min(a.C, c0 + per);
+  const uint32_t tm = a.T - 1u, ts = (uint32_t)__builtin_ctz(a.T);
+  const uint32_t S = ((a.C + 1023u) >> 10) << 6;
+  const uint32_t s0 = wave * S, s1 = min(a.C, s0 + S);
   uint32_t sr = 0, sk = 0;
-#pragma unroll 4
-  for (uint32_t c = c0; c < c1; ++c) {
-    const uint32_t n = a.counts[c];
-    sr += n;
-    sk += (n + a.T - 1u) / a.T;
+  u32x32 first = load_steps(a.counts, s0, s1, lane);
+#pragma unroll
+  for (int q = 0; q < 32; ++q) {
+    sr += first[q];
+    sk += (first[q] + tm) >> ts;
   }
-  const uint32_t ir = wave_incl_scan(sr), ik = wave_incl_scan(sk);
-  if (lane == 63) {
-    s_wr[wave] = ir;
-    s_wk[wave] = ik;
+  for (uint32_t b = s0 + 2048u; b < s1; b += 2048u) {
+    const u32x32 v = load_steps(a.counts, b, s1, lane);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      sr += v[q];
+      sk += (v[q] + tm) >> ts;
+    }
+  }
+  const uint32_t tr = lane63(wave_incl_scan(sr)), tk = lane63(wave_incl_scan(sk));
+  if (lane == 0) {
+    s_wr[wave] = tr;
+    s_wk[wave] = tk;
   }
   __syncthreads();
   if (wave == 0) {
     const uint32_t vr = lane < 16 ? s_wr[lane] : 0u, vk = lane < 16 ? s_wk[lane] : 0u;
-    const uint32_t er = wave_incl_scan(vr) - vr, ek = wave_incl_scan(vk) - vk;
+    const uint32_t ir = wave_incl_scan(vr), ik = wave_incl_scan(vk);
     if (lane < 16) {
-      s_wr[lane] = er;
-      s_wk[lane] = ek;
+      s_wr[lane] = ir - vr;
+      s_wk[lane] = ik - vk;
     }
-    const uint32_t nch = __shfl(ek + vk, 15);
+    const uint32_t nch = lane63(ik);
     if (lane == 15) {
       *a.n_chunks = nch;
       if (a.zero_word) *a.zero_word = 0u;
-      if (a.total) *a.total += er + vr;
+      if (a.total) *a.total += ir;
     }
     if (lane < (uint32_t)kGroups) {
       const uint32_t g0 = (uint32_t)(((uint64_t)nch * lane) / kGroups);
@@ -279,17 +318,26 @@ __global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
     }
   }
   __syncthreads();
-  uint32_t R = s_wr[wave] + ir - sr, K = s_wk[wave] + ik - sk;
-#pragma unroll 4
-  for (uint32_t c = c0; c < c1; ++c) {
-    const uint32_t n = a.counts[c];
-    a.cursor[c] = R;
-    for (uint32_t i = 0; i < n; i += a.T) {
-      const uint32_t m = min(a.T, n - i);
-      a.chunks[K++] = make_uint2(c | (m << kCellBits), R + i);
+  uint32_t R = s_wr[wave], K = s_wk[wave];
+  for (uint32_t b = s0; b < s1; b += 2048u) {
+    const u32x32 v = b == s0 ? first : load_steps(a.counts, b, s1, lane);
+#pragma unroll
+    for (int q = 0; q < 32; ++q) {
+      if (b + 64u * (uint32_t)q >= s1) break;
+      const uint32_t c = b + 64u * (uint32_t)q + lane;
+      const uint32_t n = v[q];
+      const uint32_t k = (n + tm) >> ts;
+      const uint32_t ir = wave_incl_scan(n), ik = wave_incl_scan(k);
+      if (n) {
+        const uint32_t r = R + ir - n;
+        uint32_t j = K + ik - k;
+        a.cursor[c] = r;
+        for (uint32_t i = 0; i < n; i += a.T) a.chunks[j++] = make_uint2(c | (min(a.T, n - i) << kCellBits), r + i);
+        if (a.zero_counts) a.counts[c] = 0u;
+      }
+      R += lane63(ir);
+      K += lane63(ik);
     }
-    R += n;
-    if (a.zero_counts) a.counts[c] = 0u;
   }
 }
 
@@ -374,32 +422,92 @@ __device__ __forceinline__ uint32_t neighbor_cell(const SceneGeom& sg, uint32_t 
 
 // Rounds >= 1: each chunk of the previous round left its next-round rays in
 // its own range of U, grouped by exit face (and a seventh group that stays
-// in the cell); one wave moves each run into its cell's bin (one atomic per
-// run).
+// in the cell); one wave moves the chunk's runs into their cells' bins (one
+// atomic per run).  The records are loaded while the atomics are in flight
+// and copied in one flat pass: a record's run follows from the seven run
+// offsets.  The next chunk's descriptors are fetched ahead.
+// a value that is the same in every lane, as a scalar
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+
+// destination of record i of a chunk's runs: the base of the run that holds
+// it (o_f = offset of run f, d_f = destination of run f minus o_f), plus i
+__device__ __forceinline__ uint32_t run_dest(uint32_t i, uint32_t o1, uint32_t o2, uint32_t o3, uint32_t o4,
+                                             uint32_t o5, uint32_t o6, uint32_t d0, uint32_t d1, uint32_t d2,
+                                             uint32_t d3, uint32_t d4, uint32_t d5, uint32_t d6) {
+  uint32_t d = d0;
+  d = i >= o1 ? d1 : d;
+  d = i >= o2 ? d2 : d;
+  d = i >= o3 ? d3 : d;
+  d = i >= o4 ? d4 : d;
+  d = i >= o5 ? d5 : d;
+  d = i >= o6 ? d6 : d;
+  return d + i;
+}
+
 __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterChunksArgs a) {
   const uint32_t nch = *a.n_chunks;
-  const int lane = lane_id();
+  const uint32_t lane = (uint32_t)lane_id();
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+  uint2 c = make_uint2(0u, 0u);
+  uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = fa;
+  if (wave < nch) {
+    c = a.chunks[wave];
+    fa = a.chunk_out[2 * wave];
+    fb = a.chunk_out[2 * wave + 1];
+  }
+  uint4* out = reinterpret_cast<uint4*>(a.S);
   for (uint32_t j = wave; j < nch; j += nwaves) {
-    const uint2 c = a.chunks[j];
-    const uint32_t cell = c.x & kCellMask, start = c.y;
-    const uint4 fa = a.chunk_out[2 * j], fb = a.chunk_out[2 * j + 1];
-    const uint32_t faces[7] = {fa.x, fa.y, fa.z, fa.w, fb.x, fb.y, fb.z};
+    // the chunk is the same in every lane
+    const uint32_t cell = uniform(c.x) & kCellMask, start = uniform(c.y);
+    // run sizes by exit face (x-, x+, y-, y+, z-, z+, stay) and their offsets
+    const uint32_t n0 = uniform(fa.x), n1 = uniform(fa.y), n2 = uniform(fa.z), n3 = uniform(fa.w);
+    const uint32_t n4 = uniform(fb.x), n5 = uniform(fb.y), n6 = uniform(fb.z);
+    const uint32_t o1 = n0, o2 = o1 + n1, o3 = o2 + n2, o4 = o3 + n3, o5 = o4 + n4, o6 = o5 + n5;
+    const uint32_t total = o6 + n6;
+    const uint32_t jn = j + nwaves;
+    if (jn < nch) {
+      c = a.chunks[jn];
+      fa = a.chunk_out[2 * jn];
+      fb = a.chunk_out[2 * jn + 1];
+    }
+    if (total == 0u) continue;
+    // the first 256 records are loaded before the atomics; indexes past the
+    // chunk's records are clamped to its last one (and not stored)
+    const uint4* src = reinterpret_cast<const uint4*>(a.U) + start;
+    const uint32_t last = total - 1u;
+    uint4 v0 = src[min(lane, last)], v1 = src[min(lane + 64u, last)];
+    uint4 v2 = src[min(lane + 128u, last)], v3 = src[min(lane + 192u, last)];
     // lanes 0..6 reserve the seven runs' destinations at once
-    uint32_t mine = 0, dst = 0;
-#pragma unroll
-    for (int f = 0; f < 7; ++f)
-      if (lane == f) mine = faces[f];
-    if (lane < 7 && mine)
-      dst = atomicAdd(&a.cursor[neighbor_cell(a.tabs.scenes[scene_of(a.tabs, cell)].sg, cell, lane)], mine);
-    uint32_t off = 0;
-#pragma unroll
-    for (int f = 0; f < 7; ++f) {
-      const uint32_t n = faces[f];
-      const uint32_t base = __shfl(dst, f);
-      for (uint32_t i = (uint32_t)lane; i < n; i += 64u) a.S[base + i] = a.U[start + off + i];
-      off += n;
+    const uint32_t mine = lane == 0u ? n0 : lane == 1u ? n1 : lane == 2u ? n2 : lane == 3u ? n3
+                        : lane == 4u ? n4 : lane == 5u ? n5 : lane == 6u ? n6 : 0u;
+    uint32_t dst = 0;
+    if (mine)
+      dst = atomicAdd(&a.cursor[neighbor_cell(a.tabs.scenes[scene_of(a.tabs, cell)].sg, cell, (int)lane)], mine);
+    // destination of record i: its run's base minus the run's offset, plus i
+    const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 0);
+    const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 1) - o1;
+    const uint32_t d2 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 2) - o2;
+    const uint32_t d3 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 3) - o3;
+    const uint32_t d4 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 4) - o4;
+    const uint32_t d5 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 5) - o5;
+    const uint32_t d6 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 6) - o6;
+    for (uint32_t b0 = 0;;) {
+      const uint32_t i0 = b0 + lane, i1 = i0 + 64u, i2 = i0 + 128u, i3 = i0 + 192u;
+      const uint32_t e0 = run_dest(i0, o1, o2, o3, o4, o5, o6, d0, d1, d2, d3, d4, d5, d6);
+      const uint32_t e1 = run_dest(i1, o1, o2, o3, o4, o5, o6, d0, d1, d2, d3, d4, d5, d6);
+      const uint32_t e2 = run_dest(i2, o1, o2, o3, o4, o5, o6, d0, d1, d2, d3, d4, d5, d6);
+      const uint32_t e3 = run_dest(i3, o1, o2, o3, o4, o5, o6, d0, d1, d2, d3, d4, d5, d6);
+      if (i0 < total) out[e0] = v0;
+      if (i1 < total) out[e1] = v1;
+      if (i2 < total) out[e2] = v2;
+      if (i3 < total) out[e3] = v3;
+      b0 += 256u;
+      if (b0 >= total) break;
+      v0 = src[min(b0 + lane, last)];
+      v1 = src[min(b0 + lane + 64u, last)];
+      v2 = src[min(b0 + lane + 128u, last)];
+      v3 = src[min(b0 + lane + 192u, last)];
     }
   }
 }
@@ -1588,6 +1696,7 @@ hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t st) {
+  if (a.T == 0 || a.T > 512 || (a.T & (a.T - 1u)) != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a);
   return hipGetLastError();
 }

@@ -91,7 +91,7 @@ struct ResolveArgs {
 
 struct ScanArgs {
   uint32_t* counts;      // per-cell counts (read; zeroed if zero_counts)
-  uint32_t C, T;         // cells, chunk size (<= 1023)
+  uint32_t C, T;         // cells, chunk size (a power of two, <= 512)
   int zero_counts;
   uint32_t* cursor;      // out: bin start per cell (scatter cursor)
   uint2* chunks;         // out: (cell | count << 22, start)
