@@ -590,10 +590,15 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
   f32x4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g);
+  {
+    uint4 wf[2 * NB];   // the layer's fragments are read together, ahead of its MFMAs
 #pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(2 * b) * 64 + lane]), e0, acc[b]);
-    acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(2 * b + 1) * 64 + lane]), e1, acc[b]);
+    for (int i = 0; i < 2 * NB; ++i) wf[i] = fr[i * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, wf[2 * b]), e0, acc[b]);
+      acc[b] = mfma_bf16(__builtin_bit_cast(bf16x8, wf[2 * b + 1]), e1, acc[b]);
+    }
   }
   bf16x8 x[H / 32];
 #pragma unroll
@@ -604,10 +609,13 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
 #pragma unroll
-  for (int c = 0; c < H / 32; ++c)
+  for (int c = 0; c < H / 32; ++c) {
+    uint4 wf[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc2[b] = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc2[b]);
+    for (int b = 0; b < NB; ++b) wf[b] = fr[(F1 + b * (H / 32) + c) * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc2[b] = mfma_bf16(__builtin_bit_cast(bf16x8, wf[b]), x[c], acc2[b]);
+  }
   // SDF output row on MFMA: row 0 of the product, in lane group 0
   f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
@@ -843,10 +851,15 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
   f32x4 acc[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  {
+    uint2 wf[2 * NB];   // the layer's fragments are read together, ahead of its MFMAs
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
+    for (int i = 0; i < 2 * NB; ++i) wf[i] = fr[i * 64 + lane];
 #pragma unroll
-    for (int c = 0; c < 2; ++c) acc[b] = mfma_fp8(__builtin_bit_cast(long, fr[(2 * b + c) * 64 + lane]), e[c], acc[b]);
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) acc[b] = mfma_fp8(__builtin_bit_cast(long, wf[2 * b + c]), e[c], acc[b]);
+  }
   long x[H / 32];
 #pragma unroll
   for (int c = 0; c < H / 32; ++c) {
@@ -861,10 +874,13 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc[b] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int c = 0; c < H / 32; ++c)
+  for (int c = 0; c < H / 32; ++c) {
+    uint2 wf[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b)
-      acc[b] = mfma_fp8(__builtin_bit_cast(long, fr[(F1 + b * (H / 32) + c) * 64 + lane]), x[c], acc[b]);
+    for (int b = 0; b < NB; ++b) wf[b] = fr[(F1 + b * (H / 32) + c) * 64 + lane];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) acc[b] = mfma_fp8(__builtin_bit_cast(long, wf[b]), x[c], acc[b]);
+  }
   f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int c = 0; c < H / 32; ++c) {

@@ -449,7 +449,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
                          w.U,
                          w.S,
                          w.cursor};
-    KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 4), st));
+    KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 16), st));
   }
   if (n_new) {
     ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor, 0};
