@@ -255,6 +255,15 @@ __device__ __forceinline__ void cosine_dir(const float n[3], float u1, float u2,
   for (int k = 0; k < 3; ++k) out[k] = lx * b1[k] + ly * b2[k] + lz * n[k];
 }
 
+// The same address as a pointer into global memory.  Pointers read from
+// tables in memory are generic to the compiler; its flat accesses through them
+// also count against the LDS wait counter, so that LDS waits after a flat
+// store wait for the store.  Accesses through the cast are global.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p) {
+  return (__attribute__((address_space(1))) T*)p;
+}
+
 // equirectangular environment [h][w][3]: u = 1/2 + atan2(d_x, -d_z) / 2 pi,
 // v = acos(d_y) / pi; bilinear between texel centres, wrap in u, clamp in v
 __device__ __forceinline__ void env_lookup(const float* env, uint32_t w, uint32_t h, const float d[3],
@@ -272,8 +281,8 @@ __device__ __forceinline__ void env_lookup(const float* env, uint32_t w, uint32_
   if (x0 < 0) x0 += (int)w;
   const int x1 = (x0 + 1) % (int)w;
   const int y0 = min(max((int)fy0, 0), (int)h - 1), y1 = min(max((int)fy0 + 1, 0), (int)h - 1);
-  const float* r0 = env + (size_t)y0 * w * 3;
-  const float* r1 = env + (size_t)y1 * w * 3;
+  const auto r0 = gmem(env + (size_t)y0 * w * 3);
+  const auto r1 = gmem(env + (size_t)y1 * w * 3);
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
     const float t0 = (1.0f - fx) * r0[3 * x0 + c] + fx * r0[3 * x1 + c];

@@ -72,18 +72,18 @@ __device__ __forceinline__ void wg_count(uint32_t* counter, bool flag, uint32_t*
 __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int steps, float t,
                                            float t_entry, int32_t cell, int32_t status, bool rgb = true) {
   if (rgb) {
-    o.rgb[3 * pix + 0] = o.bg[0];
-    o.rgb[3 * pix + 1] = o.bg[1];
-    o.rgb[3 * pix + 2] = o.bg[2];
+    gmem(o.rgb)[3 * pix + 0] = o.bg[0];
+    gmem(o.rgb)[3 * pix + 1] = o.bg[1];
+    gmem(o.rgb)[3 * pix + 2] = o.bg[2];
   }
-  if (o.depth) o.depth[pix] = 0.0f;
+  if (o.depth) gmem(o.depth)[pix] = 0.0f;
   if (o.normal) {
-    o.normal[3 * pix + 0] = 0.0f;
-    o.normal[3 * pix + 1] = 0.0f;
-    o.normal[3 * pix + 2] = 0.0f;
+    gmem(o.normal)[3 * pix + 0] = 0.0f;
+    gmem(o.normal)[3 * pix + 1] = 0.0f;
+    gmem(o.normal)[3 * pix + 2] = 0.0f;
   }
-  if (o.hit) o.hit[pix] = 0;
-  if (o.steps) o.steps[pix] = (uint16_t)steps;
+  if (o.hit) gmem(o.hit)[pix] = 0;
+  if (o.steps) gmem(o.steps)[pix] = (uint16_t)steps;
   if (o.trace) o.trace[pix] = TraceRec{t, t_entry, cell, status};
 }
 
@@ -355,7 +355,8 @@ __device__ __forceinline__ bool grab_batch(uint32_t* grab, uint32_t n, uint32_t 
   for (uint32_t k = 0; k < (uint32_t)kGroups; ++k) {
     const uint32_t x = (home + k) % (uint32_t)kGroups;
     const uint32_t end = (uint32_t)(((uint64_t)n * (x + 1)) / kGroups);
-    if (*(volatile uint32_t*)&grab[x * kGroupStride] >= end) continue;  // early-out; the atomic decides
+    if (__hip_atomic_load(&grab[x * kGroupStride], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= end)
+      continue;  // early-out; the atomic decides
     const uint32_t j = atomicAdd(&grab[x * kGroupStride], batch);
     if (j < end) {
       first = j;
@@ -905,7 +906,7 @@ __device__ __forceinline__ void march_eval2(const float* blk, int lane, int g, c
 
 // copies one packed per-cell block (words % 4 == 0) into LDS
 __device__ __forceinline__ void stage_block(float* lds, const float* src, uint32_t words) {
-  const f32x4* s = reinterpret_cast<const f32x4*>(src);
+  const auto s = gmem(reinterpret_cast<const f32x4*>(src));
   f32x4* d = reinterpret_cast<f32x4*>(lds);
   for (uint32_t i = threadIdx.x; i < words / 4u; i += blockDim.x) d[i] = s[i];
 }
@@ -965,29 +966,58 @@ struct Job {
   bool valid;
 };
 
-__device__ __forceinline__ Job read_job(const volatile uint32_t* s) {
+// (plain LDS reads: the workgroup barrier before every call orders them)
+__device__ __forceinline__ Job read_job(const uint32_t* s) {
   return Job{s[0], s[1], s[2], s[3], s[5], s[4] != 0u};
 }
 
-// thread 0: next work item into s[0..5] (cell, start, count, id, valid,
-// scene), from the batch [bat[0], bat[1]) or a new batch
-__device__ __forceinline__ void grab_job(const MarchArgs& a, uint32_t* s, uint32_t* bat) {
-  if (bat[0] >= bat[1]) {
-    uint32_t first, last;
-    if (!grab_batch(a.grab, *a.n_chunks, 2u, first, last)) {
-      s[4] = 0u;
-      return;
-    }
-    bat[0] = first;
-    bat[1] = last;
-  }
-  const uint32_t j = bat[0]++;
-  const uint2 c = a.chunks[j];
+// Thread 0's source of march work items.  Items are taken one at a time from
+// the workgroup's home range, and the atomic for the following item is issued
+// when one is taken, so its round trip overlaps the item in progress (the
+// workgroup holds at most two items; increments past the end of the range
+// are harmless).  Once the home range is used up the other ranges are visited
+// synchronously.
+// The cursor is advanced with an atomic increment (bound 2^32 - 1, so it
+// never wraps), which the compiler leaves alone, so the result is waited for
+// only where it is used.
+__device__ __forceinline__ uint32_t cursor_take(uint32_t* c) {
+  return __builtin_amdgcn_atomic_inc32(c, 0xFFFFFFFFu, __ATOMIC_RELAXED, "agent");
+}
+
+struct Grabber {
+  uint32_t n;        // work items in this launch
+  uint32_t end;      // end of the home range
+  uint32_t pend;     // result of the atomic issued ahead on the home range
+  uint32_t* cursor;  // the home range's cursor
+};
+
+__device__ __forceinline__ Grabber grab_init(uint32_t* grab, uint32_t n) {
+  const uint32_t home = blockIdx.x % (uint32_t)kGroups;
+  Grabber G;
+  G.n = n;
+  G.end = (uint32_t)(((uint64_t)n * (home + 1)) / kGroups);
+  G.cursor = grab + home * kGroupStride;
+  G.pend = cursor_take(G.cursor);
+  return G;
+}
+
+__device__ __forceinline__ bool grab_next(uint32_t* grab, Grabber& G, uint32_t& j) {
+  // taken into a scalar first, so the new atomic can reuse the register
+  j = (uint32_t)__builtin_amdgcn_readfirstlane((int)G.pend);
+  G.pend = cursor_take(G.cursor);
+  if (j < G.end) return true;
+  uint32_t last;
+  return grab_batch(grab, G.n, 1u, j, last);
+}
+
+// work item j (its descriptor c) into s[0..5] (cell, start, count, id,
+// valid, scene)
+__device__ __forceinline__ void put_job(const PoolTabs& t, uint32_t* s, uint2 c, uint32_t j) {
   s[0] = c.x & kCellMask;
   s[1] = c.y;
   s[2] = c.x >> kCellBits;
   s[3] = j;
-  s[5] = scene_of(a.tabs, s[0]);
+  s[5] = scene_of(t, s[0]);
   s[4] = 1u;
 }
 
@@ -1031,7 +1061,6 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
   float* s_w = reinterpret_cast<float*>(s_act + 2 * kChunk);      // weight block (16-byte aligned)
   __shared__ uint32_t s_job[6], s_jn[6];   // current / next work item: cell, start, count, id, valid, scene
-  __shared__ uint32_t s_bat[2];            // thread 0's batch of work items
   __shared__ uint32_t s_nact[2], s_pair;
   __shared__ uint32_t s_face[7], s_foff[7];
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
@@ -1046,9 +1075,12 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   RayStatic pf_st = {0, 0, 0, 0, 0, 0, 1, 0};
   bool pf_rec_ok = false, pf_st_ok = false;
   if (tid < kMaxSlots) s_miss[tid] = 0u;
+  Grabber G{0u, 0u, 0u, nullptr};   // thread 0's
   if (tid == 0) {
-    s_bat[0] = s_bat[1] = 0u;
-    grab_job(a, s_job, s_bat);
+    G = grab_init(a.grab, *a.n_chunks);
+    uint32_t j;
+    if (grab_next(a.grab, G, j)) put_job(a.tabs, s_job, a.chunks[j], j);
+    else s_job[4] = 0u;
   }
   for (;;) {
     if (tid == 0) {
@@ -1065,6 +1097,15 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     const Job jb = read_job(s_job);
     if (!jb.valid) break;
     const uint32_t cell = jb.cell, start = jb.start, count = jb.count, job = jb.id;
+    // thread 0 takes the next work item's index now and starts loading its
+    // descriptor; both round trips overlap the staging below
+    uint2 cn = make_uint2(0u, 0u);
+    uint32_t jn = 0;
+    bool jn_ok = false;
+    if (tid == 0) {
+      jn_ok = grab_next(a.grab, G, jn);
+      if (jn_ok) cn = a.chunks[jn];
+    }
     const SceneEnt* se = a.tabs.scenes + __builtin_amdgcn_readfirstlane(jb.scene);
     const SceneGeom sg = se->sg;
     const SoftplusK spk = se->spk;
@@ -1099,9 +1140,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     }
     pf_rec_ok = pf_st_ok = false;
     __syncthreads();
-    // thread 0 takes the next work item now; its wave catches up because
-    // the tile pairs of a pass are handed out dynamically
-    if (tid == 0) grab_job(a, s_jn, s_bat);
+    if (tid == 0 && jn_ok) put_job(a.tabs, s_jn, cn, jn);
 
     // passes over the rays still inside the cell; after max_passes the rest
     // go on in the next round (same cell), so a few slow rays near the
@@ -1529,19 +1568,19 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           smp = r.rid % q.spp;
           aux = pr.bounce == 0 && smp == 0;
         } else {
-          out.rgb[3 * px + 0] = rgb[0];
-          out.rgb[3 * px + 1] = rgb[1];
-          out.rgb[3 * px + 2] = rgb[2];
+          gmem(out.rgb)[3 * px + 0] = rgb[0];
+          gmem(out.rgb)[3 * px + 1] = rgb[1];
+          gmem(out.rgb)[3 * px + 2] = rgb[2];
         }
         if (aux) {
-          if (out.depth) out.depth[px] = t;
+          if (out.depth) gmem(out.depth)[px] = t;
           if (out.normal) {
-            out.normal[3 * px + 0] = n[0];
-            out.normal[3 * px + 1] = n[1];
-            out.normal[3 * px + 2] = n[2];
+            gmem(out.normal)[3 * px + 0] = n[0];
+            gmem(out.normal)[3 * px + 1] = n[1];
+            gmem(out.normal)[3 * px + 2] = n[2];
           }
-          if (out.hit) out.hit[px] = 1;
-          if (out.steps) out.steps[px] = (uint16_t)(r.key >> kCellBits);
+          if (out.hit) gmem(out.hit)[px] = 1;
+          if (out.steps) gmem(out.steps)[px] = (uint16_t)(r.key >> kCellBits);
           if (out.trace) out.trace[px] = TraceRec{r.t, r.t_entry, (int32_t)cell, kHit};
         }
         if constexpr (PT) {
