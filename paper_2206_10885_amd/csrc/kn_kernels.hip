@@ -405,10 +405,13 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
 }
 
 // Index of the pool scene that owns global cell `cell`.
-__device__ __forceinline__ uint32_t scene_of(const PoolTabs& t, uint32_t cell) {
+__device__ __forceinline__ uint32_t scene_index(const SceneEnt* scn, uint32_t n_scenes, uint32_t cell) {
   uint32_t k = 0;
-  while (k + 1u < t.n_scenes && cell >= t.scenes[k].cell_end) ++k;
+  while (k + 1u < n_scenes && cell >= scn[k].cell_end) ++k;
   return k;
+}
+__device__ __forceinline__ uint32_t scene_of(const PoolTabs& t, uint32_t cell) {
+  return scene_index(t.scenes, t.n_scenes, cell);
 }
 
 // Neighbour of `cell` through face f = 2 * axis + (positive side); f = 6 is
@@ -1012,12 +1015,12 @@ __device__ __forceinline__ bool grab_next(uint32_t* grab, Grabber& G, uint32_t& 
 
 // work item j (its descriptor c) into s[0..5] (cell, start, count, id,
 // valid, scene)
-__device__ __forceinline__ void put_job(const PoolTabs& t, uint32_t* s, uint2 c, uint32_t j) {
+__device__ __forceinline__ void put_job(const SceneEnt* scn, uint32_t n_scenes, uint32_t* s, uint2 c, uint32_t j) {
   s[0] = c.x & kCellMask;
   s[1] = c.y;
   s[2] = c.x >> kCellBits;
   s[3] = j;
-  s[5] = scene_of(t, s[0]);
+  s[5] = scene_index(scn, n_scenes, s[0]);
   s[4] = 1u;
 }
 
@@ -1065,6 +1068,11 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   __shared__ uint32_t s_face[7], s_foff[7];
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
   __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
+  // the pool's scene table and each request slot's eps and step budget,
+  // copied once: every work item reads them
+  __shared__ SceneEnt s_scn[kMaxScenes];
+  __shared__ float s_qeps[kMaxSlots];
+  __shared__ uint32_t s_qmst[kMaxSlots];
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
   unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
@@ -1074,12 +1082,24 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   RayRec pf_rec = {0, 0, 0, 0};
   RayStatic pf_st = {0, 0, 0, 0, 0, 0, 1, 0};
   bool pf_rec_ok = false, pf_st_ok = false;
-  if (tid < kMaxSlots) s_miss[tid] = 0u;
+  if (tid < kMaxSlots) {
+    s_miss[tid] = 0u;
+    s_qeps[tid] = a.tabs.reqs[tid].eps;
+    s_qmst[tid] = a.tabs.reqs[tid].max_steps;
+  }
+  {
+    static_assert(sizeof(SceneEnt) % 4 == 0, "scene entries are copied as words");
+    const uint32_t words = a.tabs.n_scenes * (uint32_t)(sizeof(SceneEnt) / 4);
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.tabs.scenes);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(s_scn);
+    for (uint32_t i = (uint32_t)tid; i < words; i += 256u) dst[i] = src[i];
+  }
+  __syncthreads();
   Grabber G{0u, 0u, 0u, nullptr};   // thread 0's
   if (tid == 0) {
     G = grab_init(a.grab, *a.n_chunks);
     uint32_t j;
-    if (grab_next(a.grab, G, j)) put_job(a.tabs, s_job, a.chunks[j], j);
+    if (grab_next(a.grab, G, j)) put_job(s_scn, a.tabs.n_scenes, s_job, a.chunks[j], j);
     else s_job[4] = 0u;
   }
   for (;;) {
@@ -1106,7 +1126,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       jn_ok = grab_next(a.grab, G, jn);
       if (jn_ok) cn = a.chunks[jn];
     }
-    const SceneEnt* se = a.tabs.scenes + __builtin_amdgcn_readfirstlane(jb.scene);
+    const SceneEnt* se = s_scn + __builtin_amdgcn_readfirstlane(jb.scene);
     const SceneGeom sg = se->sg;
     const SoftplusK spk = se->spk;
     const int H = HM ? HM : sg.H;
@@ -1120,7 +1140,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     if ((uint32_t)tid < count) {
       const RayRec r = pf_rec_ok ? pf_rec : a.S[start + tid];
       const RayStatic st = pf_st_ok ? pf_st : a.rs[r.rid];
-      const ReqEnt* q = a.tabs.reqs + (st.pix >> kPixBits);
+      const uint32_t qs = st.pix >> kPixBits;
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
       int eax;
       const float ce = cell_exit(sg, cb, o, d, &eax);
@@ -1132,15 +1152,15 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
       s_tf[tid] = st.t_far;
       s_ce[tid] = ce;
-      s_eps[tid] = q->eps;
+      s_eps[tid] = s_qeps[qs];
       s_rid[tid] = r.rid;
       s_pix[tid] = st.pix;
-      s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10) | (q->max_steps << 16);
+      s_st[tid] = (r.key >> kCellBits) | ((uint32_t)eax << 10) | (s_qmst[qs] << 16);
       s_act[tid] = (uint16_t)tid;
     }
     pf_rec_ok = pf_st_ok = false;
     __syncthreads();
-    if (tid == 0 && jn_ok) put_job(a.tabs, s_jn, cn, jn);
+    if (tid == 0 && jn_ok) put_job(s_scn, a.tabs.n_scenes, s_jn, cn, jn);
 
     // passes over the rays still inside the cell; after max_passes the rest
     // go on in the next round (same cell), so a few slow rays near the
@@ -1274,7 +1294,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         const uint32_t px = s_pix[tid];
         slot = px >> kPixBits;
         miss = true;
-        const ReqEnt& q = a.tabs.reqs[slot];
+        const ReqEnt q = a.tabs.reqs[slot];   // copied before the first store
         const int32_t mst = status == kOutExit ? kExitMiss : kBudgetMiss;
         if (q.pt) {
           // the path escapes: radiance += throughput x environment
@@ -1556,7 +1576,9 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
       uint32_t ncell = 0;
       RayRec nrec{0, 0, 0, 0};
       if (writer) {
-        const ReqEnt& q = a.tabs.reqs[slot];
+        // copied before the first store, so all its fields load together
+        // (a store through an output pointer could otherwise alias the table)
+        const ReqEnt q = a.tabs.reqs[slot];
         const OutPtrs& out = q.out;
         const uint32_t px = st.pix & kPixMask;
         const float rgb[3] = {sigmoid(c2[0]), sigmoid(c2[1]), sigmoid(c2[2])};
