@@ -907,12 +907,25 @@ __device__ __forceinline__ void march_eval2(const float* blk, int lane, int g, c
   else march_eval2_f32<H>(blk, lane, g, v0, v1, k, f0, f1);
 }
 
-// copies one packed per-cell block (words % 4 == 0) into LDS
+// Copies one packed per-cell block (words % 4 == 0, 16-byte aligned at both
+// ends) into LDS with direct global-to-LDS loads: 16 bytes per lane, so one
+// wave instruction fills 1 KB, and all of a thread's loads are in flight at
+// once without passing through registers.  stage_wait() must precede the
+// barrier after which the block is read.
 __device__ __forceinline__ void stage_block(float* lds, const float* src, uint32_t words) {
-  const auto s = gmem(reinterpret_cast<const f32x4*>(src));
-  f32x4* d = reinterpret_cast<f32x4*>(lds);
-  for (uint32_t i = threadIdx.x; i < words / 4u; i += blockDim.x) d[i] = s[i];
+  const uint32_t n4 = words / 4u, lane = threadIdx.x & 63u;
+  const uint32_t nw = blockDim.x >> 6;
+  for (uint32_t c = threadIdx.x >> 6; c * 64u < n4; c += nw) {
+    const uint32_t i = c * 64u + lane;
+    if (i < n4)
+      __builtin_amdgcn_global_load_lds(
+          (const __attribute__((address_space(1))) void*)(src + 4u * i),
+          (__attribute__((address_space(3))) void*)(lds + 256u * c), 16, 0, 0);
+  }
 }
+
+// the wave's direct-to-LDS loads have landed
+__device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 struct CellBox {
   int ix, iy, iz;
@@ -1159,6 +1172,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       s_act[tid] = (uint16_t)tid;
     }
     pf_rec_ok = pf_st_ok = false;
+    stage_wait();
     __syncthreads();
     if (tid == 0 && jn_ok) put_job(s_scn, a.tabs.n_scenes, s_jn, cn, jn);
 
@@ -1462,6 +1476,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
     const uint32_t lc = cell - sg.cell_base;
     if (cell != loaded) {
       stage_block(s_block, se->shade + (size_t)lc * se->shade_words, se->shade_words);
+      stage_wait();
       __syncthreads();
       loaded = cell;
     }
@@ -1695,6 +1710,7 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
     const uint32_t lc = cell - sg.cell_base;
     if (cell != loaded) {
       stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_wait();
       __syncthreads();
       loaded = cell;
     }
@@ -1733,6 +1749,7 @@ __global__ __launch_bounds__(256) void k_query_full(QueryArgs a) {
     const uint32_t lc = cell - sg.cell_base;
     if (cell != loaded) {
       stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_wait();
       __syncthreads();
       loaded = cell;
     }
