@@ -40,21 +40,31 @@ __device__ __forceinline__ void atomic_count_grouped(uint32_t* arr, uint32_t key
   }
 }
 
+// Reserves a slot in arr[key] for every valid lane.  The lanes are grouped by
+// key first (ballots only); then each group's first lane adds the group's size
+// with one atomic, all groups in the same instruction, so the wave waits for
+// a single round trip however many keys it holds.
 __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t key, bool valid) {
+  const int lane = lane_id();
   uint64_t todo = __ballot(valid);
-  uint32_t pos = 0;
+  int leader = lane;
+  uint32_t rank = 0, size = 0;
   while (todo) {
-    int leader = __ffsll((unsigned long long)todo) - 1;
-    uint32_t lk = __shfl(key, leader);
-    bool mine = valid && key == lk;
-    uint64_t grp = __ballot(mine);
-    uint32_t base = 0;
-    if (lane_id() == leader) base = atomicAdd(&arr[lk], (uint32_t)__popcll(grp));
-    base = __shfl(base, leader);
-    if (mine) pos = base + (uint32_t)__popcll(grp & lanemask_lt());
+    const int l = __ffsll((unsigned long long)todo) - 1;
+    const uint32_t lk = __shfl(key, l);
+    const bool mine = valid && key == lk;
+    const uint64_t grp = __ballot(mine);
+    if (mine) {
+      leader = l;
+      rank = (uint32_t)__popcll(grp & lanemask_lt());
+    }
+    if (lane == l) size = (uint32_t)__popcll(grp);
     todo &= ~grp;
   }
-  return pos;
+  uint32_t base = 0;
+  if (valid && lane == leader) base = atomicAdd(&arr[key], size);
+  base = (uint32_t)__shfl((int)base, leader);
+  return base + rank;
 }
 
 // Adds the workgroup's count of `flag` to *counter with one global atomic

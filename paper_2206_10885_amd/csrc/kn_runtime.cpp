@@ -453,7 +453,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   }
   if (n_new) {
     ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor, 0};
-    KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_new + 255u) / 256u, 4096u), st));
+    KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_new + 255u) / 256u, 65536u), st));
   }
   if (n_new_dev) {
     ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor, 0};
@@ -500,7 +500,7 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sa.total = &w.ctrl->n_hits;
   KN_HIP(ctx, launch_scan(sa, st));
   ScatterArgs sc{w.HL, w.S, n_ids, nullptr, w.cursor, 1};
-  KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_ids + 255u) / 256u, 4096u), st));
+  KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_ids + 255u) / 256u, 65536u), st));
   ShadeArgs sh{};
   sh.tabs = pool_tabs(w, c.n_scenes);
   sh.S = w.S;
@@ -1031,7 +1031,7 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
   ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0};
-  KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 4096), stream));
+  KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536), stream));
   QueryArgs qa{};
   qa.sg = s->geom;
   qa.S = w.S;
