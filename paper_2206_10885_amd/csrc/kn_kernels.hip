@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_resolve(ResolveArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// per-round scan (one workgroup): bin starts, scatter cursors, work chunks
+// per-round scan: bin starts, scatter cursors, work chunks
 // ---------------------------------------------------------------------------
 // Inclusive prefix sum over the 64 lanes of a wave on DPP: four row shifts
 // build the sums inside each row of 16 lanes, then the last lane of row 0 is
@@ -258,96 +258,129 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
 
 __device__ __forceinline__ uint32_t lane63(uint32_t v) { return (uint32_t)__builtin_amdgcn_readlane((int)v, 63); }
 
-typedef uint32_t u32x32 __attribute__((ext_vector_type(32)));
-
-// counts of 32 steps of 64 cells from b on (lane's cell of each step; 0 past e)
-__device__ __forceinline__ u32x32 load_steps(const uint32_t* counts, uint32_t b, uint32_t e, uint32_t lane) {
-  u32x32 v;
-#pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    const uint32_t c = b + 64u * (uint32_t)q + lane;
-    v[q] = c < e ? counts[c] : 0u;
-  }
-  return v;
-}
-
-// One workgroup of 16 waves.  Wave w owns the contiguous strip of cells
-// [w*S, (w+1)*S), S a multiple of 64, and walks it 64 cells at a time with one
-// cell per lane, so that every load and store of a wave covers consecutive
-// words; counts are loaded 32 steps at a time (the first 32 stay in registers
-// for the second sweep).  The first sweep sums the strip; the strip offsets
-// come from a scan of the 16 wave sums; the second sweep scans each step of
-// 64 cells across the lanes and carries the step total to the next.  Cells
-// are visited in increasing order, so bins and chunks are laid out in cell
-// order.  Empty cells are not written: their cursor is never read and their
-// count is already zero.  T is a power of two.
-__global__ __launch_bounds__(1024) void k_scan(ScanArgs a) {
-  __shared__ uint32_t s_wr[16], s_wk[16];
-  const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id(), wave = tid >> 6;
+// The scan runs as kScanTiles workgroups of 4 waves; workgroup g owns the
+// cell tile [g*TS, (g+1)*TS) and wave w of it the strip of SW cells at w*SW
+// (TS, SW multiples of 64).  A wave walks its strip 64 cells at a time, one
+// cell per lane, so that every load and store covers consecutive words.
+//  1. each wave sums its strip; the 4 sums are scanned into wave offsets and
+//     the tile's sums;
+//  2. the tile publishes its sums (tagged with the launch's epoch) and adds
+//     up those of the tiles before it as they appear (decoupled look-back).
+//     Tiles are numbered by a ticket taken at start, so a tile only waits for
+//     tiles that started before it and never wait themselves: every wait
+//     ends.  The last tile writes the totals and the work cursors;
+//  3. each wave scans every step of 64 cells across the lanes, carrying the
+//     step total, and writes the bin starts and the chunks of its cells.
+// Cells are visited in increasing order, so bins and chunks are laid out in
+// cell order.  Empty cells are not written: their cursor is never read and
+// their count is already zero.  T is a power of two.
+__global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
+  __shared__ uint32_t s_tile, s_wr[4], s_wk[4], s_base[2];
+  const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id();
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(tid >> 6));
+  if (tid == 0) s_tile = atomicAdd(a.ticket, 1u);
+  __syncthreads();
+  const uint32_t ticket = (uint32_t)__builtin_amdgcn_readfirstlane((int)s_tile);
+  const uint32_t g = ticket % kScanTiles;
+  const unsigned long long epoch = (unsigned long long)(ticket / kScanTiles + 1u) << 32;
   const uint32_t tm = a.T - 1u, ts = (uint32_t)__builtin_ctz(a.T);
-  const uint32_t S = ((a.C + 1023u) >> 10) << 6;
-  const uint32_t s0 = wave * S, s1 = min(a.C, s0 + S);
+  const uint32_t TS = ((a.C + 64u * kScanTiles - 1u) / (64u * kScanTiles)) * 64u;
+  const uint32_t SW = ((TS / 64u + 3u) / 4u) * 64u;
+  const uint32_t t0 = min(a.C, g * TS), t1 = min(a.C, t0 + TS);
+  const uint32_t s0 = min(t1, t0 + wave * SW), s1 = min(t1, s0 + SW);
+  const uint32_t nst = (s1 - s0 + 63u) >> 6;   // steps of 64 cells in this strip
+  const uint32_t* counts = a.counts;
   uint32_t sr = 0, sk = 0;
-  u32x32 first = load_steps(a.counts, s0, s1, lane);
+  for (uint32_t q = 0; q < nst; q += 8u) {
+    uint32_t v[8];
 #pragma unroll
-  for (int q = 0; q < 32; ++q) {
-    sr += first[q];
-    sk += (first[q] + tm) >> ts;
-  }
-  for (uint32_t b = s0 + 2048u; b < s1; b += 2048u) {
-    const u32x32 v = load_steps(a.counts, b, s1, lane);
+    for (int u = 0; u < 8; ++u) {
+      const uint32_t c = s0 + 64u * (q + (uint32_t)u) + lane;
+      v[u] = c < s1 ? counts[c] : 0u;
+    }
 #pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      sr += v[q];
-      sk += (v[q] + tm) >> ts;
+    for (int u = 0; u < 8; ++u) {
+      sr += v[u];
+      sk += (v[u] + tm) >> ts;
     }
   }
-  const uint32_t tr = lane63(wave_incl_scan(sr)), tk = lane63(wave_incl_scan(sk));
+  const uint32_t wr = lane63(wave_incl_scan(sr)), wk = lane63(wave_incl_scan(sk));
   if (lane == 0) {
-    s_wr[wave] = tr;
-    s_wk[wave] = tk;
+    s_wr[wave] = wr;
+    s_wk[wave] = wk;
   }
   __syncthreads();
   if (wave == 0) {
-    const uint32_t vr = lane < 16 ? s_wr[lane] : 0u, vk = lane < 16 ? s_wk[lane] : 0u;
+    const uint32_t vr = lane < 4u ? s_wr[lane] : 0u, vk = lane < 4u ? s_wk[lane] : 0u;
     const uint32_t ir = wave_incl_scan(vr), ik = wave_incl_scan(vk);
-    if (lane < 16) {
+    if (lane < 4u) {
       s_wr[lane] = ir - vr;
       s_wk[lane] = ik - vk;
     }
-    const uint32_t nch = lane63(ik);
-    if (lane == 15) {
-      *a.n_chunks = nch;
-      if (a.zero_word) *a.zero_word = 0u;
-      if (a.total) *a.total += ir;
+    const uint32_t tr = lane63(ir), tk = lane63(ik);
+    if (lane == 0) {
+      __hip_atomic_store(&a.flags[2 * g], epoch | tr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&a.flags[2 * g + 1], epoch | tk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (lane < (uint32_t)kGroups) {
-      const uint32_t g0 = (uint32_t)(((uint64_t)nch * lane) / kGroups);
-      a.grab[lane * kGroupStride] = g0;
-      a.grab0[lane * kGroupStride] = g0;
+    // look back: lane j < g waits for tile j's sums
+    uint32_t pr = 0, pk = 0;
+    if (lane < g) {
+      for (uint32_t it = 0;; ++it) {
+        const unsigned long long fr =
+            __hip_atomic_load(&a.flags[2 * lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned long long fk =
+            __hip_atomic_load(&a.flags[2 * lane + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((fr & ~0xFFFFFFFFull) == epoch && (fk & ~0xFFFFFFFFull) == epoch) {
+          pr = (uint32_t)fr;
+          pk = (uint32_t)fk;
+          break;
+        }
+        if (it == (1u << 22)) {   // bound on the wait (never reached)
+          atomicOr(a.err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+    const uint32_t br = lane63(wave_incl_scan(pr)), bk = lane63(wave_incl_scan(pk));
+    if (lane == 0) {
+      s_base[0] = br;
+      s_base[1] = bk;
+    }
+    if (g == kScanTiles - 1u) {
+      const uint32_t nch = bk + tk;
+      if (lane == 0) {
+        *a.n_chunks = nch;
+        if (a.zero_word) *a.zero_word = 0u;
+        if (a.total) *a.total += br + tr;
+      }
+      if (lane < (uint32_t)kGroups) {
+        const uint32_t g0 = (uint32_t)(((uint64_t)nch * lane) / kGroups);
+        a.grab[lane * kGroupStride] = g0;
+        a.grab0[lane * kGroupStride] = g0;
+      }
     }
   }
   __syncthreads();
-  uint32_t R = s_wr[wave], K = s_wk[wave];
-  for (uint32_t b = s0; b < s1; b += 2048u) {
-    const u32x32 v = b == s0 ? first : load_steps(a.counts, b, s1, lane);
-#pragma unroll
-    for (int q = 0; q < 32; ++q) {
-      if (b + 64u * (uint32_t)q >= s1) break;
-      const uint32_t c = b + 64u * (uint32_t)q + lane;
-      const uint32_t n = v[q];
-      const uint32_t k = (n + tm) >> ts;
-      const uint32_t ir = wave_incl_scan(n), ik = wave_incl_scan(k);
-      if (n) {
-        const uint32_t r = R + ir - n;
-        uint32_t j = K + ik - k;
-        a.cursor[c] = r;
-        for (uint32_t i = 0; i < n; i += a.T) a.chunks[j++] = make_uint2(c | (min(a.T, n - i) << kCellBits), r + i);
-        if (a.zero_counts) a.counts[c] = 0u;
-      }
-      R += lane63(ir);
-      K += lane63(ik);
+  uint32_t R = s_base[0] + s_wr[wave], K = s_base[1] + s_wk[wave];
+  uint32_t c = s0 + lane;
+  uint32_t n1 = c < s1 ? counts[c] : 0u;
+  uint32_t n2 = c + 64u < s1 ? counts[c + 64u] : 0u;
+  for (uint32_t q = 0; q < nst; ++q, c += 64u) {
+    const uint32_t n = n1;
+    n1 = n2;
+    n2 = c + 128u < s1 ? counts[c + 128u] : 0u;
+    const uint32_t k = (n + tm) >> ts;
+    const uint32_t ir = wave_incl_scan(n), ik = wave_incl_scan(k);
+    if (n) {
+      const uint32_t r = R + ir - n;
+      uint32_t j = K + ik - k;
+      a.cursor[c] = r;
+      for (uint32_t i = 0; i < n; i += a.T) a.chunks[j++] = make_uint2(c | (min(a.T, n - i) << kCellBits), r + i);
+      if (a.zero_counts) a.counts[c] = 0u;
     }
+    R += lane63(ir);
+    K += lane63(ik);
   }
 }
 
@@ -1801,7 +1834,8 @@ hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st) {
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t st) {
   if (a.T == 0 || a.T > 512 || (a.T & (a.T - 1u)) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, a);
+  if (!a.ticket || !a.flags || !a.err) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_scan, dim3(kScanTiles), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -100,6 +100,9 @@ struct ScanArgs {
   uint32_t* grab0;       // out: a copy of the initial cursors (to restart a pass)
   uint32_t* zero_word;   // optional counter reset to 0
   uint32_t* total;       // optional: the sum of the counts is added to it
+  uint32_t* ticket;      // Ctrl::scan_ticket
+  unsigned long long* flags;  // Ctrl::scan_flags
+  uint32_t* err;         // Ctrl::scan_err
 };
 
 struct ScatterArgs {

@@ -438,6 +438,9 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   sa.n_chunks = &w.ctrl->n_chunks[par];
   sa.grab = w.ctrl->grab;
   sa.grab0 = w.ctrl->grab0;
+  sa.ticket = &w.ctrl->scan_ticket;
+  sa.flags = w.ctrl->scan_flags;
+  sa.err = &w.ctrl->scan_err;
   sa.zero_word = nullptr;
   sa.total = nullptr;
   KN_HIP(ctx, launch_scan(sa, st));
@@ -496,6 +499,9 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sa.n_chunks = &w.ctrl->n_chunks[2];
   sa.grab = w.ctrl->grab;
   sa.grab0 = w.ctrl->grab0;
+  sa.ticket = &w.ctrl->scan_ticket;
+  sa.flags = w.ctrl->scan_flags;
+  sa.err = &w.ctrl->scan_err;
   sa.zero_word = pt ? &w.ctrl->n_in : nullptr;
   sa.total = &w.ctrl->n_hits;
   KN_HIP(ctx, launch_scan(sa, st));
@@ -942,6 +948,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   if (stats) {
     Ctrl hc;
     KN_HIP(ctx, hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (hc.scan_err) return fail(KN_E_DEVICE, "cell scan: a look-back wait ran out");
     float ms = 0.0f;
     KN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_end));
     stats->gpu_ms = ms;
@@ -1028,6 +1035,9 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.n_chunks = &w.ctrl->n_chunks[0];
   sa.grab = w.ctrl->grab;
   sa.grab0 = w.ctrl->grab0;
+  sa.ticket = &w.ctrl->scan_ticket;
+  sa.flags = w.ctrl->scan_flags;
+  sa.err = &w.ctrl->scan_err;
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
   ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0};
