@@ -6,8 +6,10 @@ initialisation toward a sphere of radius 0.6 with N(0, 0.02^2) noise,
 1920x1080 primary rays per frame, 8 seeded orbit views cycled, at most 128
 sphere-tracing steps, eps 1e-4.  One step = one frame (2,073,600 rays)
 through every stage: ray generation and box clip, per-round cell binning,
-the march (bfloat16 MLP on MFMA), hit binning, refinement and shading.
-The same frames are then timed with the float32 march for the ratio.
+the march (bfloat16 MLP on MFMA), hit binning, refinement and shading (the
+SDF MLP's products on bfloat16 MFMA with hi/lo split operands, about 2^-16
+relative error each).  The same frames are then timed with the float32 march
+and float32 shading for the ratio.
 
 Prints one JSON line: metric, value, unit, timing, dtype, config, the
 roofline of the dominant kernel and the oracle's CPU rate.
@@ -212,8 +214,8 @@ def serve_bench(n_req: int, torch) -> dict:
 
 def pathtrace_bench(torch, frames: int = 3) -> dict:
     """32^3 grid, H=64, 1920x1080, 4 spp, 3 Lambertian bounces, 512x256
-    environment; FP8 e4m3 march against bfloat16 (refinement and shading in
-    float32)."""
+    environment; FP8 e4m3 march against bfloat16 (refinement and shading on
+    split-bfloat16 MFMA)."""
     from paper_2206_10885_amd import kn, synth
     c = synth.CONFIGS["c5"]
     sc = synth.config_scene("c5")
@@ -310,7 +312,9 @@ def main():
         "config": {"workload": "C3: 16^3 grid of per-cell SDF MLPs (39->2x64 softplus->16) and "
                                "color MLPs (48->32->3), 1920x1080, 8 seeded orbit views, "
                                "<=128 steps, eps 1e-4; march in " + args.precision +
-                               ", refinement and shading in fp32",
+                               (", refinement and shading in fp32" if args.precision == "fp32" else
+                                ", refinement and shading on split-bf16 MFMA (hi/lo operands, "
+                                "~2^-16 per product)"),
                    "rays_per_frame": rays, "views": len(views)},
         "frame_ms_p50": pct(r["gpu_ms"], 50),
         "frame_ms_p99": pct(r["gpu_ms"], 99),

@@ -1456,6 +1456,107 @@ __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, boo
   return y;
 }
 
+// ---------------------------------------------------------------------------
+// The same SDF MLP (value and tangent columns) on bfloat16 MFMA with split
+// operands: every weight w is hi + lo with hi = bf16(w), lo = bf16(w - hi)
+// (packed on the host), every layer input x likewise (split here), and each
+// product is wh*xh + wh*xl + wl*xh, accumulated in float32; the dropped wl*xl
+// term and the rounding of the lo parts leave a relative error of about 2^-16
+// per product.  Fragment layout of the bf16 march (units in unit_bf16 order),
+// biases and activations as in sdf_full.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void split_bf16x8(const float (&x)[8], bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const __bf16 h = (__bf16)x[i];
+    hi[i] = h;
+    lo[i] = (__bf16)(x[i] - (float)h);
+  }
+}
+
+__device__ __forceinline__ f32x4 mfma_split(uint4 wh, uint4 wl, bf16x8 xh, bf16x8 xl, f32x4 c) {
+  c = mfma_bf16(__builtin_bit_cast(bf16x8, wl), xh, c);
+  c = mfma_bf16(__builtin_bit_cast(bf16x8, wh), xl, c);
+  return mfma_bf16(__builtin_bit_cast(bf16x8, wh), xh, c);
+}
+
+template <int H, int C = 4>
+__device__ __forceinline__ f32x4 sdf_full3(const float* blk, int lane, int g, bool value_col,
+                                           const float (&v)[kPeSlots], SoftplusK k) {
+  constexpr int NB = H / 16, F1 = NB * 2, F2 = F1 + NB * (H / 32), NF = shade3_frags(H);
+  const uint4* fh = reinterpret_cast<const uint4*>(blk);
+  const uint4* fl = fh + NF * 64;
+  const float* vec = blk + 2 * 256 * NF + 64 * 32;
+  bf16x8 eh[2], el[2];
+  {
+    float x0[8], x1[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      x0[i] = v[i];
+      x1[i] = i < kPeSlots - 8 ? v[8 + i] : 0.0f;
+    }
+    split_bf16x8(x0, eh[0], el[0]);
+    split_bf16x8(x1, eh[1], el[1]);
+  }
+  f32x4 acc[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    acc[b] = value_col ? *reinterpret_cast<const f32x4*>(vec + 16 * b + 4 * g) : f32x4{0, 0, 0, 0};
+    const uint4 h0 = fh[(2 * b) * 64 + lane], h1 = fh[(2 * b + 1) * 64 + lane];
+    const uint4 l0 = fl[(2 * b) * 64 + lane], l1 = fl[(2 * b + 1) * 64 + lane];
+    acc[b] = mfma_split(h0, l0, eh[0], el[0], acc[b]);
+    acc[b] = mfma_split(h1, l1, eh[1], el[1], acc[b]);
+  }
+  float a1[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float ds;
+      const float sp = softplus_d(acc[b][r], k, &ds);
+      const float dv = group_bcast<C>(ds);
+      a1[b][r] = value_col ? sp : dv * acc[b][r];
+    }
+  f32x4 acc2[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+    acc2[b] = value_col ? *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g) : f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c) {
+    float x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = a1[2 * c + i / 4][i % 4];
+    bf16x8 xh, xl;
+    split_bf16x8(x, xh, xl);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      const int f = F1 + b * (H / 32) + c;
+      acc2[b] = mfma_split(fh[f * 64 + lane], fl[f * 64 + lane], xh, xl, acc2[b]);
+    }
+  }
+  float a2[NB][4];
+#pragma unroll
+  for (int b = 0; b < NB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float ds;
+      const float sp = softplus_d(acc2[b][r], k, &ds);
+      const float dv = group_bcast<C>(ds);
+      a2[b][r] = value_col ? sp : dv * acc2[b][r];
+    }
+  f32x4 y = value_col ? *reinterpret_cast<const f32x4*>(vec + 2 * H + 4 * g) : f32x4{0, 0, 0, 0};
+#pragma unroll
+  for (int c = 0; c < H / 32; ++c) {
+    float x[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) x[i] = a2[2 * c + i / 4][i % 4];
+    bf16x8 xh, xl;
+    split_bf16x8(x, xh, xl);
+    y = mfma_split(fh[(F2 + c) * 64 + lane], fl[(F2 + c) * 64 + lane], xh, xl, y);
+  }
+  return y;
+}
+
 // Encoding slot e (0..32) of the color input [x_l(3), gamma_4(v)(27), n(3)].
 __device__ __forceinline__ float color_in_slot(int e, const float xl[3], const float v[3],
                                                const float n[3]) {
@@ -1473,10 +1574,17 @@ __device__ __forceinline__ float color_in_slot(int e, const float xl[3], const f
 // ---------------------------------------------------------------------------
 // shading: per chunk of a cell's hits; each wave shades 4 hits per tile
 // ---------------------------------------------------------------------------
-template <int HM, int C = 4>
+template <int HM, int C = 4, bool B3 = false>
 __device__ __forceinline__ f32x4 sdf_full_h(int H, const float* blk, int lane, int g, bool value_col,
                                             const float (&v)[kPeSlots], SoftplusK k) {
-  if constexpr (HM != 0) {
+  if constexpr (B3) {
+    if constexpr (HM != 0) {
+      return sdf_full3<HM, C>(blk, lane, g, value_col, v, k);
+    } else {
+      if (H == 64) return sdf_full3<64, C>(blk, lane, g, value_col, v, k);
+      return sdf_full3<32, C>(blk, lane, g, value_col, v, k);
+    }
+  } else if constexpr (HM != 0) {
     return sdf_full<HM, C>(blk, lane, g, value_col, v, k);
   } else {
     if (H == 64) return sdf_full<64, C>(blk, lane, g, value_col, v, k);
@@ -1485,10 +1593,12 @@ __device__ __forceinline__ f32x4 sdf_full_h(int H, const float* blk, int lane, i
 }
 
 // PT: path tracing; the hit scatters (Lambertian, albedo = color MLP) or
-// ends its path; otherwise the color is the pixel's rgb.
+// ends its path; otherwise the color is the pixel's rgb.  B3: the SDF MLP
+// from the split-bfloat16 block (pools marching in bf16 or fp8), else from
+// the float32 block.
 // 3 waves per SIMD: the shading chain (MFMA -> softplus -> MFMA) is
 // latency-bound, and 3 waves fit in the register file without spills
-template <int HM, bool PT>
+template <int HM, bool PT, bool B3>
 __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
   extern __shared__ __align__(16) float s_mem[];
   float* s_stage = s_mem;                 // 4 waves x 4 hits x 48
@@ -1523,8 +1633,10 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
       __syncthreads();
       loaded = cell;
     }
-    const float* vec = s_block + 64 * shade_frag_slots(H);
-    const int SC1 = (H / 16) * kPeSlots + (H / 16) * (H / 4) + H / 4;  // first color fragment slot
+    // colour fragments (one float per lane) and the bias vector
+    const float* cfr = B3 ? s_block + 2 * 256 * shade3_frags(H)
+                          : s_block + 64 * ((H / 16) * kPeSlots + (H / 16) * (H / 4) + H / 4);
+    const float* vec = cfr + 64 * 32;
     const CellBox cb = cell_box(sg, lc);
     float* stage = s_stage + wave * 4 * kColIn;
     // each wave takes 8 hits: two 2-column passes (value and derivative
@@ -1556,7 +1668,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           float v[kPeSlots];
           pe_values_dir(pl, sA == 0, d[0] * sg.inv_half[0], d[1] * sg.inv_half[1], d[2] * sg.inv_half[2],
                         xl[0], xl[1], xl[2], v);
-          const f32x4 y = sdf_full_h<HM, 2>(H, s_block, lane, g, sA == 0, v, spk);
+          const f32x4 y = sdf_full_h<HM, 2, B3>(H, s_block, lane, g, sA == 0, v, spk);
           const float f0 = __shfl(y[0], 2 * hA), gd = __shfl(y[0], 2 * hA + 1);
           if (gd < -1e-3f) tA = fminf(fmaxf(tA - f0 / gd, r.t_entry), ce);
         }
@@ -1584,7 +1696,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
         float v[kPeSlots];
         const float ih = s == 1 ? sg.inv_half[0] : s == 2 ? sg.inv_half[1] : s == 3 ? sg.inv_half[2] : 0.0f;
         pe_values_tangent(pl, s, ih, xl[0], xl[1], xl[2], v);
-        y = sdf_full_h<HM>(H, s_block, lane, g, value_col, v, spk);
+        y = sdf_full_h<HM, 4, B3>(H, s_block, lane, g, value_col, v, spk);
         const int src = 4 * h;
         gr[0] = __shfl(y[0], src + 1);
         gr[1] = __shfl(y[0], src + 2);
@@ -1622,12 +1734,12 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
       for (int q = 0; q < 12; ++q) {
         const float bq = stage[h * kColIn + 4 * q + g];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) c1[b] = mfma_f32(s_block[(SC1 + b * 12 + q) * 64 + lane], bq, c1[b]);
+        for (int b = 0; b < 2; ++b) c1[b] = mfma_f32(cfr[(b * 12 + q) * 64 + lane], bq, c1[b]);
       }
       f32x4 c2 = g == 0 ? *reinterpret_cast<const f32x4*>(vc + 32) : f32x4{0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        c2 = mfma_f32(s_block[(SC1 + 24 + q) * 64 + lane], fmaxf(c1[q / 4][q % 4], 0.0f), c2);
+        c2 = mfma_f32(cfr[(24 + q) * 64 + lane], fmaxf(c1[q / 4][q % 4], 0.0f), c2);
       const bool writer = valid && g == 0 && value_col;
       const uint32_t slot = st.pix >> kPixBits;
       bool done = writer, spawn = false;
@@ -1879,18 +1991,21 @@ hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_word
   return hipErrorInvalidValue;
 }
 
-template <bool PT>
+template <bool PT, bool B3>
 static hipError_t shade_t(const ShadeArgs& a, int H, size_t lds, uint32_t grid, hipStream_t st) {
-  if (H == 32) hipLaunchKernelGGL((k_shade<32, PT>), dim3(grid), dim3(256), lds, st, a);
-  else if (H == 64) hipLaunchKernelGGL((k_shade<64, PT>), dim3(grid), dim3(256), lds, st, a);
-  else if (H == 0) hipLaunchKernelGGL((k_shade<0, PT>), dim3(grid), dim3(256), lds, st, a);
+  if (H == 32) hipLaunchKernelGGL((k_shade<32, PT, B3>), dim3(grid), dim3(256), lds, st, a);
+  else if (H == 64) hipLaunchKernelGGL((k_shade<64, PT, B3>), dim3(grid), dim3(256), lds, st, a);
+  else if (H == 0) hipLaunchKernelGGL((k_shade<0, PT, B3>), dim3(grid), dim3(256), lds, st, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const ShadeArgs& a, int H, bool pt, uint32_t block_words, uint32_t grid, hipStream_t st) {
+hipError_t launch_shade(const ShadeArgs& a, int H, int prec, bool pt, uint32_t block_words, uint32_t grid,
+                        hipStream_t st) {
   const size_t lds = shade_lds_bytes(block_words);
-  return pt ? shade_t<true>(a, H, lds, grid, st) : shade_t<false>(a, H, lds, grid, st);
+  const bool b3 = prec != kPrecF32;
+  if (pt) return b3 ? shade_t<true, true>(a, H, lds, grid, st) : shade_t<true, false>(a, H, lds, grid, st);
+  return b3 ? shade_t<false, true>(a, H, lds, grid, st) : shade_t<false, false>(a, H, lds, grid, st);
 }
 
 hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st) {

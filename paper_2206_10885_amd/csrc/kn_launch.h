@@ -188,7 +188,10 @@ size_t march_lds_bytes(uint32_t block_words);
 size_t shade_lds_bytes(uint32_t block_words);
 hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_words, uint32_t grid,
                         hipStream_t st);
-hipError_t launch_shade(const ShadeArgs& a, int H, bool pt, uint32_t block_words, uint32_t grid, hipStream_t st);
+// prec: the pool's march precision; float32 pools shade with the float32
+// block, bf16 and fp8 pools with the split-bfloat16 block
+hipError_t launch_shade(const ShadeArgs& a, int H, int prec, bool pt, uint32_t block_words, uint32_t grid,
+                        hipStream_t st);
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st);
 hipError_t launch_query_d(const QueryArgs& a, int H, int prec, uint32_t grid, hipStream_t st);
 hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream_t st);

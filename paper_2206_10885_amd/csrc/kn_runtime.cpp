@@ -228,6 +228,45 @@ static void pack_shade(const float* blk, const float* cblk, int H, float* out) {
   vec[2 * H + 16 + kColHid + 3] = 0.0f;
 }
 
+// Split-bfloat16 shading block: every weight w of the SDF MLP as hi =
+// bf16(w) and lo = bf16(w - hi), in the bf16 march's fragment layout (W1, W2
+// and W3 unhalved, all 16 rows of W3); the colour fragments and the biases
+// are the float32 block's.
+static void pack_shade3(const float* blk, const float* cblk, int H, float* out_words) {
+  const SdfView w = sdf_view(blk, H);
+  const int NB = H / 16, F1 = NB * 2, F2 = F1 + NB * (H / 32), NF = shade3_frags(H);
+  uint16_t* hi = reinterpret_cast<uint16_t*>(out_words);
+  uint16_t* lo = hi + (size_t)NF * 64 * 8;
+  for (int f = 0; f < NF; ++f)
+    for (int lane = 0; lane < 64; ++lane) {
+      const int m = lane % 16, g = lane / 16;
+      for (int i = 0; i < 8; ++i) {
+        float val;
+        if (f < F1) {
+          const int b = f / 2, c = f % 2, j = 8 * c + i;
+          const int idx = j < kPeSlots ? pe_index(j, g) : -1;
+          val = idx < 0 ? 0.0f : w.W1[(16 * b + m) * kSdfIn + idx];
+        } else if (f < F2) {
+          const int f2 = f - F1, b = f2 / (H / 32), c = f2 % (H / 32);
+          val = w.W2[(16 * b + m) * H + unit_bf16(c, g, i)];
+        } else {
+          val = w.W3[m * H + unit_bf16(f - F2, g, i)];
+        }
+        const size_t at = ((size_t)f * 64 + lane) * 8 + i;
+        hi[at] = bf16_bits(val);
+        lo[at] = bf16_bits(val - bf16_value(val));
+      }
+    }
+  // colour fragments and biases, copied from the float32 block
+  std::vector<float> f32((size_t)shade_block_words(H));
+  pack_shade(blk, cblk, H, f32.data());
+  const int S3 = NB * kPeSlots + NB * (H / 4) + H / 4, ST = shade_frag_slots(H);
+  float* rest = out_words + 2 * 256 * NF;
+  std::copy(f32.begin() + 64 * S3, f32.end(), rest);
+  static_assert(2 * 12 + 8 == 32, "colour fragments");
+  (void)ST;
+}
+
 }  // namespace kn
 
 // ---------------------------------------------------------------------------
@@ -240,8 +279,9 @@ struct KnScene {
   float* march_f32 = nullptr;
   float* march_bf16 = nullptr;
   float* march_fp8 = nullptr;
-  float* shade = nullptr;
-  uint32_t march_f32_words = 0, march_bf16_words = 0, march_fp8_words = 0, shade_words = 0;
+  float* shade = nullptr;    // float32 shading blocks (float32 pools, point queries)
+  float* shade3 = nullptr;   // split-bfloat16 shading blocks (bf16 and fp8 pools)
+  uint32_t march_f32_words = 0, march_bf16_words = 0, march_fp8_words = 0, shade_words = 0, shade3_words = 0;
 
   const float* march(int prec) const {
     return prec == KN_BF16 ? march_bf16 : prec == KN_FP8_E4M3 ? march_fp8 : march_f32;
@@ -249,6 +289,8 @@ struct KnScene {
   uint32_t march_words(int prec) const {
     return prec == KN_BF16 ? march_bf16_words : prec == KN_FP8_E4M3 ? march_fp8_words : march_f32_words;
   }
+  const float* shading(int prec) const { return prec == KN_FP32 ? shade : shade3; }
+  uint32_t shading_words(int prec) const { return prec == KN_FP32 ? shade_words : shade3_words; }
   size_t bytes = 0;
   std::atomic<int> refs{0};
 };
@@ -399,8 +441,8 @@ SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base) {
   e.cell_end = cell_base + (uint32_t)(s->N * s->N * s->N);
   e.march = s->march(prec);
   e.march_words = s->march_words(prec);
-  e.shade = s->shade;
-  e.shade_words = s->shade_words;
+  e.shade = s->shading(prec);
+  e.shade_words = s->shading_words(prec);
   e.spk = softplus_consts(s->geom.beta);
   return e;
 }
@@ -518,7 +560,7 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sh.n_spawn = &w.ctrl->n_in;
   sh.counts_next = w.counts + (next_round & 1) * w.cells;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
-  KN_HIP(ctx, launch_shade(sh, c.hmode, pt, c.shade_words, persistent_grid(ctx, 3), st));
+  KN_HIP(ctx, launch_shade(sh, c.hmode, c.prec, pt, c.shade_words, persistent_grid(ctx, 3), st));
   if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
   return KN_OK;
 }
@@ -635,11 +677,13 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
   s->march_bf16_words = (uint32_t)march_block_words(H, kPrecBf16);
   s->march_fp8_words = (uint32_t)march_block_words(H, kPrecFp8);
   s->shade_words = (uint32_t)shade_block_words(H);
+  s->shade3_words = (uint32_t)shade3_block_words(H);
   const bool want_bf16 = (d->precisions >> KN_BF16) & 1u;
   const bool want_fp8 = (d->precisions >> KN_FP8_E4M3) & 1u;
   const size_t bytes = cells * 4 * ((size_t)s->march_f32_words + s->shade_words +
                                     (want_bf16 ? s->march_bf16_words : 0) +
-                                    (want_fp8 ? s->march_fp8_words : 0));
+                                    (want_fp8 ? s->march_fp8_words : 0) +
+                                    (want_bf16 || want_fp8 ? s->shade3_words : 0));
   if (ctx->used.load() + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "scene needs %zu bytes; budget %llu, in use %llu", bytes,
                 (unsigned long long)ctx->budget, (unsigned long long)ctx->used.load());
@@ -671,6 +715,12 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
     pack_shade(d->sdf_params + c * psdf, d->col_params + c * pcol, H, o);
   });
   if (st != KN_OK) return st;
+  if (want_bf16 || want_fp8) {
+    st = upload(&s->shade3, s->shade3_words, [&](size_t c, float* o) {
+      pack_shade3(d->sdf_params + c * psdf, d->col_params + c * pcol, H, o);
+    });
+    if (st != KN_OK) return st;
+  }
   s->bytes = bytes;
   ctx->used += bytes;
   std::lock_guard<std::mutex> lk(ctx->mu);
@@ -695,6 +745,7 @@ kn_status kn_scene_destroy(kn_ctx* ctx, kn_scene_id id) {
   if (s->march_bf16) (void)hipFree(s->march_bf16);
   if (s->march_fp8) (void)hipFree(s->march_fp8);
   if (s->shade) (void)hipFree(s->shade);
+  if (s->shade3) (void)hipFree(s->shade3);
   ctx->used -= s->bytes;
   delete s;
   ctx->scenes.erase(it);
@@ -812,7 +863,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   q.env_w = c->env_w;
   q.env_h = c->env_h;
   *ctx->h_req = q;
-  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, s->shade_words, (uint32_t)cells,
+  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, (uint32_t)cells,
                      ctx->max_passes};
 
   const bool timed = stats && stats->kernel_times;
@@ -1278,7 +1329,7 @@ class ServeLoop {
     if (hipMemcpyAsync(pool.scenes + k, h_scenes + k, sizeof(SceneEnt), hipMemcpyHostToDevice, stream) !=
         hipSuccess)
       return -2;
-    table.push_back(TabEnt{s->id, cells_used, cells, h_scenes[k].march_words, s->shade_words, s->H});
+    table.push_back(TabEnt{s->id, cells_used, cells, h_scenes[k].march_words, h_scenes[k].shade_words, s->H});
     cells_used += cells;
     return k;
   }
