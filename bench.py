@@ -43,8 +43,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run (fetch x2.0, write x1.0); summary and
 # commands in profiles/k_march_bf16_c3_1080p.md.  Valid only for the kernel
 # sources they were taken on: any change to them makes the figure null.
-MARCH_TRAFFIC = dict(sources_sha256="88f78c2f4a5f1fd93121b443457ce97fbc25ad808746641f41e0e9af4a0d7775",
-                     bytes_per_launch=64989601.0, fetch_kib=24020.57, write_kib=15426.98,
+MARCH_TRAFFIC = dict(sources_sha256="f67c248142210031717dd2b742a2eb24d5a823bc5de2050053832e17674f8697",
+                     bytes_per_launch=65275835.9, fetch_kib=24124.42, write_kib=15498.84,
                      fetch_factor=2.0, write_factor=1.0)
 
 
