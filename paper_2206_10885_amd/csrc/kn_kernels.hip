@@ -272,8 +272,11 @@ __device__ __forceinline__ uint32_t lane63(uint32_t v) { return (uint32_t)__buil
 //  3. each wave scans every step of 64 cells across the lanes, carrying the
 //     step total, and writes the bin starts and the chunks of its cells.
 // Cells are visited in increasing order, so bins and chunks are laid out in
-// cell order.  Empty cells are not written: their cursor is never read and
-// their count is already zero.  T is a power of two.
+// cell order.  A cell's count is its new records (counts) plus, when runs is
+// given, the rays the previous round's chunks hand on to it; those come first
+// in the bin, at offsets their chunks reserved.  Empty cells are not written:
+// their cursor is never read and their counts are already zero.  T is a power
+// of two.
 __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
   __shared__ uint32_t s_tile, s_wr[4], s_wk[4], s_base[2];
   const uint32_t tid = threadIdx.x, lane = (uint32_t)lane_id();
@@ -290,13 +293,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
   const uint32_t s0 = min(t1, t0 + wave * SW), s1 = min(t1, s0 + SW);
   const uint32_t nst = (s1 - s0 + 63u) >> 6;   // steps of 64 cells in this strip
   const uint32_t* counts = a.counts;
+  const uint32_t* runs = a.runs;
   uint32_t sr = 0, sk = 0;
   for (uint32_t q = 0; q < nst; q += 8u) {
     uint32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t c = s0 + 64u * (q + (uint32_t)u) + lane;
-      v[u] = c < s1 ? counts[c] : 0u;
+      v[u] = c < s1 ? counts[c] + (runs ? runs[c] : 0u) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -363,21 +367,30 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
   }
   __syncthreads();
   uint32_t R = s_base[0] + s_wr[wave], K = s_base[1] + s_wk[wave];
+  // the bin of cell c: the runs handed on to it first (at base[c]), then the
+  // new records (cursor[c] = base[c] + runs[c])
   uint32_t c = s0 + lane;
-  uint32_t n1 = c < s1 ? counts[c] : 0u;
-  uint32_t n2 = c + 64u < s1 ? counts[c + 64u] : 0u;
+  uint32_t m1 = c < s1 ? counts[c] : 0u, m2 = c + 64u < s1 ? counts[c + 64u] : 0u;
+  uint32_t h1 = c < s1 && runs ? runs[c] : 0u, h2 = c + 64u < s1 && runs ? runs[c + 64u] : 0u;
   for (uint32_t q = 0; q < nst; ++q, c += 64u) {
-    const uint32_t n = n1;
-    n1 = n2;
-    n2 = c + 128u < s1 ? counts[c + 128u] : 0u;
+    const uint32_t nm = m1, nh = h1;
+    m1 = m2;
+    h1 = h2;
+    m2 = c + 128u < s1 ? counts[c + 128u] : 0u;
+    h2 = c + 128u < s1 && runs ? runs[c + 128u] : 0u;
+    const uint32_t n = nm + nh;
     const uint32_t k = (n + tm) >> ts;
     const uint32_t ir = wave_incl_scan(n), ik = wave_incl_scan(k);
     if (n) {
       const uint32_t r = R + ir - n;
       uint32_t j = K + ik - k;
-      a.cursor[c] = r;
+      a.cursor[c] = r + nh;
+      if (a.base) a.base[c] = r;
       for (uint32_t i = 0; i < n; i += a.T) a.chunks[j++] = make_uint2(c | (min(a.T, n - i) << kCellBits), r + i);
-      if (a.zero_counts) a.counts[c] = 0u;
+      if (a.zero_counts) {
+        if (nm) a.counts[c] = 0u;
+        if (nh) a.runs[c] = 0u;
+      }
     }
     R += lane63(ir);
     K += lane63(ik);
@@ -467,12 +480,6 @@ __device__ __forceinline__ uint32_t neighbor_cell(const SceneGeom& sg, uint32_t 
   return sg.cell_base + (uint32_t)(idx[0] + (int)N * (idx[1] + (int)N * idx[2]));
 }
 
-// Rounds >= 1: each chunk of the previous round left its next-round rays in
-// its own range of U, grouped by exit face (and a seventh group that stays
-// in the cell); one wave moves the chunk's runs into their cells' bins (one
-// atomic per run).  The records are loaded while the atomics are in flight
-// and copied in one flat pass: a record's run follows from the seven run
-// offsets.  The next chunk's descriptors are fetched ahead.
 // a value that is the same in every lane, as a scalar
 __device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 
@@ -491,17 +498,26 @@ __device__ __forceinline__ uint32_t run_dest(uint32_t i, uint32_t o1, uint32_t o
   return d + i;
 }
 
+// Rounds >= 1: each chunk of the previous round left its next-round rays in
+// its own range of U, grouped by exit face (and a seventh group that stays
+// in the cell), and reserved each run's place in its destination bin when it
+// counted it; one wave moves the chunk's runs there (bin start + reserved
+// offset: no atomics).  The records and the bin starts are loaded together
+// and copied in one flat pass: a record's run follows from the seven run
+// offsets.  The next chunk's descriptors are fetched ahead.
 __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterChunksArgs a) {
   const uint32_t nch = *a.n_chunks;
   const uint32_t lane = (uint32_t)lane_id();
   const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
   uint2 c = make_uint2(0u, 0u);
-  uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = fa;
+  uint4 fa = make_uint4(0u, 0u, 0u, 0u), fb = fa, oa = fa, ob = fa;
   if (wave < nch) {
     c = a.chunks[wave];
-    fa = a.chunk_out[2 * wave];
-    fb = a.chunk_out[2 * wave + 1];
+    fa = a.chunk_out[4 * wave];
+    fb = a.chunk_out[4 * wave + 1];
+    oa = a.chunk_out[4 * wave + 2];
+    ob = a.chunk_out[4 * wave + 3];
   }
   uint4* out = reinterpret_cast<uint4*>(a.S);
   for (uint32_t j = wave; j < nch; j += nwaves) {
@@ -512,25 +528,29 @@ __global__ __launch_bounds__(256) void k_scatter_chunks(ScatterChunksArgs a) {
     const uint32_t n4 = uniform(fb.x), n5 = uniform(fb.y), n6 = uniform(fb.z);
     const uint32_t o1 = n0, o2 = o1 + n1, o3 = o2 + n2, o4 = o3 + n3, o5 = o4 + n4, o6 = o5 + n5;
     const uint32_t total = o6 + n6;
+    // lane f < 7: run f's reserved offset in its destination bin
+    const uint32_t roff = lane == 0u ? oa.x : lane == 1u ? oa.y : lane == 2u ? oa.z : lane == 3u ? oa.w
+                        : lane == 4u ? ob.x : lane == 5u ? ob.y : lane == 6u ? ob.z : 0u;
     const uint32_t jn = j + nwaves;
     if (jn < nch) {
       c = a.chunks[jn];
-      fa = a.chunk_out[2 * jn];
-      fb = a.chunk_out[2 * jn + 1];
+      fa = a.chunk_out[4 * jn];
+      fb = a.chunk_out[4 * jn + 1];
+      oa = a.chunk_out[4 * jn + 2];
+      ob = a.chunk_out[4 * jn + 3];
     }
     if (total == 0u) continue;
-    // the first 256 records are loaded before the atomics; indexes past the
-    // chunk's records are clamped to its last one (and not stored)
+    // indexes past the chunk's records are clamped to its last one (and not
+    // stored)
     const uint4* src = reinterpret_cast<const uint4*>(a.U) + start;
     const uint32_t last = total - 1u;
     uint4 v0 = src[min(lane, last)], v1 = src[min(lane + 64u, last)];
     uint4 v2 = src[min(lane + 128u, last)], v3 = src[min(lane + 192u, last)];
-    // lanes 0..6 reserve the seven runs' destinations at once
+    // lanes 0..6: the seven runs' destinations
     const uint32_t mine = lane == 0u ? n0 : lane == 1u ? n1 : lane == 2u ? n2 : lane == 3u ? n3
                         : lane == 4u ? n4 : lane == 5u ? n5 : lane == 6u ? n6 : 0u;
     uint32_t dst = 0;
-    if (mine)
-      dst = atomicAdd(&a.cursor[neighbor_cell(a.tabs.scenes[scene_of(a.tabs, cell)].sg, cell, (int)lane)], mine);
+    if (mine) dst = a.base[neighbor_cell(a.tabs.scenes[scene_of(a.tabs, cell)].sg, cell, (int)lane)] + roff;
     // destination of record i: its run's base minus the run's offset, plus i
     const uint32_t d0 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 0);
     const uint32_t d1 = (uint32_t)__builtin_amdgcn_readlane((int)dst, 1) - o1;
@@ -967,8 +987,10 @@ __device__ __forceinline__ void stage_block(float* lds, const float* src, uint32
   }
 }
 
-// the wave's direct-to-LDS loads have landed
-__device__ __forceinline__ void stage_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+// the wave's direct-to-LDS loads have landed: vmcnt(0) (expcnt and lgkmcnt
+// left at their maxima), as a builtin so that the compiler's own wait
+// tracking knows every vector memory operation before it is complete
+__device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
 struct CellBox {
   int ix, iy, iz;
@@ -1152,6 +1174,9 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   }
   __syncthreads();
   Grabber G{0u, 0u, 0u, nullptr};   // thread 0's
+  // threads 1..7: the last work item's run reservation, stored one item later
+  constexpr uint32_t kNoJob = 0xFFFFFFFFu;
+  uint32_t pend_job = kNoJob, pend_off = 0u;
   if (tid == 0) {
     G = grab_init(a.grab, *a.n_chunks);
     uint32_t j;
@@ -1216,6 +1241,10 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     }
     pf_rec_ok = pf_st_ok = false;
     stage_wait();
+    if (tid >= 1 && tid <= 7 && pend_job != kNoJob) {
+      reinterpret_cast<uint32_t*>(a.chunk_out)[16u * pend_job + 8u + (uint32_t)tid - 1u] = pend_off;
+      pend_job = kNoJob;
+    }
     __syncthreads();
     if (tid == 0 && jn_ok) put_job(s_scn, a.tabs.n_scenes, s_jn, cn, jn);
 
@@ -1376,15 +1405,20 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         s_foff[f] = off;
         off += s_face[f];
       }
-      a.chunk_out[2 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
-      a.chunk_out[2 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
+      a.chunk_out[4 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
+      a.chunk_out[4 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
       if (s_nhit) atomicAdd(&a.hit_count[cell], s_nhit);
       wg_evals += s_evals;
       wg_tiles += s_tiles;
       ++wg_chunks;
     } else if (tid <= 7) {
-      const uint32_t n = s_face[tid - 1];
-      if (n) atomicAdd(&a.counts_next[neighbor_cell(sg, cell, tid - 1)], n);
+      // run f = tid - 1 reserves its place in the destination cell's next bin
+      // (an empty run adds 0 to this cell); the offset is stored during the
+      // next work item, after a wait that staging makes anyway, so the
+      // atomic's round trip is never waited for on its own
+      const uint32_t f = (uint32_t)tid - 1u, n = s_face[f];
+      pend_off = atomicAdd(&a.runs_next[n ? neighbor_cell(sg, cell, (int)f) : cell], n);
+      pend_job = job;
     }
     __syncthreads();
     if ((uint32_t)tid < count) {
@@ -1395,6 +1429,8 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     if (tid < 6) s_job[tid] = s_jn[tid];
     __syncthreads();
   }
+  if (tid >= 1 && tid <= 7 && pend_job != kNoJob)
+    reinterpret_cast<uint32_t*>(a.chunk_out)[16u * pend_job + 8u + (uint32_t)tid - 1u] = pend_off;
   if (tid < kMaxSlots && s_miss[tid]) atomicAdd(&a.tabs.miss_done[tid], s_miss[tid]);
   if (tid == 0 && wg_chunks) {
     atomicAdd(&a.evals[0], wg_evals);

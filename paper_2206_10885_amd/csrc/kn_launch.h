@@ -100,6 +100,9 @@ struct ScanArgs {
   uint32_t* grab0;       // out: a copy of the initial cursors (to restart a pass)
   uint32_t* zero_word;   // optional counter reset to 0
   uint32_t* total;       // optional: the sum of the counts is added to it
+  uint32_t* runs;        // optional: per-cell rays handed on by the previous round's chunks,
+                         // binned first (read; zeroed if zero_counts)
+  uint32_t* base;        // optional out: bin start per cell (cursor = base + runs)
   uint32_t* ticket;      // Ctrl::scan_ticket
   unsigned long long* flags;  // Ctrl::scan_flags
   uint32_t* err;         // Ctrl::scan_err
@@ -117,11 +120,11 @@ struct ScatterArgs {
 struct ScatterChunksArgs {
   PoolTabs tabs;
   const uint2* chunks;        // previous round's chunks
-  const uint4* chunk_out;     // their exit-face counts (2 x uint4 per chunk)
+  const uint4* chunk_out;     // their exit-face counts and offsets (4 x uint4 per chunk)
   const uint32_t* n_chunks;
   const RayRec* U;
   RayRec* S;
-  uint32_t* cursor;
+  const uint32_t* base;       // bin start per cell
 };
 
 struct MarchArgs {
@@ -131,9 +134,10 @@ struct MarchArgs {
   const uint2* chunks;
   const uint32_t* n_chunks;
   uint32_t* grab;        // per-range work cursors set by the scan
-  uint4* chunk_out;          // per chunk: rays leaving through each face / staying, hits
+  uint4* chunk_out;          // per chunk (4 x uint4): rays leaving through each face /
+                             // staying, hits; then each run's offset in its next bin
   RayRec* U;                 // next-round rays, in each chunk's own range
-  uint32_t* counts_next;
+  uint32_t* runs_next;       // per cell: rays this round's chunks hand on to it
   RayRec* hits;              // hits, indexed by pool ray id (invalid key: none)
   uint32_t* hit_count;       // hits per cell
   unsigned long long* evals;     // [0] evaluations, [1] tiles, [2] chunks

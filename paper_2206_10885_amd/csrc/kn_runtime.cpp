@@ -305,11 +305,13 @@ struct Pool {
   RayRec* Uin = nullptr;           // records of newly generated rays
   RayRec* HL = nullptr;            // hit list since the last shading pass
   PathRec* path = nullptr;         // path tracing state (allocated on first use)
-  uint32_t* counts = nullptr;      // [2][cells]
+  uint32_t* counts = nullptr;      // [2][cells]: new records arriving for a round
+  uint32_t* runs = nullptr;        // [2][cells]: rays handed on by the previous round's chunks
   uint32_t* hit_count = nullptr;   // [cells]
   uint32_t* cursor = nullptr;      // [cells]
+  uint32_t* base = nullptr;        // [cells]: bin starts of the current round
   uint2* chunk = nullptr;          // [3][chunks]: rounds of parity 0 / 1, shading
-  uint4* chunk_out = nullptr;      // [2][chunks][2]
+  uint4* chunk_out = nullptr;      // [2][chunks][4]
   Ctrl* ctrl = nullptr;
   SceneEnt* scenes = nullptr;      // [kMaxScenes]
   ReqEnt* reqs = nullptr;          // [kMaxSlots]
@@ -361,8 +363,8 @@ kn_status check_ctx(kn_ctx* ctx) {
 }
 
 void free_pool(Pool& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.hit_count, w.cursor, w.chunk,
-                  w.chunk_out, w.ctrl, w.scenes, w.reqs};
+  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.runs, w.hit_count, w.cursor, w.base,
+                  w.chunk, w.chunk_out, w.ctrl, w.scenes, w.reqs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   w = Pool{};
@@ -373,7 +375,7 @@ constexpr size_t kRayBytes = sizeof(RayStatic) + 4 * sizeof(RayRec);
 size_t uin_entries(size_t R) { return R + R / 8 + kListSlack; }
 
 size_t pool_bytes(size_t R, size_t C, size_t K) {
-  return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * 4 + K * (3 * 8 + 2 * 32) +
+  return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * 7 + K * (3 * 8 + 2 * 64) +
          sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) + kMaxSlots * sizeof(ReqEnt);
 }
 
@@ -406,10 +408,12 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
   if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * 4));
+  KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * 4));
   KN_HIP(ctx, hipMalloc(&n.cursor, C * 4));
+  KN_HIP(ctx, hipMalloc(&n.base, C * 4));
   KN_HIP(ctx, hipMalloc(&n.chunk, 3 * K * 8));
-  KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 32));
+  KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 64));
   KN_HIP(ctx, hipMalloc(&n.ctrl, sizeof(Ctrl)));
   KN_HIP(ctx, hipMemset(n.HL, 0xFF, R * sizeof(RayRec)));   // no hits
   KN_HIP(ctx, hipMalloc(&n.scenes, kMaxScenes * sizeof(SceneEnt)));
@@ -472,6 +476,8 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   const PoolTabs tabs = pool_tabs(w, c.n_scenes);
   ScanArgs sa{};
   sa.counts = w.counts + par * w.cells;
+  sa.runs = w.runs + par * w.cells;
+  sa.base = w.base;
   sa.C = c.cells;
   sa.T = kChunk;
   sa.zero_counts = 1;
@@ -489,11 +495,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   if (r > 0) {
     ScatterChunksArgs sc{tabs,
                          w.chunk + (size_t)(par ^ 1) * w.chunks,
-                         w.chunk_out + (size_t)(par ^ 1) * w.chunks * 2,
+                         w.chunk_out + (size_t)(par ^ 1) * w.chunks * 4,
                          &w.ctrl->n_chunks[par ^ 1],
                          w.U,
                          w.S,
-                         w.cursor};
+                         w.base};
     KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 16), st));
   }
   if (n_new) {
@@ -511,9 +517,9 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.chunks = w.chunk + (size_t)par * w.chunks;
   ma.n_chunks = &w.ctrl->n_chunks[par];
   ma.grab = w.ctrl->grab;
-  ma.chunk_out = w.chunk_out + (size_t)par * w.chunks * 2;
+  ma.chunk_out = w.chunk_out + (size_t)par * w.chunks * 4;
   ma.U = w.U;
-  ma.counts_next = w.counts + (par ^ 1) * w.cells;
+  ma.runs_next = w.runs + (par ^ 1) * w.cells;
   ma.hits = w.HL;
   ma.hit_count = w.hit_count;
   ma.evals = &w.ctrl->evals;
@@ -890,6 +896,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
   // both parities of the per-cell counts ([2][w.cells]) and the hit counts
   KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.runs, 0, 2 * w.cells * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
 
@@ -1170,6 +1177,7 @@ class ServeLoop {
     KN_HIP(ctx, hipHostMalloc((void**)&h_reqs, kMaxSlots * sizeof(ReqEnt), hipHostMallocDefault));
     KN_HIP(ctx, hipMemsetAsync(pool.ctrl, 0, sizeof(Ctrl), stream));
     KN_HIP(ctx, hipMemsetAsync(pool.counts, 0, 2 * pool.cells * 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.runs, 0, 2 * pool.cells * 4, stream));
     KN_HIP(ctx, hipMemsetAsync(pool.hit_count, 0, pool.cells * 4, stream));
     KN_HIP(ctx, hipStreamSynchronize(stream));
     free_ranges[0] = pool.cap;
