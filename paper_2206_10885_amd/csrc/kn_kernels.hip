@@ -1142,7 +1142,10 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
   float* s_w = reinterpret_cast<float*>(s_act + 2 * kChunk);      // weight block (16-byte aligned)
   __shared__ uint32_t s_job[6], s_jn[6];   // current / next work item: cell, start, count, id, valid, scene
-  __shared__ uint32_t s_nact[2], s_pair;
+  // per pass p: tile counter s_pair[p % 3], survivors s_nact[(p + 1) % 3]
+  // (three slots, so that thread 0 can clear the next pass's ones during a
+  // pass: a slot's last reader is always behind an earlier barrier)
+  __shared__ uint32_t s_nact[3], s_pair[3];
   __shared__ uint32_t s_face[7], s_foff[7];
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
   __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
@@ -1177,24 +1180,25 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   // threads 1..7: the last work item's run reservation, stored one item later
   constexpr uint32_t kNoJob = 0xFFFFFFFFu;
   uint32_t pend_job = kNoJob, pend_off = 0u;
+  // thread 0: a work item's counters start at zero
+  auto clear_item = [&]() {
+    s_nact[1] = 0u;
+    s_pair[0] = 0u;
+    s_nhit = 0u;
+    s_evals = 0u;
+    s_tiles = 0u;
+    s_jn[4] = 0u;
+    for (int f = 0; f < 7; ++f) s_face[f] = 0u;
+  };
   if (tid == 0) {
     G = grab_init(a.grab, *a.n_chunks);
     uint32_t j;
     if (grab_next(a.grab, G, j)) put_job(s_scn, a.tabs.n_scenes, s_job, a.chunks[j], j);
     else s_job[4] = 0u;
+    clear_item();
   }
+  __syncthreads();
   for (;;) {
-    if (tid == 0) {
-      s_nact[0] = s_job[2];
-      s_nact[1] = 0u;
-      s_pair = 0u;
-      s_nhit = 0u;
-      s_evals = 0u;
-      s_tiles = 0u;
-      s_jn[4] = 0u;
-      for (int f = 0; f < 7; ++f) s_face[f] = 0u;
-    }
-    __syncthreads();
     const Job jb = read_job(s_job);
     if (!jb.valid) break;
     const uint32_t cell = jb.cell, start = jb.start, count = jb.count, job = jb.id;
@@ -1257,10 +1261,15 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       const uint32_t ntiles = (nact + 15u) >> 4;
       const uint16_t* act_in = s_act + cur * kChunk;
       uint16_t* act_out = s_act + (cur ^ 1) * kChunk;
+      const int i0 = pass % 3, i1 = (pass + 1) % 3, i2 = (pass + 2) % 3;
+      if (tid == 0) {   // the next pass's counters (last used two passes ago)
+        s_pair[i1] = 0u;
+        s_nact[i2] = 0u;
+      }
       // tile pairs handed out through an LDS counter
       for (;;) {
         uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&s_pair, PAIR ? 2u : 1u);
+        if (lane == 0) tile = atomicAdd(&s_pair[i0], PAIR ? 2u : 1u);
         tile = __shfl(tile, 0);
         if (tile >= ntiles) break;
         uint32_t ri[2];
@@ -1324,18 +1333,14 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         if (sm0 | sm1) {
           const uint32_t n0 = (uint32_t)__popcll(sm0);
           uint32_t base = 0;
-          if (lane == 0) base = atomicAdd(&s_nact[cur ^ 1], n0 + (uint32_t)__popcll(sm1));
+          if (lane == 0) base = atomicAdd(&s_nact[i1], n0 + (uint32_t)__popcll(sm1));
           base = __shfl(base, 0);
           if (stay[0]) act_out[base + (uint32_t)__popcll(sm0 & lanemask_lt())] = (uint16_t)ri[0];
           if (stay[1]) act_out[base + n0 + (uint32_t)__popcll(sm1 & lanemask_lt())] = (uint16_t)ri[1];
         }
       }
       __syncthreads();
-      if (tid == 0) {
-        s_nact[cur] = 0u;
-        s_pair = 0u;
-      }
-      nact = s_nact[cur ^ 1];
+      nact = s_nact[i1];
       // the next work item is known after the first barrier: start loading
       // its rays (the static data one pass later, once the record is in)
       if (pass == 0) {
@@ -1348,7 +1353,6 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         pf_st = a.rs[pf_rec.rid];
         pf_st_ok = true;
       }
-      __syncthreads();
       cur ^= 1;
     }
     if (lane == 0) {
@@ -1426,7 +1430,10 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         a.U[start + s_foff[face] + rank] =
             RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
     }
-    if (tid < 6) s_job[tid] = s_jn[tid];
+    if (tid == 0) {   // the next work item, and its counters cleared
+      for (int i = 0; i < 6; ++i) s_job[i] = s_jn[i];
+      clear_item();
+    }
     __syncthreads();
   }
   if (tid >= 1 && tid <= 7 && pend_job != kNoJob)
