@@ -219,9 +219,9 @@ def test_render_full_size_sampled(ctx, cfg, views, samples):
 
 @pytest.mark.parametrize("precision", ["bf16", "fp8"])
 def test_render_lowp_vs_fp32_report(ctx, precision):
-    """BF16 or FP8 march (FP32 refinement and shading) against the FP32 path
-    on the same inputs, and the FP64 oracle on sampled pixels: reported; the
-    masks must largely agree."""
+    """BF16 or FP8 march (refinement and shading on split-bf16 MFMA) against
+    the FP32 path on the same inputs, and the FP64 oracle on sampled pixels:
+    reported; the masks must largely agree."""
     sc = synth.sphere_scene(16, 64, 0.6, 0.02, seed=3000)
     sid = ctx.scene_create(sc, precisions=(precision,))
     view = synth.config_views("c3")[0]
@@ -240,6 +240,35 @@ def test_render_lowp_vs_fp32_report(ctx, precision):
     rep = P.compare(sc, view, 480, 270, 128, 1e-4, P.gpu_arrays(out, pix), pixels=pix)
     log(f"{precision} vs FP64 oracle (1500 pixels):", rep.as_dict())
     assert agree > 0.95
+    ctx.scene_destroy(sid)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp8"])
+def test_split_bf16_shading_on_the_same_surface(ctx, precision):
+    MIN_OK = {"bf16": 0.99, "fp8": 0.95}
+    """Pools marching in bf16 or fp8 refine and shade on bf16 MFMA with split
+    (hi + lo) operands.  On a smooth scene (no per-cell noise) the
+    low-precision march ends next to the same crossing as the float32 one
+    (depths within 1e-3), and two Newton steps take both to the same point, so
+    what is left is the refinement and shading arithmetic: depth, normal and
+    colour must agree with the float32 frame to the parity tolerances."""
+    sc = synth.sphere_scene(16, 64, 0.6, 0.0, seed=3001)
+    sid = ctx.scene_create(sc, precisions=(precision,))
+    view = synth.config_views("c3")[1]
+    a = P.gpu_arrays(_render(ctx, sid, view, 480, 270, 128))
+    b = P.gpu_arrays(_render(ctx, sid, view, 480, 270, 128, precision=precision))
+    both = (a["hit"] == 1) & (b["hit"] == 1)
+    dd = np.abs(a["depth"] - b["depth"])
+    same = both & (dd < 1e-3)
+    an = P.angle_deg(a["normal"][same], b["normal"][same])
+    dc = np.abs(a["rgb"] - b["rgb"]).max(axis=1)[same]
+    log(f"{precision}: same-surface {same.sum()} of {both.sum()} common hits; depth p99 "
+        f"{np.percentile(dd[same], 99):.2e} max {dd[same].max():.2e}; normal p99 {np.percentile(an, 99):.2e} "
+        f"max {an.max():.2e} deg; rgb p99 {np.percentile(dc, 99):.2e} max {dc.max():.2e}")
+    ok = (dd[same] <= P.TOL_DEPTH) & (an <= P.TOL_NORMAL_DEG) & (dc <= P.TOL_RGB)
+    log(f"{precision}: {ok.mean():.5f} of the same-surface pixels within all three tolerances")
+    assert same.sum() > 0.9 * both.sum()
+    assert ok.mean() >= MIN_OK[precision]
     ctx.scene_destroy(sid)
 
 
