@@ -1355,6 +1355,17 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
       cur ^= 1;
     }
+    // the weights are not read again for this work item: the next one's
+    // block starts loading now, behind the output phase (the staging wait
+    // of the next item covers it)
+    {
+      const Job nx = read_job(s_jn);
+      if (nx.valid && nx.cell != loaded) {
+        const SceneEnt* sn = s_scn + __builtin_amdgcn_readfirstlane(nx.scene);
+        stage_block(s_w, sn->march + (size_t)(nx.cell - sn->sg.cell_base) * sn->march_words, sn->march_words);
+        loaded = nx.cell;
+      }
+    }
     if (lane == 0) {
       atomicAdd(&s_evals, wave_evals);
       atomicAdd(&s_tiles, wave_tiles);
