@@ -1357,7 +1357,12 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     }
     // the weights are not read again for this work item: the next one's
     // block starts loading now, behind the output phase (the staging wait
-    // of the next item covers it)
+    // of the next item covers it); so does the next item's static ray data
+    // when this item ended after one pass
+    if (pf_rec_ok && !pf_st_ok) {
+      pf_st = a.rs[pf_rec.rid];
+      pf_st_ok = true;
+    }
     {
       const Job nx = read_job(s_jn);
       if (nx.valid && nx.cell != loaded) {
