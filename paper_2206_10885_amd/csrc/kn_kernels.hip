@@ -1249,8 +1249,18 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       reinterpret_cast<uint32_t*>(a.chunk_out)[16u * pend_job + 8u + (uint32_t)tid - 1u] = pend_off;
       pend_job = kNoJob;
     }
-    __syncthreads();
+    // the next work item's descriptor is in (the staging wait covered it)
     if (tid == 0 && jn_ok) put_job(s_scn, a.tabs.n_scenes, s_jn, cn, jn);
+    __syncthreads();
+    // start loading the next work item's rays (their static data one pass
+    // later, once the record is in)
+    {
+      const Job nx = read_job(s_jn);
+      if (nx.valid && (uint32_t)tid < nx.count) {
+        pf_rec = a.S[nx.start + tid];
+        pf_rec_ok = true;
+      }
+    }
 
     // passes over the rays still inside the cell; after max_passes the rest
     // go on in the next round (same cell), so a few slow rays near the
@@ -1341,15 +1351,9 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
       __syncthreads();
       nact = s_nact[i1];
-      // the next work item is known after the first barrier: start loading
-      // its rays (the static data one pass later, once the record is in)
-      if (pass == 0) {
-        const Job nx = read_job(s_jn);
-        if (nx.valid && (uint32_t)tid < nx.count) {
-          pf_rec = a.S[nx.start + tid];
-          pf_rec_ok = true;
-        }
-      } else if (pass == 1 && pf_rec_ok) {
+      // the next work item's ray records (loaded before pass 0) are in: its
+      // static ray data follows
+      if (pass == 0 && pf_rec_ok) {
         pf_st = a.rs[pf_rec.rid];
         pf_st_ok = true;
       }
