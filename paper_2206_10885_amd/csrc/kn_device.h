@@ -206,6 +206,46 @@ __device__ __forceinline__ float group_bcast(float v) {
   else return pair_bcast(v);
 }
 
+// value of lane SRC of each lane pair (SRC = 0, 1)
+template <int SRC>
+__device__ __forceinline__ float pair_from(float v) {
+  constexpr int ctrl = SRC | (SRC << 2) | ((2 + SRC) << 4) | ((2 + SRC) << 6);
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), ctrl, 0xF,
+                                                            0xF, false));
+}
+
+// Forward-mode activation of one MFMA output block: z holds the lane's four
+// units of its column, s = lane % C its column within the point (0: value).
+// The value column takes softplus(z); a tangent column takes
+// sigma(beta z_value) * dz.  Only the value column's four units need the
+// softplus, so they are spread over the point's C adjacent lanes (C = 4: one
+// unit each, C = 2: two each) and the results broadcast back: the same
+// arithmetic as every lane evaluating its own, a quarter (a half) of it.
+template <int C>
+__device__ __forceinline__ void act_forward(const f32x4& z, int s, bool value_col, SoftplusK k, float (&a)[4]) {
+  if constexpr (C == 4) {
+    const float z0 = quad_bcast<0>(z[0]), z1 = quad_bcast<0>(z[1]);
+    const float z2 = quad_bcast<0>(z[2]), z3 = quad_bcast<0>(z[3]);
+    const float zs = s == 0 ? z0 : s == 1 ? z1 : s == 2 ? z2 : z3;
+    float ds;
+    const float sp = softplus_d(zs, k, &ds);
+    const float sp_r[4] = {quad_bcast<0>(sp), quad_bcast<1>(sp), quad_bcast<2>(sp), quad_bcast<3>(sp)};
+    const float ds_r[4] = {quad_bcast<0>(ds), quad_bcast<1>(ds), quad_bcast<2>(ds), quad_bcast<3>(ds)};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = value_col ? sp_r[r] : ds_r[r] * z[r];
+  } else {
+    static_assert(C == 2, "two or four columns per point");
+    const float z0 = pair_bcast(z[0]), z1 = pair_bcast(z[1]), z2 = pair_bcast(z[2]), z3 = pair_bcast(z[3]);
+    const float za = s == 0 ? z0 : z1, zb = s == 0 ? z2 : z3;   // units s and s + 2
+    float da, db;
+    const float pa = softplus_d(za, k, &da), pb = softplus_d(zb, k, &db);
+    const float sp_r[4] = {pair_from<0>(pa), pair_from<1>(pa), pair_from<0>(pb), pair_from<1>(pb)};
+    const float ds_r[4] = {pair_from<0>(da), pair_from<1>(da), pair_from<0>(db), pair_from<1>(db)};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) a[r] = value_col ? sp_r[r] : ds_r[r] * z[r];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Path tracing helpers
 // ---------------------------------------------------------------------------

@@ -1486,14 +1486,7 @@ __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, boo
     for (int b = 0; b < NB; ++b) acc[b] = mfma_f32(blk[(b * kPeSlots + q) * 64 + lane], v[q], acc[b]);
   float a1[NB][4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float ds;
-      const float sp = softplus_d(acc[b][r], k, &ds);
-      const float dv = group_bcast<C>(ds);
-      a1[b][r] = value_col ? sp : dv * acc[b][r];
-    }
+  for (int b = 0; b < NB; ++b) act_forward<C>(acc[b], lane & (C - 1), value_col, k, a1[b]);
   f32x4 acc2[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -1505,14 +1498,7 @@ __device__ __forceinline__ f32x4 sdf_full(const float* blk, int lane, int g, boo
       acc2[b] = mfma_f32(blk[(S1 + b * (H / 4) + q) * 64 + lane], a1[q / 4][q % 4], acc2[b]);
   float a2[NB][4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float ds;
-      const float sp = softplus_d(acc2[b][r], k, &ds);
-      const float dv = group_bcast<C>(ds);
-      a2[b][r] = value_col ? sp : dv * acc2[b][r];
-    }
+  for (int b = 0; b < NB; ++b) act_forward<C>(acc2[b], lane & (C - 1), value_col, k, a2[b]);
   f32x4 y = value_col ? *reinterpret_cast<const f32x4*>(vec + 2 * H + 4 * g) : f32x4{0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < H / 4; ++q) y = mfma_f32(blk[(S2 + q) * 64 + lane], a2[q / 4][q % 4], y);
@@ -1572,14 +1558,7 @@ __device__ __forceinline__ f32x4 sdf_full3(const float* blk, int lane, int g, bo
   }
   float a1[NB][4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float ds;
-      const float sp = softplus_d(acc[b][r], k, &ds);
-      const float dv = group_bcast<C>(ds);
-      a1[b][r] = value_col ? sp : dv * acc[b][r];
-    }
+  for (int b = 0; b < NB; ++b) act_forward<C>(acc[b], lane & (C - 1), value_col, k, a1[b]);
   f32x4 acc2[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b)
@@ -1599,14 +1578,7 @@ __device__ __forceinline__ f32x4 sdf_full3(const float* blk, int lane, int g, bo
   }
   float a2[NB][4];
 #pragma unroll
-  for (int b = 0; b < NB; ++b)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      float ds;
-      const float sp = softplus_d(acc2[b][r], k, &ds);
-      const float dv = group_bcast<C>(ds);
-      a2[b][r] = value_col ? sp : dv * acc2[b][r];
-    }
+  for (int b = 0; b < NB; ++b) act_forward<C>(acc2[b], lane & (C - 1), value_col, k, a2[b]);
   f32x4 y = value_col ? *reinterpret_cast<const f32x4*>(vec + 2 * H + 4 * g) : f32x4{0, 0, 0, 0};
 #pragma unroll
   for (int c = 0; c < H / 32; ++c) {
