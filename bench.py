@@ -43,8 +43,8 @@ PEAK_HBM = 8.0e12
 # 1 GiB device copy in the same run (fetch x2.0, write x1.0); summary and
 # commands in profiles/k_march_bf16_c3_1080p.md.  Valid only for the kernel
 # sources they were taken on: any change to them makes the figure null.
-MARCH_TRAFFIC = dict(sources_sha256="f67c248142210031717dd2b742a2eb24d5a823bc5de2050053832e17674f8697",
-                     bytes_per_launch=65275835.9, fetch_kib=24124.42, write_kib=15498.84,
+MARCH_TRAFFIC = dict(sources_sha256="ddce026a98c17da8500052104dc374a51afb2ece6db7fa270e544faa5e74d0c2",
+                     bytes_per_launch=65735344.6, fetch_kib=24087.47, write_kib=16021.47,
                      fetch_factor=2.0, write_factor=1.0)
 
 
