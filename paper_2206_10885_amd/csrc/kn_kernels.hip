@@ -1142,10 +1142,10 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   uint16_t* s_act = reinterpret_cast<uint16_t*>(s_st + kChunk);  // [2][kChunk]
   float* s_w = reinterpret_cast<float*>(s_act + 2 * kChunk);      // weight block (16-byte aligned)
   __shared__ uint32_t s_job[6], s_jn[6];   // current / next work item: cell, start, count, id, valid, scene
-  // per pass p: tile counter s_pair[p % 3], survivors s_nact[(p + 1) % 3]
-  // (three slots, so that thread 0 can clear the next pass's ones during a
-  // pass: a slot's last reader is always behind an earlier barrier)
-  __shared__ uint32_t s_nact[3], s_pair[3];
+  // per pass p: survivors counted in s_nact[(p + 1) % 3] (three slots, so
+  // that thread 0 can clear the next pass's one during a pass: a slot's last
+  // reader is always behind an earlier barrier)
+  __shared__ uint32_t s_nact[3];
   __shared__ uint32_t s_face[7], s_foff[7];
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
   __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
@@ -1183,7 +1183,6 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   // thread 0: a work item's counters start at zero
   auto clear_item = [&]() {
     s_nact[1] = 0u;
-    s_pair[0] = 0u;
     s_nhit = 0u;
     s_evals = 0u;
     s_tiles = 0u;
@@ -1271,17 +1270,13 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       const uint32_t ntiles = (nact + 15u) >> 4;
       const uint16_t* act_in = s_act + cur * kChunk;
       uint16_t* act_out = s_act + (cur ^ 1) * kChunk;
-      const int i0 = pass % 3, i1 = (pass + 1) % 3, i2 = (pass + 2) % 3;
-      if (tid == 0) {   // the next pass's counters (last used two passes ago)
-        s_pair[i1] = 0u;
-        s_nact[i2] = 0u;
-      }
-      // tile pairs handed out through an LDS counter
-      for (;;) {
-        uint32_t tile = 0;
-        if (lane == 0) tile = atomicAdd(&s_pair[i0], PAIR ? 2u : 1u);
-        tile = __shfl(tile, 0);
-        if (tile >= ntiles) break;
+      const int i1 = (pass + 1) % 3, i2 = (pass + 2) % 3;
+      if (tid == 0) s_nact[i2] = 0u;   // the next pass's counter (last used two passes ago)
+      // tiles dealt round-robin to the workgroup's waves: every tile costs
+      // one evaluation, so a fixed deal balances as well as a shared counter
+      // would, without its two LDS round trips per tile
+      constexpr uint32_t kTileStep = (PAIR ? 2u : 1u) * (256u / 64u);
+      for (uint32_t tile = (PAIR ? 2u : 1u) * (uint32_t)wave; tile < ntiles; tile += kTileStep) {
         uint32_t ri[2];
         bool valid[2];
         float t[2], o[2][3], d[2][3], v[2][kPeSlots];
@@ -1344,7 +1339,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
           const uint32_t n0 = (uint32_t)__popcll(sm0);
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(&s_nact[i1], n0 + (uint32_t)__popcll(sm1));
-          base = __shfl(base, 0);
+          base = __builtin_amdgcn_readfirstlane(base);   // every lane is active here
           if (stay[0]) act_out[base + (uint32_t)__popcll(sm0 & lanemask_lt())] = (uint16_t)ri[0];
           if (stay[1]) act_out[base + n0 + (uint32_t)__popcll(sm1 & lanemask_lt())] = (uint16_t)ri[1];
         }
