@@ -1,10 +1,14 @@
 """CPU emulation of the low-precision march MLP (test infrastructure only).
 
 The paper fixes no precision for the renderer; the bfloat16 variant used by
-the march is defined here as: the SDF MLP of eq. 3 (Sec. 3.1) with every
-weight and every layer input rounded to bfloat16 (round to nearest even),
-products accumulated in float32, biases and softplus in float32, the SDF
-output row's weights also in bfloat16.  Plain torch CPU float32 ops, one cell
+the march is defined here as: the SDF MLP of eq. 3 (Sec. 3.1) with its two
+hidden layers written for u' = k u, k = beta / ln 2, which leaves eq. 3
+unchanged in exact arithmetic since 2k softplus(u) = u' + |u'| +
+2 log2(1 + 2^-|u'|); every weight (k W1, W2 / 2) and every layer input (the
+encoding, 2k a1, 2k a2) rounded to bfloat16 (round to nearest even),
+products accumulated in float32, biases and activations in float32; the
+output row W3 / (2k) as a pair hi = bf16(w), lo = bf16(w - hi), whose two
+products are added.  Plain torch CPU float32 ops, one cell
 at a time.  The fp8 e4m3 variant (sdf_fp8) rounds the two hidden layers'
 weights and inputs to e4m3 with power-of-two per-(cell, layer) scales.
 
@@ -101,8 +105,8 @@ def sdf_fp8(scene, pts: np.ndarray, quantize: bool = True) -> np.ndarray:
     """SDF value of the cell containing each world point, fp8 e4m3 variant:
     the encoding (scale 1) and W1 / s1 rounded to e4m3; u1 = s1 (W1q eq) + b1;
     a1 = softplus(u1) scaled by 1 / sa and rounded; u2 = s2 sa (W2q a1q) + b2;
-    a2 = softplus(u2); output row and a2 in bfloat16, as the bfloat16 variant.
-    quantize=False skips every rounding (float32 throughout)."""
+    a2 = softplus(u2) in bfloat16; the output row W3 as a hi + lo bfloat16
+    pair.  quantize=False skips every rounding (float32 throughout)."""
     q = e4m3 if quantize else (lambda t: t.float())
     qb = _bf16 if quantize else (lambda t: t.float())
     out = torch.zeros(len(pts), dtype=torch.float32)
@@ -115,18 +119,34 @@ def sdf_fp8(scene, pts: np.ndarray, quantize: bool = True) -> np.ndarray:
         a1 = _softplus(u1, scene.beta)
         u2 = (q(a1 / sa) @ q(W2 / s2).T) * (s2 * sa) + b2
         a2 = _softplus(u2, scene.beta)
-        out[m] = qb(a2) @ qb(W3[0]) + b3[0]
+        hi, lo = _split(W3[0], qb)
+        out[m] = (qb(a2) @ hi + qb(a2) @ lo) + b3[0]
     return out.numpy()
+
+
+def _split(w: torch.Tensor, qb) -> tuple:
+    """A float32 row as hi = bf16(w) and lo = bf16(w - hi) (with qb the
+    identity: w and 0)."""
+    hi = qb(w.float())
+    return hi, qb(w.float() - hi)
+
+
+def _softplus_2k(up: torch.Tensor) -> torch.Tensor:
+    """2k softplus(u) from u' = k u (k = beta / ln 2)."""
+    return up + up.abs() + 2.0 * torch.log2(1.0 + torch.exp2(-up.abs()))
 
 
 def sdf_bf16(scene, pts: np.ndarray, quantize: bool = True) -> np.ndarray:
     """SDF value of the cell containing each world point (points clamped to
-    the grid), bfloat16 variant; quantize=False skips every rounding."""
+    the grid), bfloat16 variant; quantize=False skips every rounding.  The
+    scaled weights are formed in float64 and rounded to float32 first."""
     qb = _bf16 if quantize else (lambda t: t.float())
+    k = scene.beta / math.log(2.0)
     out = torch.zeros(len(pts), dtype=torch.float32)
     for m, xl, (W1, b1, W2, b2, W3, b3) in _cell_blocks(scene, pts):
         e = qb(_encode(xl, 6))
-        a1 = _softplus(e @ qb(W1).T + b1, scene.beta)
-        a2 = _softplus(qb(a1) @ qb(W2).T + b2, scene.beta)
-        out[m] = qb(a2) @ qb(W3[0]) + b3[0]
+        a1 = _softplus_2k(e @ qb((k * W1.double()).float()).T + (k * b1.double()).float())
+        a2 = _softplus_2k(qb(a1) @ qb(0.5 * W2).T + (k * b2.double()).float())
+        hi, lo = _split((W3[0].double() * (0.5 / k)).float(), qb)
+        out[m] = (qb(a2) @ hi + qb(a2) @ lo) + b3[0]
     return out.numpy()

@@ -54,6 +54,14 @@ __device__ __forceinline__ float softplus_x2(float u, SoftplusK k) {
   return fmaf(__builtin_amdgcn_logf(1.0f + e), 2.0f * k.ln2b, u + fabsf(u));
 }
 
+// 2k softplus(u) from u' = k u with k = beta log2(e):
+// u' + |u'| + 2 log2(1 + 2^(-|u'|)); the negated absolute value is a source
+// modifier of the exponential, so the scale costs no instruction
+__device__ __forceinline__ float softplus_x2k(float up) {
+  float e = __builtin_amdgcn_exp2f(-fabsf(up));
+  return fmaf(__builtin_amdgcn_logf(1.0f + e), 2.0f, up + fabsf(up));
+}
+
 __device__ __forceinline__ float softplus(float u, SoftplusK k) {
   float e = __builtin_amdgcn_exp2f(k.nbl2e * fabsf(u));
   return fmaf(__builtin_amdgcn_logf(1.0f + e), k.ln2b, 0.5f * (u + fabsf(u)));

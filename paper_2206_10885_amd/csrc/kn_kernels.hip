@@ -640,7 +640,8 @@ __device__ __forceinline__ float march_eval_f32(const float* blk, int lane, int 
 }
 
 // bfloat16: A fragments ([frag][lane] x 8 bf16) from the LDS block; every
-// layer input rounded to bfloat16, float32 accumulation, bias and softplus
+// layer input rounded to bfloat16, float32 accumulation, bias and softplus;
+// the hidden layers' pre-activations come out scaled by beta log2(e)
 template <int H>
 __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int g, const float (&v)[kPeSlots],
                                                  SoftplusK k) {
@@ -671,7 +672,7 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
 #pragma unroll
   for (int c = 0; c < H / 32; ++c)
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus_x2(acc[2 * c + i / 4][i % 4], k);
+    for (int i = 0; i < 8; ++i) x[c][i] = (__bf16)softplus_x2k(acc[2 * c + i / 4][i % 4]);
   f32x4 acc2[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc2[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -683,16 +684,17 @@ __device__ __forceinline__ float march_eval_bf16(const float* blk, int lane, int
 #pragma unroll
     for (int b = 0; b < NB; ++b) acc2[b] = mfma_bf16(__builtin_bit_cast(bf16x8, wf[b]), x[c], acc2[b]);
   }
-  // SDF output row on MFMA: row 0 of the product, in lane group 0
+  // SDF output row on MFMA: rows 0 (bfloat16 weights) and 1 (their
+  // remainders) of the product, in lane group 0
   f32x4 y = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int c = 0; c < H / 32; ++c) {
     bf16x8 x2;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) x2[i] = (__bf16)softplus_x2(acc2[2 * c + i / 4][i % 4], k);
+    for (int i = 0; i < 8; ++i) x2[i] = (__bf16)softplus_x2k(acc2[2 * c + i / 4][i % 4]);
     y = mfma_bf16(__builtin_bit_cast(bf16x8, fr[(F2 + c) * 64 + lane]), x2, y);
   }
-  return y[0] + vec[3 * H];
+  return (y[0] + y[1]) + vec[3 * H];   // output row: hi (row 0) + lo (row 1)
 }
 
 // fp8: one tile through the two-tile evaluator (used by the point query)
@@ -801,8 +803,8 @@ __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int
   for (int c = 0; c < H / 32; ++c)
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      x0[c][i] = (__bf16)softplus_x2(acc0[2 * c + i / 4][i % 4], k);
-      x1[c][i] = (__bf16)softplus_x2(acc1[2 * c + i / 4][i % 4], k);
+      x0[c][i] = (__bf16)softplus_x2k(acc0[2 * c + i / 4][i % 4]);
+      x1[c][i] = (__bf16)softplus_x2k(acc1[2 * c + i / 4][i % 4]);
     }
 #pragma unroll
   for (int b = 0; b < NB; ++b) acc1[b] = acc0[b] = *reinterpret_cast<const f32x4*>(vec + H + 16 * b + 4 * g);
@@ -820,25 +822,22 @@ __device__ __forceinline__ void march_eval2_bf16(const float* blk, int lane, int
     bf16x8 z0, z1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      z0[i] = (__bf16)softplus_x2(acc0[2 * c + i / 4][i % 4], k);
-      z1[i] = (__bf16)softplus_x2(acc1[2 * c + i / 4][i % 4], k);
+      z0[i] = (__bf16)softplus_x2k(acc0[2 * c + i / 4][i % 4]);
+      z1[i] = (__bf16)softplus_x2k(acc1[2 * c + i / 4][i % 4]);
     }
     const bf16x8 w = __builtin_bit_cast(bf16x8, fr[(F2 + c) * 64 + lane]);
     y0 = mfma_bf16(w, z0, y0);
     y1 = mfma_bf16(w, z1, y1);
   }
-  f0 = y0[0] + vec[3 * H];
-  f1 = y1[0] + vec[3 * H];
+  f0 = (y0[0] + y0[1]) + vec[3 * H];   // output row: hi (row 0) + lo (row 1)
+  f1 = (y1[0] + y1[1]) + vec[3 * H];
 }
 
 // fp8 e4m3: A fragments ([frag][lane] x 8 bytes); layer inputs quantised
-// with power-of-two scales (encoding: 1; a1: 1 / vec[3H+3]), the products
-// accumulated in float32, then u = acc * scale + bias; softplus in float32;
-// the SDF output row as in the bfloat16 variant.
-// fp8 e4m3: A fragments ([frag][lane] x 8 bytes); layer inputs quantised
-// with power-of-two scales (encoding: 1; a1: vec[3H+3] applied to 2 a1),
-// the products accumulated in float32, then u = acc * scale + bias; softplus
-// in float32; the SDF output row on bfloat16 MFMA as in the bfloat16 variant.
+// with power-of-two scales (encoding: 1; a1: vec[3H+3] applied to 2k a1),
+// the products accumulated in float32, then u = acc * scale + bias (for
+// layer 1 both stored times k = beta log2(e), as the bfloat16 block's);
+// softplus in float32; the SDF output row on bfloat16 MFMA.
 template <int H>
 __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int g, const float (&v0)[kPeSlots],
                                                 const float (&v1)[kPeSlots], SoftplusK k, float& f0, float& f1) {
@@ -870,8 +869,8 @@ __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int 
     for (int i = 0; i < 8; ++i) {
       const int b = 2 * c + i / 4, r = i % 4;
       const float bias = vec[16 * b + 4 * g + r];
-      q0[i] = fminf(softplus_x2(fmaf(acc0[b][r], s1, bias), k) * ia, kE4m3MaxF);
-      q1[i] = fminf(softplus_x2(fmaf(acc1[b][r], s1, bias), k) * ia, kE4m3MaxF);
+      q0[i] = fminf(softplus_x2k(fmaf(acc0[b][r], s1, bias)) * ia, kE4m3MaxF);
+      q1[i] = fminf(softplus_x2k(fmaf(acc1[b][r], s1, bias)) * ia, kE4m3MaxF);
     }
     x0[c] = fp8x8(q0[0], q0[1], q0[2], q0[3], q0[4], q0[5], q0[6], q0[7]);
     x1[c] = fp8x8(q1[0], q1[1], q1[2], q1[3], q1[4], q1[5], q1[6], q1[7]);
@@ -901,8 +900,8 @@ __device__ __forceinline__ void march_eval2_fp8(const float* blk, int lane, int 
     y0 = mfma_bf16(w, z0, y0);
     y1 = mfma_bf16(w, z1, y1);
   }
-  f0 = y0[0] + vec[3 * H];
-  f1 = y1[0] + vec[3 * H];
+  f0 = (y0[0] + y0[1]) + vec[3 * H];   // output row: hi (row 0) + lo (row 1)
+  f1 = (y1[0] + y1[1]) + vec[3 * H];
 }
 
 template <int H>
@@ -934,7 +933,7 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int b = 2 * c + i / 4, r = i % 4;
-      q[i] = fminf(softplus_x2(fmaf(acc[b][r], s1, vec[16 * b + 4 * g + r]), k) * ia, kE4m3MaxF);
+      q[i] = fminf(softplus_x2k(fmaf(acc[b][r], s1, vec[16 * b + 4 * g + r])) * ia, kE4m3MaxF);
     }
     x[c] = fp8x8(q[0], q[1], q[2], q[3], q[4], q[5], q[6], q[7]);
   }
@@ -959,7 +958,7 @@ __device__ __forceinline__ float march_eval_fp8(const float* blk, int lane, int 
     }
     y = mfma_bf16(__builtin_bit_cast(bf16x8, f3[c * 64 + lane]), z, y);
   }
-  return y[0] + vec[3 * H];
+  return (y[0] + y[1]) + vec[3 * H];   // output row: hi (row 0) + lo (row 1)
 }
 
 template <int H, int P>

@@ -90,19 +90,30 @@ static void pack_march_f32(const float* blk, int H, float* out) {
   vec[3 * H + 1] = vec[3 * H + 2] = vec[3 * H + 3] = 0.0f;
 }
 
-// SDF output row as bfloat16 MFMA A fragments (row 0 = the row, halved;
-// rows 1..15 zero), K order of the layer-2 outputs
-static void pack_w3_bf16(const SdfView& w, int H, uint16_t* out) {
+// SDF output row as bfloat16 MFMA A fragments, K order of the layer-2
+// outputs: row 0 = hi = bf16(w), row 1 = lo = bf16(w - hi) for the row
+// w = `scale` x W3[0] rounded to float32 (the two product rows add up to the
+// row at about 2^-16 relative); rows 2..15 zero
+static void pack_w3_bf16(const SdfView& w, int H, double scale, uint16_t* out) {
   for (int c = 0; c < H / 32; ++c)
     for (int lane = 0; lane < 64; ++lane) {
       const int m = lane % 16, g = lane / 16;
-      for (int i = 0; i < 8; ++i)
-        out[((size_t)c * 64 + lane) * 8 + i] = bf16_bits(m == 0 ? 0.5f * w.W3[unit_bf16(c, g, i)] : 0.0f);
+      for (int i = 0; i < 8; ++i) {
+        const float x = (float)(scale * w.W3[unit_bf16(c, g, i)]);
+        const float hi = bf16_value(x);
+        out[((size_t)c * 64 + lane) * 8 + i] = bf16_bits(m == 0 ? hi : m == 1 ? x - hi : 0.0f);
+      }
     }
 }
 
-static void pack_march_bf16(const float* blk, int H, float* out_words) {
+// bfloat16 march block.  The two hidden layers work on u' = k u with
+// k = beta log2(e): W1, b1 and b2 are stored times k, so the activation
+// 2k softplus(u) = u' + |u'| + 2 log2(1 + 2^(-|u'|)) needs no scaling
+// multiply; W2 keeps the factor 1/2 of the other blocks and the output row
+// takes 1/(2k).
+static void pack_march_bf16(const float* blk, int H, float beta, float* out_words) {
   const SdfView w = sdf_view(blk, H);
+  const double k = (double)beta / std::log(2.0);
   const int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
   uint16_t* out = reinterpret_cast<uint16_t*>(out_words);
   for (int f = 0; f < NF; ++f) {
@@ -113,21 +124,21 @@ static void pack_march_bf16(const float* blk, int H, float* out_words) {
         if (f < F1) {
           const int b = f / 2, c = f % 2, j = 8 * c + i;
           const int idx = j < kPeSlots ? pe_index(j, g) : -1;
-          val = idx < 0 ? 0.0f : w.W1[(16 * b + m) * kSdfIn + idx];
+          val = idx < 0 ? 0.0f : (float)(k * w.W1[(16 * b + m) * kSdfIn + idx]);
         } else {
           const int f2 = f - F1, b = f2 / (H / 32), c = f2 % (H / 32);
-          val = 0.5f * w.W2[(16 * b + m) * H + unit_bf16(c, g, i)];   // layer 1 hands on 2 softplus
+          val = 0.5f * w.W2[(16 * b + m) * H + unit_bf16(c, g, i)];   // layer 1 hands on 2k softplus
         }
         out[((size_t)f * 64 + lane) * 8 + i] = bf16_bits(val);
       }
     }
   }
-  pack_w3_bf16(w, H, out + (size_t)NF * 64 * 8);
+  pack_w3_bf16(w, H, 0.5 / k, out + (size_t)NF * 64 * 8);
   const int NFW = NF + H / 32;
   float* vec = out_words + 64 * 4 * NFW;
   for (int j = 0; j < H; ++j) {
-    vec[j] = w.b1[j];
-    vec[H + j] = w.b2[j];
+    vec[j] = (float)(k * w.b1[j]);
+    vec[H + j] = (float)(k * w.b2[j]);
     vec[2 * H + j] = bf16_value(w.W3[j]);
   }
   vec[3 * H] = w.b3[0];
@@ -142,8 +153,12 @@ static double softplus_host(double u, double beta) {
 // (absmax / 448 rounded up); the layer-2 input scale from a bound on the
 // layer-1 activations over inputs with |e_k| <= 1:
 //   a1_j <= softplus(sum_k |W1[j][k]| + b1[j]).
+// As in the bfloat16 block the first hidden layer works on u' = k u
+// (k = beta log2(e)), here through its dequantisation scale and bias: the
+// e4m3 layer-2 inputs are the same numbers; layer 2 keeps the plain scale.
 static void pack_march_fp8(const float* blk, int H, float beta, float* out_words) {
   const SdfView w = sdf_view(blk, H);
+  const double k = (double)beta / std::log(2.0);
   const int NB = H / 16, F1 = NB * 2, NF = F1 + NB * (H / 32);
   double m1 = 0.0, m2 = 0.0, abound = 0.0;
   for (int j = 0; j < H; ++j) {
@@ -174,17 +189,17 @@ static void pack_march_fp8(const float* blk, int H, float beta, float* out_words
       }
     }
   }
-  pack_w3_bf16(w, H, reinterpret_cast<uint16_t*>(out_words + 2 * 64 * NF));
+  pack_w3_bf16(w, H, 0.5, reinterpret_cast<uint16_t*>(out_words + 2 * 64 * NF));
   float* vec = out_words + 2 * 64 * NF + 4 * 64 * (H / 32);
   for (int j = 0; j < H; ++j) {
-    vec[j] = w.b1[j];
+    vec[j] = (float)(k * w.b1[j]);
     vec[H + j] = w.b2[j];
     vec[2 * H + j] = bf16_value(w.W3[j]);
   }
   vec[3 * H] = w.b3[0];
-  vec[3 * H + 1] = s1;
+  vec[3 * H + 1] = (float)(k * s1);
   vec[3 * H + 2] = s2 * sa;
-  vec[3 * H + 3] = 0.5f / sa;   // layer 1 hands on 2 softplus
+  vec[3 * H + 3] = (float)(0.5 / (sa * k));   // layer 1 hands on 2k softplus
 }
 
 static void pack_shade(const float* blk, const float* cblk, int H, float* out) {
@@ -707,8 +722,9 @@ kn_status kn_scene_create(kn_ctx* ctx, const kn_scene_desc* d, kn_scene_id* out)
               [&](size_t c, float* o) { pack_march_f32(d->sdf_params + c * psdf, H, o); });
   if (st != KN_OK) return st;
   if (want_bf16) {
+    const float beta = d->softplus_beta;
     st = upload(&s->march_bf16, s->march_bf16_words,
-                [&](size_t c, float* o) { pack_march_bf16(d->sdf_params + c * psdf, H, o); });
+                [&](size_t c, float* o) { pack_march_bf16(d->sdf_params + c * psdf, H, beta, o); });
     if (st != KN_OK) return st;
   }
   if (want_fp8) {
