@@ -100,10 +100,29 @@ __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int s
 // ---------------------------------------------------------------------------
 // ray generation: one thread per pixel
 // ---------------------------------------------------------------------------
+// Pixel of position t (< W H) in tile order: bands of 16 rows, each cut into
+// strips of 16 columns (the last band and strip narrower) taken row by row,
+// so a workgroup's 256 positions cover a 16 x 16 tile and a wave's 64 a
+// 16 x 4 one.  Rays binned together then enter the grid through few cells,
+// so far fewer per-cell atomics of the count and of the first scatter meet
+// at one address than with whole rows.
+__device__ __forceinline__ uint32_t tile_order_pixel(uint32_t t, uint32_t W, uint32_t H) {
+  const uint32_t band = t / (16u * W), row0 = 16u * band;
+  const uint32_t hb = min(16u, H - row0);
+  const uint32_t o = t - 16u * W * band;
+  const uint32_t s = o / (16u * hb), col0 = 16u * s;
+  const uint32_t ws = min(16u, W - col0);
+  const uint32_t q = o - 16u * hb * s;
+  return (row0 + q / ws) * W + col0 + q % ws;
+}
+
+// Primary rays: position t takes pixel tile_order_pixel(t); t is also the
+// ray's place in U and, offset by rid_base, its id.
 __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
   const uint32_t npix = (uint32_t)a.W * (uint32_t)a.Hh;
-  const uint32_t pix = blockIdx.x * 256u + threadIdx.x;
-  const bool valid = pix < npix;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  const bool valid = t < npix;
+  const uint32_t pix = valid ? tile_order_pixel(t, (uint32_t)a.W, (uint32_t)a.Hh) : 0u;
   const SceneGeom& sg = a.sg;
   uint32_t cell = 0;
   bool inbox = false;
@@ -111,7 +130,7 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
   float d[3] = {0, 0, 0};
   if (valid) {
     const int row = (int)(pix / (uint32_t)a.W), col = (int)(pix % (uint32_t)a.W);
-    const uint32_t rid = a.rid_base + pix;
+    const uint32_t rid = a.rid_base + t;
     const float u = (2.0f * ((float)col + 0.5f) / (float)a.W - 1.0f) * a.tx;
     const float v = (1.0f - 2.0f * ((float)row + 0.5f) / (float)a.Hh) * a.ty;
     float n2 = 0.0f;
@@ -145,9 +164,9 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
       cell = sg.cell_base + (uint32_t)(idx[0] + sg.N * (idx[1] + sg.N * idx[2]));
       a.rs[rid] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2],
                             (a.slot << kPixBits) | pix};
-      a.U[pix] = RayRec{t0, t0, cell, rid};
+      a.U[t] = RayRec{t0, t0, cell, rid};
     } else {
-      a.U[pix] = RayRec{0.0f, 0.0f, kInvalidKey, rid};
+      a.U[t] = RayRec{0.0f, 0.0f, kInvalidKey, rid};
       write_miss(a.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss);
     }
   }

@@ -58,7 +58,7 @@ struct RaygenArgs {
   uint32_t slot;           // request slot
   uint32_t rid_base;       // first pool ray id of the request
   RayStatic* rs;           // indexed by pool ray id
-  RayRec* U;               // this request's records (one per pixel)
+  RayRec* U;               // this request's records (one per pixel, in tile order)
   uint32_t* counts;        // arrivals per global cell for the next round
   uint32_t* miss_done;     // per slot
   OutPtrs out;
