@@ -29,22 +29,22 @@ constexpr uint32_t kInvalidKey = 0xFFFFFFFFu;  // record without a cell (box mis
 // ---------------------------------------------------------------------------
 // wave-aggregated atomics
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void atomic_count_grouped(uint32_t* arr, uint32_t key, bool valid) {
+__device__ __forceinline__ void atomic_count_grouped(uint32_t* arr, uint32_t cs, uint32_t key, bool valid) {
   uint64_t todo = __ballot(valid);
   while (todo) {
     int leader = __ffsll((unsigned long long)todo) - 1;
     uint32_t lk = __shfl(key, leader);
     uint64_t grp = __ballot(valid && key == lk);
-    if (lane_id() == leader) atomicAdd(&arr[lk], (uint32_t)__popcll(grp));
+    if (lane_id() == leader) atomicAdd(&arr[(size_t)lk * cs], (uint32_t)__popcll(grp));
     todo &= ~grp;
   }
 }
 
-// Reserves a slot in arr[key] for every valid lane.  The lanes are grouped by
+// Reserves a slot in arr[key * cs] for every valid lane.  The lanes are grouped by
 // key first (ballots only); then each group's first lane adds the group's size
 // with one atomic, all groups in the same instruction, so the wave waits for
 // a single round trip however many keys it holds.
-__device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t key, bool valid) {
+__device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t cs, uint32_t key, bool valid) {
   const int lane = lane_id();
   uint64_t todo = __ballot(valid);
   int leader = lane;
@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t 
     todo &= ~grp;
   }
   uint32_t base = 0;
-  if (valid && lane == leader) base = atomicAdd(&arr[key], size);
+  if (valid && lane == leader) base = atomicAdd(&arr[(size_t)key * cs], size);
   base = (uint32_t)__shfl((int)base, leader);
   return base + rank;
 }
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(256) void k_raygen(RaygenArgs a) {
       write_miss(a.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss);
     }
   }
-  atomic_count_grouped(a.counts, cell, inbox);
+  atomic_count_grouped(a.counts, a.cs, cell, inbox);
   __shared__ uint32_t s_cnt;
   wg_count(&a.miss_done[a.slot], valid && !inbox, &s_cnt);
 }
@@ -240,7 +240,7 @@ __global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
     }
     a.path[id] = pr;
   }
-  atomic_count_grouped(a.counts, cell, inbox);
+  atomic_count_grouped(a.counts, a.cs, cell, inbox);
   __shared__ uint32_t s_cnt;
   wg_count(&a.miss_done[a.slot], valid && !inbox, &s_cnt);
 }
@@ -313,13 +313,14 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
   const uint32_t nst = (s1 - s0 + 63u) >> 6;   // steps of 64 cells in this strip
   const uint32_t* counts = a.counts;
   const uint32_t* runs = a.runs;
+  const size_t cs = a.cs;
   uint32_t sr = 0, sk = 0;
   for (uint32_t q = 0; q < nst; q += 8u) {
     uint32_t v[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const uint32_t c = s0 + 64u * (q + (uint32_t)u) + lane;
-      v[u] = c < s1 ? counts[c] + (runs ? runs[c] : 0u) : 0u;
+      v[u] = c < s1 ? counts[(size_t)c * cs] + (runs ? runs[(size_t)c * cs] : 0u) : 0u;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -389,26 +390,26 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
   // the bin of cell c: the runs handed on to it first (at base[c]), then the
   // new records (cursor[c] = base[c] + runs[c])
   uint32_t c = s0 + lane;
-  uint32_t m1 = c < s1 ? counts[c] : 0u, m2 = c + 64u < s1 ? counts[c + 64u] : 0u;
-  uint32_t h1 = c < s1 && runs ? runs[c] : 0u, h2 = c + 64u < s1 && runs ? runs[c + 64u] : 0u;
+  uint32_t m1 = c < s1 ? counts[c * cs] : 0u, m2 = c + 64u < s1 ? counts[(c + 64u) * cs] : 0u;
+  uint32_t h1 = c < s1 && runs ? runs[c * cs] : 0u, h2 = c + 64u < s1 && runs ? runs[(c + 64u) * cs] : 0u;
   for (uint32_t q = 0; q < nst; ++q, c += 64u) {
     const uint32_t nm = m1, nh = h1;
     m1 = m2;
     h1 = h2;
-    m2 = c + 128u < s1 ? counts[c + 128u] : 0u;
-    h2 = c + 128u < s1 && runs ? runs[c + 128u] : 0u;
+    m2 = c + 128u < s1 ? counts[(c + 128u) * cs] : 0u;
+    h2 = c + 128u < s1 && runs ? runs[(c + 128u) * cs] : 0u;
     const uint32_t n = nm + nh;
     const uint32_t k = (n + tm) >> ts;
     const uint32_t ir = wave_incl_scan(n), ik = wave_incl_scan(k);
     if (n) {
       const uint32_t r = R + ir - n;
       uint32_t j = K + ik - k;
-      a.cursor[c] = r + nh;
+      a.cursor[c * cs] = r + nh;
       if (a.base) a.base[c] = r;
       for (uint32_t i = 0; i < n; i += a.T) a.chunks[j++] = make_uint2(c | (min(a.T, n - i) << kCellBits), r + i);
       if (a.zero_counts) {
-        if (nm) a.counts[c] = 0u;
-        if (nh) a.runs[c] = 0u;
+        if (nm) a.counts[c * cs] = 0u;
+        if (nh) a.runs[c * cs] = 0u;
       }
     }
     R += lane63(ir);
@@ -471,7 +472,7 @@ __global__ __launch_bounds__(256) void k_scatter(ScatterArgs a) {
     RayRec r = i < n ? a.in[i] : RayRec{0, 0, kInvalidKey, 0};
     const bool valid = r.key != kInvalidKey;
     const uint32_t cell = r.key & kCellMask;
-    const uint32_t pos = atomic_slot_grouped(a.cursor, cell, valid);
+    const uint32_t pos = atomic_slot_grouped(a.cursor, a.cs, cell, valid);
     if (valid) {
       a.out[pos] = r;
       if (a.clear_in) a.in[i].key = kInvalidKey;
@@ -1444,7 +1445,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
       a.chunk_out[4 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
       a.chunk_out[4 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
-      if (s_nhit) atomicAdd(&a.hit_count[cell], s_nhit);
+      if (s_nhit) atomicAdd(&a.hit_count[(size_t)cell * a.cs], s_nhit);
       wg_evals += s_evals;
       wg_tiles += s_tiles;
       ++wg_chunks;
@@ -1454,7 +1455,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       // next work item, after a wait that staging makes anyway, so the
       // atomic's round trip is never waited for on its own
       const uint32_t f = (uint32_t)tid - 1u, n = s_face[f];
-      pend_off = atomicAdd(&a.runs_next[n ? neighbor_cell(sg, cell, (int)f) : cell], n);
+      pend_off = atomicAdd(&a.runs_next[(size_t)(n ? neighbor_cell(sg, cell, (int)f) : cell) * a.cs], n);
       pend_job = job;
     }
     __syncthreads();
@@ -1864,7 +1865,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           if (spawn) a.spawn[sp_cur + (uint32_t)__popcll(sm & lanemask_lt())] = nrec;
           sp_cur += ns;
         }
-        atomic_count_grouped(a.counts_next, ncell, spawn);
+        atomic_count_grouped(a.counts_next, a.cs, ncell, spawn);
       }
       if (done) atomicAdd(&s_done[slot], 1u);
       }
@@ -1893,7 +1894,7 @@ __global__ __launch_bounds__(256) void k_query_bin(QueryBinArgs a) {
     cell = a.sg.cell_base + (uint32_t)(idx[0] + a.sg.N * (idx[1] + a.sg.N * idx[2]));
     a.U[i] = RayRec{0.0f, 0.0f, cell, (uint32_t)i};
   }
-  atomic_count_grouped(a.counts, cell, valid);
+  atomic_count_grouped(a.counts, a.cs, cell, valid);
 }
 
 template <int H, int P>
@@ -1987,12 +1988,14 @@ __global__ __launch_bounds__(256) void k_query_full(QueryArgs a) {
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   const uint32_t npix = (uint32_t)a.W * (uint32_t)a.Hh;
   hipLaunchKernelGGL(k_raygen, dim3((npix + 255u) / 256u), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   if (a.T == 0 || a.T > 512 || (a.T & (a.T - 1u)) != 0) return hipErrorInvalidValue;
   if (!a.ticket || !a.flags || !a.err) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_scan, dim3(kScanTiles), dim3(256), 0, st, a);
@@ -2000,6 +2003,7 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_scatter(const ScatterArgs& a, uint32_t grid, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   hipLaunchKernelGGL(k_scatter, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
@@ -2033,6 +2037,7 @@ static hipError_t march_p(const MarchArgs& a, int prec, uint32_t block_words, ui
 
 hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_words, uint32_t grid,
                         hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   if (H == 32) return march_p<32>(a, prec, block_words, grid, st);
   if (H == 64) return march_p<64>(a, prec, block_words, grid, st);
   if (H == 0) return march_p<0>(a, prec, block_words, grid, st);
@@ -2050,6 +2055,7 @@ static hipError_t shade_t(const ShadeArgs& a, int H, size_t lds, uint32_t grid, 
 
 hipError_t launch_shade(const ShadeArgs& a, int H, int prec, bool pt, uint32_t block_words, uint32_t grid,
                         hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   const size_t lds = shade_lds_bytes(block_words);
   const bool b3 = prec != kPrecF32;
   if (pt) return b3 ? shade_t<true, true>(a, H, lds, grid, st) : shade_t<true, false>(a, H, lds, grid, st);
@@ -2057,6 +2063,7 @@ hipError_t launch_shade(const ShadeArgs& a, int H, int prec, bool pt, uint32_t b
 }
 
 hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   const uint32_t n = (uint32_t)a.W * (uint32_t)a.Hh * a.spp;
   hipLaunchKernelGGL(k_raygen_pt, dim3((n + 255u) / 256u), dim3(256), 0, st, a);
   return hipGetLastError();
@@ -2068,6 +2075,7 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   hipLaunchKernelGGL(k_query_bin, dim3((uint32_t)((a.n + 255u) / 256u)), dim3(256), 0, st, a);
   return hipGetLastError();
 }

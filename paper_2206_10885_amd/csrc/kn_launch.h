@@ -59,7 +59,8 @@ struct RaygenArgs {
   uint32_t rid_base;       // first pool ray id of the request
   RayStatic* rs;           // indexed by pool ray id
   RayRec* U;               // this request's records (one per pixel, in tile order)
-  uint32_t* counts;        // arrivals per global cell for the next round
+  uint32_t* counts;        // arrivals per global cell for the next round (cell c at c * cs)
+  uint32_t cs;             // words between the per-cell counters of a pool (>= 1)
   uint32_t* miss_done;     // per slot
   OutPtrs out;
 };
@@ -78,7 +79,8 @@ struct RaygenPtArgs {
   RayStatic* rs;
   RayRec* U;               // one record per path (index = pool ray id)
   PathRec* path;
-  uint32_t* counts;
+  uint32_t* counts;        // cell c at c * cs
+  uint32_t cs;
   uint32_t* miss_done;     // paths finished, per slot
   OutPtrs out;
 };
@@ -106,6 +108,7 @@ struct ScanArgs {
   uint32_t* ticket;      // Ctrl::scan_ticket
   unsigned long long* flags;  // Ctrl::scan_flags
   uint32_t* err;         // Ctrl::scan_err
+  uint32_t cs;           // counts, runs and cursor hold cell c at c * cs (base: at c)
 };
 
 struct ScatterArgs {
@@ -113,8 +116,9 @@ struct ScatterArgs {
   RayRec* out;
   uint32_t n;            // number of records, or
   const uint32_t* n_dev; // if not null: the number of records, read on the device
-  uint32_t* cursor;
+  uint32_t* cursor;      // cell c at c * cs
   int clear_in;          // mark each record taken as invalid (hits indexed by ray id)
+  uint32_t cs;
 };
 
 struct ScatterChunksArgs {
@@ -137,11 +141,12 @@ struct MarchArgs {
   uint4* chunk_out;          // per chunk (4 x uint4): rays leaving through each face /
                              // staying, hits; then each run's offset in its next bin
   RayRec* U;                 // next-round rays, in each chunk's own range
-  uint32_t* runs_next;       // per cell: rays this round's chunks hand on to it
+  uint32_t* runs_next;       // per cell: rays this round's chunks hand on to it (cell c at c * cs)
   RayRec* hits;              // hits, indexed by pool ray id (invalid key: none)
-  uint32_t* hit_count;       // hits per cell
+  uint32_t* hit_count;       // hits per cell (cell c at c * cs)
   unsigned long long* evals;     // [0] evaluations, [1] tiles, [2] chunks
   int max_passes;            // in-cell passes per chunk before the rest wait a round
+  uint32_t cs;               // words between per-cell counters
 };
 
 struct ShadeArgs {
@@ -153,7 +158,8 @@ struct ShadeArgs {
   uint32_t* grab;        // per-range work cursors set by the scan
   RayRec* spawn;         // path tracing: records of the next segments
   uint32_t* n_spawn;     // their count
-  uint32_t* counts_next; // arrivals per cell for the next round
+  uint32_t* counts_next; // arrivals per cell for the next round (cell c at c * cs)
+  uint32_t cs;
 };
 
 struct QueryBinArgs {
@@ -161,7 +167,8 @@ struct QueryBinArgs {
   const float* pts;
   uint64_t n;
   RayRec* U;
-  uint32_t* counts;
+  uint32_t* counts;      // cell c at c * cs
+  uint32_t cs;
 };
 
 struct QueryArgs {

@@ -320,10 +320,13 @@ struct Pool {
   RayRec* Uin = nullptr;           // records of newly generated rays
   RayRec* HL = nullptr;            // hit list since the last shading pass
   PathRec* path = nullptr;         // path tracing state (allocated on first use)
-  uint32_t* counts = nullptr;      // [2][cells]: new records arriving for a round
-  uint32_t* runs = nullptr;        // [2][cells]: rays handed on by the previous round's chunks
-  uint32_t* hit_count = nullptr;   // [cells]
-  uint32_t* cursor = nullptr;      // [cells]
+  // per-cell counters, cell c at word c * cs: on grids of up to
+  // kPadCells cells each counter has a 128-byte line of its own
+  uint32_t cs = 1;
+  uint32_t* counts = nullptr;      // [2][cells * cs]: new records arriving for a round
+  uint32_t* runs = nullptr;        // [2][cells * cs]: rays handed on by the previous round's chunks
+  uint32_t* hit_count = nullptr;   // [cells * cs]
+  uint32_t* cursor = nullptr;      // [cells * cs]
   uint32_t* base = nullptr;        // [cells]: bin starts of the current round
   uint2* chunk = nullptr;          // [3][chunks]: rounds of parity 0 / 1, shading
   uint4* chunk_out = nullptr;      // [2][chunks][4]
@@ -389,8 +392,18 @@ constexpr size_t kRayBytes = sizeof(RayStatic) + 4 * sizeof(RayRec);
 
 size_t uin_entries(size_t R) { return R + R / 8 + kListSlack; }
 
+// Per-cell counters are targets of atomics from many workgroups at once
+// (arrivals, bin cursors, runs, hits).  Counters of neighbouring cells share
+// a cache line when packed, and on a view that enters the grid through a
+// face of consecutive cells their atomics queue at the same line; one line
+// per counter removes that.  Large pools stay packed: the scan reads every
+// counter each round.
+constexpr size_t kPadCells = 65536;
+uint32_t counter_stride(size_t C) { return C <= kPadCells ? 32u : 1u; }
+
 size_t pool_bytes(size_t R, size_t C, size_t K) {
-  return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * 7 + K * (3 * 8 + 2 * 64) +
+  return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * (6 * (size_t)counter_stride(C) + 1) +
+         K * (3 * 8 + 2 * 64) +
          sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) + kMaxSlots * sizeof(ReqEnt);
 }
 
@@ -413,6 +426,7 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   n.cells = C;
   n.chunks = K;
   n.bytes = bytes;
+  n.cs = counter_stride(C);
   KN_HIP(ctx, hipMalloc(&n.rs, R * sizeof(RayStatic)));
   KN_HIP(ctx, hipMalloc(&n.U, R * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.S, R * sizeof(RayRec)));
@@ -422,10 +436,10 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.Uin, uin_entries(R) * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
   if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
-  KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * 4));
-  KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * 4));
-  KN_HIP(ctx, hipMalloc(&n.hit_count, C * 4));
-  KN_HIP(ctx, hipMalloc(&n.cursor, C * 4));
+  KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * n.cs * 4));
+  KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * n.cs * 4));
+  KN_HIP(ctx, hipMalloc(&n.hit_count, C * n.cs * 4));
+  KN_HIP(ctx, hipMalloc(&n.cursor, C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.base, C * 4));
   KN_HIP(ctx, hipMalloc(&n.chunk, 3 * K * 8));
   KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 64));
@@ -490,8 +504,9 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   const int par = r & 1;
   const PoolTabs tabs = pool_tabs(w, c.n_scenes);
   ScanArgs sa{};
-  sa.counts = w.counts + par * w.cells;
-  sa.runs = w.runs + par * w.cells;
+  sa.counts = w.counts + par * w.cells * w.cs;
+  sa.runs = w.runs + par * w.cells * w.cs;
+  sa.cs = w.cs;
   sa.base = w.base;
   sa.C = c.cells;
   sa.T = kChunk;
@@ -518,11 +533,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
     KN_HIP(ctx, launch_scatter_chunks(sc, persistent_grid(ctx, 16), st));
   }
   if (n_new) {
-    ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor, 0};
+    ScatterArgs sc{w.Uin, w.S, n_new, nullptr, w.cursor, 0, w.cs};
     KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_new + 255u) / 256u, 65536u), st));
   }
   if (n_new_dev) {
-    ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor, 0};
+    ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor, 0, w.cs};
     KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
   }
   MarchArgs ma{};
@@ -534,9 +549,10 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.grab = w.ctrl->grab;
   ma.chunk_out = w.chunk_out + (size_t)par * w.chunks * 4;
   ma.U = w.U;
-  ma.runs_next = w.runs + (par ^ 1) * w.cells;
+  ma.runs_next = w.runs + (par ^ 1) * w.cells * w.cs;
   ma.hits = w.HL;
   ma.hit_count = w.hit_count;
+  ma.cs = w.cs;
   ma.evals = &w.ctrl->evals;
   ma.max_passes = c.max_passes;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
@@ -554,6 +570,7 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   uint2* chunks = w.chunk + 2 * w.chunks;
   ScanArgs sa{};
   sa.counts = w.hit_count;
+  sa.cs = w.cs;
   sa.C = c.cells;
   sa.T = kShadeChunk;
   sa.zero_counts = 1;
@@ -568,7 +585,7 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sa.zero_word = pt ? &w.ctrl->n_in : nullptr;
   sa.total = &w.ctrl->n_hits;
   KN_HIP(ctx, launch_scan(sa, st));
-  ScatterArgs sc{w.HL, w.S, n_ids, nullptr, w.cursor, 1};
+  ScatterArgs sc{w.HL, w.S, n_ids, nullptr, w.cursor, 1, w.cs};
   KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_ids + 255u) / 256u, 65536u), st));
   ShadeArgs sh{};
   sh.tabs = pool_tabs(w, c.n_scenes);
@@ -579,7 +596,8 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sh.grab = w.ctrl->grab;
   sh.spawn = w.Uin;
   sh.n_spawn = &w.ctrl->n_in;
-  sh.counts_next = w.counts + (next_round & 1) * w.cells;
+  sh.counts_next = w.counts + (next_round & 1) * w.cells * w.cs;
+  sh.cs = w.cs;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
   KN_HIP(ctx, launch_shade(sh, c.hmode, c.prec, pt, c.shade_words, persistent_grid(ctx, 3), st));
   if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
@@ -911,9 +929,9 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   KN_HIP(ctx, hipMemcpyAsync(w.reqs, ctx->h_req, sizeof(ReqEnt), hipMemcpyHostToDevice, stream));
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
   // both parities of the per-cell counts ([2][w.cells]) and the hit counts
-  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * 4, stream));
-  KN_HIP(ctx, hipMemsetAsync(w.runs, 0, 2 * w.cells * 4, stream));
-  KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * w.cs * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.runs, 0, 2 * w.cells * w.cs * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * w.cs * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
 
   RaygenArgs rg{};
@@ -928,6 +946,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     rg.rs = w.rs;
     rg.U = w.Uin;
     rg.counts = w.counts;
+    rg.cs = w.cs;
     rg.miss_done = &w.ctrl->miss_done[0];
     rg.out = q.out;
     KN_HIP(ctx, launch_raygen(rg, stream));
@@ -983,6 +1002,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     rp.U = w.Uin;
     rp.path = w.path;
     rp.counts = w.counts;
+    rp.cs = w.cs;
     rp.miss_done = &w.ctrl->miss_done[0];
     rp.out = q.out;
     KN_HIP(ctx, launch_raygen_pt(rp, stream));
@@ -1096,11 +1116,12 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   Pool& w = ctx->ws;
   const SoftplusK spk = softplus_consts(s->geom.beta);
   KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
-  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, cells * 4, stream));
-  QueryBinArgs qb{s->geom, points, n, w.U, w.counts};
+  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, cells * w.cs * 4, stream));
+  QueryBinArgs qb{s->geom, points, n, w.U, w.counts, w.cs};
   KN_HIP(ctx, launch_query_bin(qb, stream));
   ScanArgs sa{};
   sa.counts = w.counts;
+  sa.cs = w.cs;
   sa.C = (uint32_t)cells;
   sa.T = kQueryChunk;
   sa.zero_counts = 0;
@@ -1114,7 +1135,7 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   sa.err = &w.ctrl->scan_err;
   sa.zero_word = nullptr;
   KN_HIP(ctx, launch_scan(sa, stream));
-  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0};
+  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0, w.cs};
   KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536), stream));
   QueryArgs qa{};
   qa.sg = s->geom;
@@ -1192,9 +1213,9 @@ class ServeLoop {
     KN_HIP(ctx, hipHostMalloc((void**)&h_scenes, kMaxScenes * sizeof(SceneEnt), hipHostMallocDefault));
     KN_HIP(ctx, hipHostMalloc((void**)&h_reqs, kMaxSlots * sizeof(ReqEnt), hipHostMallocDefault));
     KN_HIP(ctx, hipMemsetAsync(pool.ctrl, 0, sizeof(Ctrl), stream));
-    KN_HIP(ctx, hipMemsetAsync(pool.counts, 0, 2 * pool.cells * 4, stream));
-    KN_HIP(ctx, hipMemsetAsync(pool.runs, 0, 2 * pool.cells * 4, stream));
-    KN_HIP(ctx, hipMemsetAsync(pool.hit_count, 0, pool.cells * 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.counts, 0, 2 * pool.cells * pool.cs * 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.runs, 0, 2 * pool.cells * pool.cs * 4, stream));
+    KN_HIP(ctx, hipMemsetAsync(pool.hit_count, 0, pool.cells * pool.cs * 4, stream));
     KN_HIP(ctx, hipStreamSynchronize(stream));
     free_ranges[0] = pool.cap;
     th = std::thread([this] { run(); });
@@ -1440,7 +1461,8 @@ class ServeLoop {
     rg.rid_base = (uint32_t)q->base;
     rg.rs = pool.rs;
     rg.U = pool.Uin + *n_new;
-    rg.counts = pool.counts + (r & 1) * pool.cells;
+    rg.counts = pool.counts + (r & 1) * pool.cells * pool.cs;
+    rg.cs = pool.cs;
     rg.miss_done = &pool.ctrl->miss_done[0];
     rg.out = q->out;
     KN_HIP(ctx, launch_raygen(rg, stream));
