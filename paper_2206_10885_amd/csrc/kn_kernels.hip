@@ -1473,10 +1473,11 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   if (tid >= 1 && tid <= 7 && pend_job != kNoJob)
     reinterpret_cast<uint32_t*>(a.chunk_out)[16u * pend_job + 8u + (uint32_t)tid - 1u] = pend_off;
   if (tid < kMaxSlots && s_miss[tid]) atomicAdd(&a.tabs.miss_done[tid], s_miss[tid]);
-  if (tid == 0 && wg_chunks) {
-    atomicAdd(&a.evals[0], wg_evals);
-    atomicAdd(&a.evals[1], wg_tiles);
-    atomicAdd(&a.evals[2], wg_chunks);
+  if (tid == 0 && wg_chunks) {   // this workgroup's line of the tallies
+    unsigned long long* ev = a.evals + (size_t)(blockIdx.x % kTallyLines) * 16u;
+    atomicAdd(&ev[0], wg_evals);
+    atomicAdd(&ev[1], wg_tiles);
+    atomicAdd(&ev[2], wg_chunks);
   }
 }
 

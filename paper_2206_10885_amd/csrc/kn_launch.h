@@ -144,7 +144,7 @@ struct MarchArgs {
   uint32_t* runs_next;       // per cell: rays this round's chunks hand on to it (cell c at c * cs)
   RayRec* hits;              // hits, indexed by pool ray id (invalid key: none)
   uint32_t* hit_count;       // hits per cell (cell c at c * cs)
-  unsigned long long* evals;     // [0] evaluations, [1] tiles, [2] chunks
+  unsigned long long* evals;     // Ctrl::tally: [kTallyLines][16], per line evaluations, tiles, chunks
   int max_passes;            // in-cell passes per chunk before the rest wait a round
   uint32_t cs;               // words between per-cell counters
 };

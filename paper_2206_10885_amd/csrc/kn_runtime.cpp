@@ -553,7 +553,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.hits = w.HL;
   ma.hit_count = w.hit_count;
   ma.cs = w.cs;
-  ma.evals = &w.ctrl->evals;
+  ma.evals = &w.ctrl->tally[0][0];
   ma.max_passes = c.max_passes;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
   KN_HIP(ctx, launch_march(ma, c.hmode, c.prec, c.march_words, persistent_grid(ctx, 4), st));
@@ -1049,9 +1049,12 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     stats->wall_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
     stats->rays = rays;
-    stats->evals = hc.evals;
-    stats->march_tiles = hc.tiles;
-    stats->march_chunks = hc.chunks;
+    stats->evals = stats->march_tiles = stats->march_chunks = 0;
+    for (uint32_t l = 0; l < kTallyLines; ++l) {
+      stats->evals += hc.tally[l][0];
+      stats->march_tiles += hc.tally[l][1];
+      stats->march_chunks += hc.tally[l][2];
+    }
     stats->hits = hc.n_hits;
     stats->rounds = (uint64_t)rounds;
     stats->march_launches = 0;
