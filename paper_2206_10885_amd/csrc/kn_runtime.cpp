@@ -9,6 +9,7 @@
 #include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -398,8 +399,16 @@ size_t uin_entries(size_t R) { return R + R / 8 + kListSlack; }
 // face of consecutive cells their atomics queue at the same line; one line
 // per counter removes that.  Large pools stay packed: the scan reads every
 // counter each round.
+// The environment variable KN_COUNTER_STRIDE (1 or 32) overrides the choice
+// for pools created afterwards; tests use it to compare the two layouts.
 constexpr size_t kPadCells = 65536;
-uint32_t counter_stride(size_t C) { return C <= kPadCells ? 32u : 1u; }
+uint32_t counter_stride(size_t C) {
+  if (const char* e = std::getenv("KN_COUNTER_STRIDE")) {
+    if (std::strcmp(e, "1") == 0) return 1u;
+    if (std::strcmp(e, "32") == 0) return 32u;
+  }
+  return C <= kPadCells ? 32u : 1u;
+}
 
 size_t pool_bytes(size_t R, size_t C, size_t K) {
   return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * (6 * (size_t)counter_stride(C) + 1) +

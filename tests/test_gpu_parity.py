@@ -2,6 +2,7 @@
 
 All calls go through the C ABI (libkn.so via the ctypes binding)."""
 import math
+import os
 import sys
 
 import numpy as np
@@ -270,6 +271,28 @@ def test_split_bf16_shading_on_the_same_surface(ctx, precision):
     assert same.sum() > 0.9 * both.sum()
     assert ok.mean() >= MIN_OK[precision]
     ctx.scene_destroy(sid)
+
+
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_counter_layouts_give_the_same_frame(precision):
+    """Per-cell counters one per 128-byte line (grids up to 65536 cells) or
+    packed (larger pools): the same frame, bit for bit."""
+    from paper_2206_10885_amd import kn
+    sc = synth.config_scene("c1")
+    view = synth.config_views("c1")[0]
+    outs = []
+    for stride in ("32", "1"):
+        os.environ["KN_COUNTER_STRIDE"] = stride
+        try:
+            with kn.Context(0) as c:
+                sid = c.scene_create(sc, precisions=("bf16",))
+                out = _render(c, sid, view, 320, 180, 96, precision=precision)
+                torch.cuda.synchronize()
+                outs.append({k: v.cpu().clone() for k, v in out.items() if torch.is_tensor(v)})
+        finally:
+            del os.environ["KN_COUNTER_STRIDE"]
+    for k in ("rgb", "depth", "normal", "hit", "steps"):
+        assert torch.equal(outs[0][k], outs[1][k]), k
 
 
 def test_render_deterministic(ctx):
