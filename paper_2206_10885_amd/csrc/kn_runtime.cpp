@@ -565,11 +565,12 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.evals = &w.ctrl->tally[0][0];
   ma.max_passes = c.max_passes;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
-  // bf16 and fp8 march kernels hold 3 workgroups per CU (3 waves per SIMD,
-  // about 33 KB of LDS each): a larger grid only adds workgroups that start
-  // as others exit, find the work taken and exit (bf16 march 3.44 -> 3.38 ms
-  // per 1080p frame).  The float32 kernel keeps 4 per CU, measured best.
-  const uint32_t march_per_cu = c.prec == KN_FP32 ? 4u : 3u;
+  // the grid is what the CUs hold at once: bf16 and fp8 march kernels 3
+  // workgroups per CU (3 waves per SIMD, about 33 KB of LDS each), the
+  // float32 one 2 (about 220 VGPRs).  A larger grid only adds workgroups
+  // that start as others exit, find the work taken and exit (bf16 march
+  // 3.44 -> 3.38 ms, fp32 9.02 -> 8.97 ms per 1080p frame).
+  const uint32_t march_per_cu = c.prec == KN_FP32 ? 2u : 3u;
   KN_HIP(ctx, launch_march(ma, c.hmode, c.prec, c.march_words, persistent_grid(ctx, march_per_cu), st));
   if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
   return KN_OK;
