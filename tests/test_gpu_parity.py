@@ -295,6 +295,21 @@ def test_counter_layouts_give_the_same_frame(precision):
         assert torch.equal(outs[0][k], outs[1][k]), k
 
 
+@pytest.mark.parametrize("precision", ["bf16", "fp32"])
+def test_march_tallies_count_every_evaluation(ctx, precision):
+    """Every SDF evaluation of the march adds one to its ray's step count, so
+    the evaluations tallied over the workgroups' lines equal the sum of the
+    per-pixel step counts."""
+    sc = synth.config_scene("c1")
+    view = synth.config_views("c1")[0]
+    sid = ctx.scene_create(sc, precisions=("bf16",))
+    out = _render(ctx, sid, view, 320, 180, 96, precision=precision)
+    torch.cuda.synchronize()
+    st = out["stats"]
+    assert st["evals"] == int(out["steps"].long().sum())
+    assert 0 < st["march_chunks"] <= st["march_tiles"] <= st["evals"]
+
+
 def test_render_deterministic(ctx):
     sc = synth.config_scene("c1")
     sid = ctx.scene_create(sc)
