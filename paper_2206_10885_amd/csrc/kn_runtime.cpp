@@ -1,6 +1,7 @@
 // Host runtime of the C ABI (include/kn.h): contexts, scene packing, the
 // per-frame round driver, the point query, and the serving loop.
 #include <hip/hip_runtime.h>
+#include <link.h>
 
 #include <algorithm>
 #include <atomic>
@@ -8,6 +9,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -37,6 +39,28 @@ kn_status fail(kn_status s, const char* fmt, ...) {
   va_end(ap);
   g_err = buf;
   return s;
+}
+
+// Paths of the HIP runtimes (libamdhip64.so*) mapped into this process.  A
+// process that loads this library before another program's own copy of the
+// runtime (torch wheels ship one, with a different file name) ends up with
+// two: each keeps its own devices, streams and allocations, and a pointer or
+// stream of one passed to the other crashes the process.
+std::vector<std::string> hip_runtimes_loaded() {
+  std::vector<std::string> found;
+  dl_iterate_phdr(
+      [](struct dl_phdr_info* info, size_t, void* data) -> int {
+        auto* v = static_cast<std::vector<std::string>*>(data);
+        const char* path = info->dlpi_name ? info->dlpi_name : "";
+        const char* base = std::strrchr(path, '/');
+        base = base ? base + 1 : path;
+        if (std::strncmp(base, "libamdhip64.so", 14) == 0 &&
+            std::find(v->begin(), v->end(), std::string(path)) == v->end())
+          v->push_back(path);
+        return 0;
+      },
+      &found);
+  return found;
 }
 
 constexpr uint32_t kShadeChunk = 64;    // hits per shading work item
@@ -381,6 +405,18 @@ kn_status check_ctx(kn_ctx* ctx) {
   return KN_OK;
 }
 
+// The cell scan's look-back wait is bounded; running out of it leaves a tile
+// with a zero prefix (overlapping bins), so every path that ran a scan reads
+// the flag back and treats it as a device error.
+kn_status check_scan(kn_ctx* ctx, uint32_t scan_err) {
+  if (!scan_err) return KN_OK;
+  ctx->poisoned = true;
+  return fail(KN_E_DEVICE, "cell scan: a look-back wait ran out; results of this call are invalid");
+}
+
+// word of kn_ctx::pinned that receives Ctrl::scan_err at the end of a call
+constexpr int kPinnedScanErr = 16;
+
 void free_pool(Pool& w) {
   void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.runs, w.hit_count, w.cursor, w.base,
                   w.chunk, w.chunk_out, w.ctrl, w.scenes, w.reqs};
@@ -628,6 +664,13 @@ const char* kn_last_error(void) { return g_err.c_str(); }
 kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out) {
   if (!out) return fail(KN_E_INVALID, "out is NULL");
   *out = nullptr;
+  const std::vector<std::string> rts = hip_runtimes_loaded();
+  if (rts.size() > 1)
+    return fail(KN_E_DEVICE,
+                "%zu HIP runtimes are loaded in this process (%s and %s): device pointers and streams of "
+                "one are invalid in the other; load the runtime that allocates the frame buffers (for "
+                "example import torch) before this library",
+                rts.size(), rts[0].c_str(), rts[1].c_str());
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) return fail(KN_E_DEVICE, "no HIP device");
   if (hip_device < 0 || hip_device >= n) return fail(KN_E_INVALID, "device %d out of range", hip_device);
@@ -662,6 +705,7 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
     if (s->march_bf16) (void)hipFree(s->march_bf16);
     if (s->march_fp8) (void)hipFree(s->march_fp8);
     if (s->shade) (void)hipFree(s->shade);
+    if (s->shade3) (void)hipFree(s->shade3);
     delete s;
   }
   free_pool(ctx->ws);
@@ -1045,19 +1089,22 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
       KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[0], &w.ctrl->n_chunks[(r - 1) & 1], 4, hipMemcpyDeviceToHost,
                                  stream));
       KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[1], &w.ctrl->n_in, 4, hipMemcpyDeviceToHost, stream));
+      KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[2], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
       KN_HIP(ctx, hipEventRecord(ctx->ev_round[0], stream));
       KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[0]));
+      if ((st = check_scan(ctx, ctx->pinned[2])) != KN_OK) return st;
       if (ctx->pinned[0] == 0 && ctx->pinned[1] == 0) break;
     }
     ResolveArgs ra{w.path, (uint32_t)npix, spp, fr->rgb};
     KN_HIP(ctx, launch_resolve(ra, stream));
   }
+  KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
   KN_HIP(ctx, hipEventRecord(ctx->ev_end, stream));
   KN_HIP(ctx, hipEventSynchronize(ctx->ev_end));
+  if ((st = check_scan(ctx, ctx->pinned[kPinnedScanErr])) != KN_OK) return st;
   if (stats) {
     Ctrl hc;
     KN_HIP(ctx, hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
-    if (hc.scan_err) return fail(KN_E_DEVICE, "cell scan: a look-back wait ran out");
     float ms = 0.0f;
     KN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_end));
     stats->gpu_ms = ms;
@@ -1179,8 +1226,9 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
     qa.z_out = z_out;
     KN_HIP(ctx, launch_query_full(qa, s->H, persistent_grid(ctx, 2), stream));
   }
+  KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
   KN_HIP(ctx, hipStreamSynchronize(stream));
-  return KN_OK;
+  return check_scan(ctx, ctx->pinned[kPinnedScanErr]);
 }
 
 }  // extern "C"
@@ -1488,9 +1536,28 @@ class ServeLoop {
     return KN_OK;
   }
 
+  // Counters of group `g`'s readback of the Ctrl head.  The slots are
+  // kCtrlHead bytes apart, which is not the alignment of a whole Ctrl, so the
+  // words are copied out rather than read through a Ctrl pointer.
+  struct Head {
+    uint32_t scan_err;
+    uint32_t miss_done[kMaxSlots];
+    uint32_t hit_done[kMaxSlots];
+  };
+  Head read_head(int64_t g) const {
+    static_assert(offsetof(Ctrl, hit_done) + sizeof(Ctrl::hit_done) <= (size_t)kCtrlHead, "head size");
+    const uint8_t* p = head + (size_t)(g & 3) * kCtrlHead;
+    Head h;
+    std::memcpy(&h.scan_err, p + offsetof(Ctrl, scan_err), sizeof h.scan_err);
+    std::memcpy(h.miss_done, p + offsetof(Ctrl, miss_done), sizeof h.miss_done);
+    std::memcpy(h.hit_done, p + offsetof(Ctrl, hit_done), sizeof h.hit_done);
+    return h;
+  }
+
   // retires the requests that group `g`'s readback shows finished
   void retire(int64_t g) {
-    const Ctrl* h = reinterpret_cast<const Ctrl*>(head + (size_t)(g & 3) * kCtrlHead);
+    const Head hd = read_head(g);
+    const Head* h = &hd;
     const auto now = std::chrono::steady_clock::now();
     bool any = false;
     std::lock_guard<std::mutex> lk(mu);
@@ -1541,6 +1608,9 @@ class ServeLoop {
       KN_HIP(ctx, hipEventRecord(ev[group & 3], stream));
       if (group > 0) {
         KN_HIP(ctx, hipEventSynchronize(ev[(group - 1) & 3]));
+        // the flag is sticky in the serving pool: every request in flight
+        // may have been binned wrongly, so all of them fail
+        if ((st = check_scan(ctx, read_head(group - 1).scan_err)) != KN_OK) return st;
         retire(group - 1);
       }
       ++group;

@@ -73,12 +73,19 @@ _lib = None
 
 
 def lib():
-    """Loads libkn.so (raises if it has not been built)."""
+    """Loads libkn.so (raises if it has not been built).
+
+    torch is imported first: its wheel ships its own HIP runtime under another
+    file name, and loading libkn.so first would map /opt/rocm's runtime as
+    well, leaving two runtimes whose device pointers and streams are invalid
+    in each other (kn_ctx_create refuses to run in such a process).  With
+    torch loaded first, libkn.so binds to torch's runtime by its soname."""
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: run paper_2206_10885_amd/build.py "
                               "(or __graft_entry__.build()) first")
+        import torch  # noqa: F401  (one HIP runtime in the process: torch's)
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.kn_last_error.restype = C.c_char_p

@@ -1,0 +1,271 @@
+// Host runtime of the C ABI (kn_runtime.cpp) driven on the CPU against the
+// host-only HIP stand-in, built with the address and undefined-behaviour
+// sanitizers: scene creation and packing at several grid and MLP sizes in
+// every precision, argument validation, frames, point queries and the serving
+// loop, and the treatment of the scan's look-back overrun flag.  Each check
+// prints one line; any failure, sanitizer report or leak ends the process
+// with a non-zero status.  Usage: driver <case>.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kn.h"
+
+namespace {
+
+int g_fail = 0;
+
+void expect(bool ok, const char* what) {
+  std::printf("%s %s\n", ok ? "ok  " : "FAIL", what);
+  if (!ok) ++g_fail;
+}
+
+// scene parameters: any finite values do for the host runtime
+struct HostScene {
+  uint32_t N, H;
+  std::vector<float> sdf, col;
+};
+
+HostScene make_scene(uint32_t N, uint32_t H, uint32_t seed) {
+  HostScene s{N, H, {}, {}};
+  const size_t cells = (size_t)N * N * N;
+  const size_t psdf = 39 * H + H + H * H + H + 16 * H + 16, pcol = 48 * 32 + 32 + 3 * 32 + 3;
+  s.sdf.resize(cells * psdf);
+  s.col.resize(cells * pcol);
+  uint32_t x = seed * 2654435761u + 1u;
+  auto next = [&x]() {
+    x = x * 1664525u + 1013904223u;
+    return (float)(x >> 8) / 16777216.0f - 0.5f;
+  };
+  for (float& v : s.sdf) v = next();
+  for (float& v : s.col) v = next();
+  return s;
+}
+
+kn_scene_desc desc_of(const HostScene& s, uint32_t precisions) {
+  kn_scene_desc d{};
+  d.abi_version = KN_ABI_VERSION;
+  d.grid_n = s.N;
+  for (int k = 0; k < 3; ++k) {
+    d.bbox_min[k] = -1.0f;
+    d.bbox_max[k] = 1.0f;
+  }
+  d.pos_freqs = 6;
+  d.dir_freqs = 4;
+  d.sdf_hidden = s.H;
+  d.sdf_layers = 2;
+  d.feat_dim = 15;
+  d.col_hidden = 32;
+  d.col_layers = 1;
+  d.col_in_has_x = 1;
+  d.softplus_beta = 100.0f;
+  d.sdf_params = s.sdf.data();
+  d.col_params = s.col.data();
+  d.precisions = precisions;
+  return d;
+}
+
+kn_camera camera(uint32_t W, uint32_t H, kn_precision p) {
+  kn_camera c{};
+  c.eye[2] = 2.5f;
+  c.up[1] = 1.0f;
+  c.width = W;
+  c.height = H;
+  c.spp = 1;
+  c.max_steps = 64;
+  c.eps = 1e-4f;
+  c.precision = p;
+  return c;
+}
+
+struct DevFrame {
+  kn_frame f{};
+  explicit DevFrame(size_t npix) {
+    (void)hipMalloc((void**)&f.rgb, npix * 12);
+    (void)hipMalloc((void**)&f.depth, npix * 4);
+    (void)hipMalloc((void**)&f.normal, npix * 12);
+    (void)hipMalloc((void**)&f.hit, npix);
+    (void)hipMalloc((void**)&f.steps, npix * 2);
+  }
+  ~DevFrame() {
+    (void)hipFree(f.rgb);
+    (void)hipFree(f.depth);
+    (void)hipFree(f.normal);
+    (void)hipFree(f.hit);
+    (void)hipFree(f.steps);
+  }
+};
+
+const uint32_t kAll = (1u << KN_BF16) | (1u << KN_FP8_E4M3);
+
+void case_scenes() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  const uint32_t sizes[][2] = {{1, 32}, {1, 64}, {3, 32}, {4, 64}, {8, 64}, {16, 32}, {12, 64}};
+  for (auto& nh : sizes) {
+    HostScene s = make_scene(nh[0], nh[1], nh[0] * 100 + nh[1]);
+    for (uint32_t prec : {0u, 1u << KN_BF16, 1u << KN_FP8_E4M3, kAll}) {
+      kn_scene_desc d = desc_of(s, prec);
+      kn_scene_id id = 0;
+      char what[96];
+      std::snprintf(what, sizeof what, "scene N=%u H=%u precisions=%u created", nh[0], nh[1], prec);
+      expect(kn_scene_create(ctx, &d, &id) == KN_OK, what);
+      std::snprintf(what, sizeof what, "scene N=%u H=%u precisions=%u destroyed", nh[0], nh[1], prec);
+      expect(kn_scene_destroy(ctx, id) == KN_OK, what);
+    }
+  }
+  // a scene left for kn_ctx_destroy to free (every resident copy)
+  HostScene s = make_scene(4, 64, 7);
+  kn_scene_desc d = desc_of(s, kAll);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene kept until the context is destroyed");
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy frees the remaining scene");
+}
+
+void case_validation() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(2, 32, 3);
+  kn_scene_id id = 0;
+  kn_scene_desc d = desc_of(s, kAll);
+  d.grid_n = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_E_UNSUPPORTED, "grid_n 0 unsupported");
+  d = desc_of(s, kAll);
+  d.sdf_hidden = 48;
+  expect(kn_scene_create(ctx, &d, &id) == KN_E_UNSUPPORTED, "sdf_hidden 48 unsupported");
+  d = desc_of(s, kAll);
+  d.abi_version = 99;
+  expect(kn_scene_create(ctx, &d, &id) == KN_E_INVALID, "wrong abi_version");
+  d = desc_of(s, 1u << 5);
+  expect(kn_scene_create(ctx, &d, &id) == KN_E_INVALID, "unknown precision bit");
+  s.sdf[s.sdf.size() - 1] = NAN;
+  d = desc_of(s, kAll);
+  expect(kn_scene_create(ctx, &d, &id) == KN_E_INVALID, "NaN in the last SDF parameter");
+  expect(std::strstr(kn_last_error(), "non-finite") != nullptr, "message names the parameter");
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
+void case_render_query(bool scan_err) {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(4, 32, 11);
+  kn_scene_desc d = desc_of(s, kAll);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  const kn_status want = scan_err ? KN_E_DEVICE : KN_OK;
+  for (kn_precision p : {KN_FP32, KN_BF16, KN_FP8_E4M3}) {
+    DevFrame fr(97 * 61);
+    kn_camera c = camera(97, 61, p);
+    kn_stats st{};
+    const kn_status r = kn_render(ctx, id, &c, &fr.f, (p == KN_BF16) ? &st : nullptr);
+    expect(r == want, scan_err ? "render reports the scan overrun" : "render");
+    if (scan_err) {
+      expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_E_DEVICE, "context poisoned afterwards");
+      break;
+    }
+  }
+  if (!scan_err) {
+    DevFrame fr(64 * 48);
+    kn_camera c = camera(64, 48, KN_BF16);
+    c.bounces = 3;
+    c.spp = 4;
+    expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_OK, "path-traced render");
+    float* pts = nullptr;
+    float *dd = nullptr, *gg = nullptr, *zz = nullptr;
+    const uint64_t n = 5000;
+    (void)hipMalloc((void**)&pts, n * 12);
+    (void)hipMalloc((void**)&dd, n * 4);
+    (void)hipMalloc((void**)&gg, n * 12);
+    (void)hipMalloc((void**)&zz, n * 60);
+    expect(kn_query(ctx, id, KN_BF16, pts, n, dd, gg, zz, nullptr) == KN_OK, "query");
+    (void)hipFree(pts);
+    (void)hipFree(dd);
+    (void)hipFree(gg);
+    (void)hipFree(zz);
+  }
+  kn_scene_destroy(ctx, id);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
+void case_query_scan_err() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(4, 32, 12);
+  kn_scene_desc d = desc_of(s, 0);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  float *pts = nullptr, *dd = nullptr;
+  (void)hipMalloc((void**)&pts, 300 * 12);
+  (void)hipMalloc((void**)&dd, 300 * 4);
+  expect(kn_query(ctx, id, KN_FP32, pts, 300, dd, nullptr, nullptr, nullptr) == KN_E_DEVICE,
+         "query reports the scan overrun");
+  (void)hipFree(pts);
+  (void)hipFree(dd);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
+void case_serve(bool scan_err) {
+  kn_ctx* ctx = nullptr;
+  // a small budget keeps the fake's host-memory pool small
+  expect(kn_ctx_create(0, (uint64_t)1 << 30, &ctx) == KN_OK, "ctx create");
+  std::vector<kn_scene_id> ids;
+  for (uint32_t k = 0; k < 3; ++k) {
+    HostScene s = make_scene(2 + 2 * k, k % 2 ? 64 : 32, 20 + k);
+    kn_scene_desc d = desc_of(s, 1u << KN_BF16);
+    kn_scene_id id = 0;
+    expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+    ids.push_back(id);
+  }
+  expect(kn_serve_start(ctx, 8, KN_BF16) == KN_OK, "serve start");
+  std::vector<DevFrame*> frames;
+  std::vector<kn_request_id> reqs;
+  int refused = 0;
+  for (int i = 0; i < 12; ++i) {
+    const uint32_t W = 16 + 8 * (i % 5), H = 9 + 4 * (i % 3);
+    frames.push_back(new DevFrame((size_t)W * H));
+    kn_camera c = camera(W, H, KN_BF16);
+    kn_request_id r = 0;
+    const kn_status s = kn_serve_submit(ctx, ids[i % 3], &c, &frames.back()->f, &r);
+    if (s == KN_OK) reqs.push_back(r);
+    else if (scan_err && (s == KN_E_DEVICE || s == KN_E_SHUTDOWN)) ++refused;   // the loop has failed
+    else expect(false, "submit");
+  }
+  const kn_status want = scan_err ? KN_E_DEVICE : KN_OK;
+  int ok = 0;
+  for (kn_request_id r : reqs) ok += kn_serve_poll(ctx, r, -1, nullptr) == want;
+  expect(!reqs.empty() && ok == (int)reqs.size(),
+         scan_err ? "every accepted request fails on the scan overrun" : "every request done");
+  if (scan_err) {
+    kn_camera c = camera(8, 8, KN_BF16);
+    kn_request_id r = 0;
+    expect(kn_serve_submit(ctx, ids[0], &c, &frames[0]->f, &r) == KN_E_DEVICE,
+           "later submits find the context poisoned");
+  }
+  expect(kn_serve_stop(ctx) == KN_OK, "serve stop");
+  for (DevFrame* f : frames) delete f;
+  for (kn_scene_id id : ids) kn_scene_destroy(ctx, id);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+  const std::string c = argc > 1 ? argv[1] : "";
+  if (c == "scenes") case_scenes();
+  else if (c == "validation") case_validation();
+  else if (c == "render") case_render_query(false);
+  else if (c == "render_scan_err") case_render_query(true);
+  else if (c == "query_scan_err") case_query_scan_err();
+  else if (c == "serve") case_serve(false);
+  else if (c == "serve_scan_err") case_serve(true);
+  else {
+    std::fprintf(stderr, "unknown case '%s'\n", c.c_str());
+    return 2;
+  }
+  return g_fail ? 1 : 0;
+}

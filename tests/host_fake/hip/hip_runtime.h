@@ -1,0 +1,60 @@
+// Host-only stand-in for <hip/hip_runtime.h>, used to build the library's
+// host runtime (kn_runtime.cpp) with g++ and the address / undefined-
+// behaviour sanitizers on a machine without a GPU.  "Device" memory is host
+// memory, every stream is synchronous, and the kernel launchers are the stubs
+// of fake_hip.cpp.  Test infrastructure only: nothing of the product is built
+// against it.
+#pragma once
+#include <cstddef>
+#include <cstdint>
+
+#define __host__
+#define __device__
+#define __global__
+
+typedef enum hipError_t { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2,
+                          hipErrorNoDevice = 100 } hipError_t;
+typedef enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
+                             hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
+struct FakeStream;
+struct FakeEvent;
+typedef FakeStream* hipStream_t;
+typedef FakeEvent* hipEvent_t;
+struct hipDeviceProp_t {
+  char name[256];
+  int multiProcessorCount;
+};
+struct uint2 { uint32_t x, y; };
+struct uint4 { uint32_t x, y, z, w; };
+inline uint2 make_uint2(uint32_t x, uint32_t y) { return uint2{x, y}; }
+inline uint4 make_uint4(uint32_t x, uint32_t y, uint32_t z, uint32_t w) { return uint4{x, y, z, w}; }
+
+constexpr unsigned hipStreamNonBlocking = 1u;
+constexpr unsigned hipEventDisableTiming = 2u;
+constexpr unsigned hipHostMallocDefault = 0u;
+
+hipError_t hipGetDeviceCount(int* n);
+hipError_t hipSetDevice(int dev);
+hipError_t hipGetDeviceProperties(hipDeviceProp_t* p, int dev);
+hipError_t hipMemGetInfo(size_t* free_b, size_t* total_b);
+hipError_t hipDeviceSynchronize();
+const char* hipGetErrorString(hipError_t e);
+hipError_t hipMalloc(void** p, size_t bytes);
+template <class T>
+hipError_t hipMalloc(T** p, size_t bytes) { return hipMalloc(reinterpret_cast<void**>(p), bytes); }
+hipError_t hipFree(void* p);
+hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
+hipError_t hipHostFree(void* p);
+hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
+hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st);
+hipError_t hipMemset(void* dst, int v, size_t bytes);
+hipError_t hipMemsetAsync(void* dst, int v, size_t bytes, hipStream_t st);
+hipError_t hipStreamCreateWithFlags(hipStream_t* st, unsigned flags);
+hipError_t hipStreamDestroy(hipStream_t st);
+hipError_t hipStreamSynchronize(hipStream_t st);
+hipError_t hipEventCreate(hipEvent_t* e);
+hipError_t hipEventCreateWithFlags(hipEvent_t* e, unsigned flags);
+hipError_t hipEventDestroy(hipEvent_t e);
+hipError_t hipEventRecord(hipEvent_t e, hipStream_t st);
+hipError_t hipEventSynchronize(hipEvent_t e);
+hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);

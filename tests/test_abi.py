@@ -5,6 +5,7 @@ from __future__ import annotations
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -47,3 +48,46 @@ def test_null_arguments_are_rejected_without_a_device():
     assert b"out" in L.kn_last_error()
     assert L.kn_ctx_destroy(None) == -1
     assert L.kn_render(None, 0, None, None, None) == -1
+
+
+_MAPS_PROBE = r"""
+import ctypes, sys
+sys.path.insert(0, {root!r})
+order = {order!r}
+if order == "binding":
+    from paper_2206_10885_amd import kn
+    L = kn.lib()
+else:
+    L = ctypes.CDLL({lib!r})
+    L.kn_last_error.restype = ctypes.c_char_p
+    import torch  # noqa: F401
+paths = set()
+for line in open("/proc/self/maps"):
+    parts = line.split()
+    if len(parts) >= 6 and parts[5].rsplit("/", 1)[-1].startswith("libamdhip64.so"):
+        paths.add(parts[5])
+h = ctypes.c_void_p()
+st = L.kn_ctx_create(0, 0, ctypes.byref(h))
+print(len(paths), st, L.kn_last_error().decode())
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(kn.LIB_PATH), reason="libkn.so not built")
+@pytest.mark.parametrize("order", ["binding", "library first"])
+def test_one_hip_runtime_per_process(order):
+    """Loading libkn.so before torch maps two HIP runtimes (torch's wheel ships
+    its own under another file name): device pointers and streams of one are
+    invalid in the other, which crashed such a process inside the library.
+    The binding imports torch first, so the library binds to torch's runtime;
+    a process that still has two is refused by kn_ctx_create before any HIP
+    call.  CPU only: no device is touched."""
+    code = _MAPS_PROBE.format(root=ROOT, order=order, lib=kn.LIB_PATH)
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600)
+    assert out.returncode == 0, out.stderr
+    n, st, msg = out.stdout.strip().split(" ", 2)
+    if order == "binding":
+        assert n == "1", out.stdout
+        assert "HIP runtimes are loaded" not in msg
+    else:
+        assert n == "2", out.stdout
+        assert int(st) == -5 and "2 HIP runtimes are loaded" in msg, out.stdout
