@@ -101,9 +101,19 @@ class Report:
     replay_rgb_max: float
     all_depth_p99: float        # all pixels where both hit (reported only)
     all_normal_p99: float
+    # every pixel where both hit (depth, normal in degrees) or whose masks
+    # agree (rgb): p50 / p99 / max, reported
+    err_all: dict = dataclasses.field(default_factory=dict)
+    # per GPU hit: the march's stop point (world) and its cell, for checks of
+    # low-precision marches in their own arithmetic
+    stop_pts: np.ndarray = None
+    stop_cells: np.ndarray = None
+    fstop: np.ndarray = None    # f_FP64(stop) - eps per GPU hit
 
     def as_dict(self):
-        return {k: (round(v, 9) if isinstance(v, float) else v) for k, v in dataclasses.asdict(self).items()}
+        skip = ("stop_pts", "stop_cells", "fstop")
+        return {f.name: (round(getattr(self, f.name), 9) if isinstance(getattr(self, f.name), float)
+                         else getattr(self, f.name)) for f in dataclasses.fields(self) if f.name not in skip}
 
     def ok(self, frac: float = 1e-3) -> bool:
         """The parity bar: hit masks agree on >= 99.9% of pixels (or as often as
@@ -175,7 +185,10 @@ def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None) -> Report:
     pn_max = pc_max = fstop = 0.0
     rd = rnm = rc = 0.0
     hits = np.nonzero(gpu["hit"] == 1)[0]
-    for q in hits:
+    stop_pts = np.zeros((len(hits), 3))
+    stop_cells = np.zeros(len(hits), np.int64)
+    fstops = np.zeros(len(hits))
+    for hi_, q in enumerate(hits):
         p = int(pix[q])
         o, d = O.camera_ray(view, W, H, p // W, p % W)
         cell = int(gpu["cell"][q])
@@ -201,7 +214,9 @@ def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None) -> Report:
             if e_pn > TOL_NORMAL_DEG or e_pc > TOL_RGB:
                 pb += 1
         xs = o + gpu["t_march"][q] * d
-        fstop = max(fstop, os_.sdf_eval(cell, (xs - c) / half)[0] - eps)
+        fstops[hi_] = os_.sdf_eval(cell, (xs - c) / half)[0] - eps
+        fstop = max(fstop, fstops[hi_])
+        stop_pts[hi_], stop_cells[hi_] = xs, cell
         # (2) FP64 replay of refinement and shading from the GPU's march state
         tr = _trace_struct(idx, gpu["t_march"][q], gpu["t_entry"][q])
         sh = os_.shade(o, d, tr)
@@ -237,4 +252,26 @@ def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None) -> Report:
         replay_n=rn_, replay_bad=rb, replay_depth_max=float(rd), replay_normal_max=rnm,
         replay_rgb_max=rc,
         all_depth_p99=float(np.percentile(dd[both], 99)) if both.any() else 0.0,
-        all_normal_p99=float(np.percentile(an[both], 99)) if both.any() else 0.0)
+        all_normal_p99=float(np.percentile(an[both], 99)) if both.any() else 0.0,
+        err_all=dict(depth=stats(dd[both]), normal_deg=stats(an[both]), rgb=stats(dc[ref["hit"] == gpu["hit"]])),
+        stop_pts=stop_pts, stop_cells=stop_cells, fstop=fstops)
+
+
+def stats(x) -> dict:
+    """p50 / p99 / max of a sample (empty: zeros)."""
+    x = np.asarray(x, np.float64).ravel()
+    if x.size == 0:
+        return dict(n=0, p50=0.0, p99=0.0, max=0.0)
+    return dict(n=int(x.size), p50=float(np.median(x)), p99=float(np.percentile(x, 99)), max=float(x.max()))
+
+
+def record(name: str, data: dict) -> None:
+    """Appends one JSON line {name: data} to the file named by KN_REPORT (if
+    set): the GPU tests' accuracy figures, kept beside the run's logs."""
+    import json
+    import os
+    path = os.environ.get("KN_REPORT")
+    if not path:
+        return
+    with open(path, "a") as fh:
+        fh.write(json.dumps({"case": name, **data}) + "\n")

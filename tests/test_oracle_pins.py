@@ -520,3 +520,64 @@ def test_path_trace_plane_one_bounce_closed_form():
         np.testing.assert_allclose(r["rgb"][p], a * O.env_lookup(env, d), rtol=1e-9)
         checked += 1
     assert checked > 30
+
+
+def _budget_count(g, c0, o, d, t0, eps):
+    """Closed form of the evaluations sphere tracing spends on an affine SDF
+    f(x) = g.x + c0 along a ray that starts at t0 in front of the plane and
+    approaches it (a = -g.d in (0, 1]): each step moves by f, so
+    f_k = f_0 (1 - a)^k, and the march evaluates f_0 .. f_m with m the first
+    k where f_k < eps: m + 1 evaluations.  Returns (m + 1, margin), margin the
+    smallest |log(f_k / eps)| over k = m - 1, m (how far the decisive values
+    are from the threshold)."""
+    a = -float(g @ d)
+    f0 = float(g @ (o + t0 * d) + c0)
+    assert 0.0 < a <= 1.0 and f0 > eps
+    k, f = 0, f0
+    while f >= eps:
+        f *= 1.0 - a
+        k += 1
+    margin = min(abs(math.log(f / eps)), abs(math.log(f / (1.0 - a) / eps)))
+    return k + 1, margin
+
+
+def test_step_budget_exact_evaluation_count():
+    """The step budget S counts SDF evaluations exactly: on a one-cell plane
+    scene of slope 1 the number of evaluations to a hit has a closed form
+    (geometric contraction of f by 1 - cos(angle) per step); with S equal to
+    it the ray hits, with one less it is a budget miss that has used all S
+    evaluations.  Rays at several angles and starting distances."""
+    rng = np.random.default_rng(77)
+    checked = 0
+    for case in range(12):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        sc = synth.plane_scene(1, 32, n, rng.uniform(-0.3, 0.3), seed=900 + case)
+        os_ = O.OracleScene.from_scene(sc)
+        g, c0 = synth.plane_affine_map(sc, 0)
+        gn = g / np.linalg.norm(g)
+        for _ in range(6):
+            cos_t = rng.uniform(0.15, 0.95)
+            tang = np.cross(gn, rng.standard_normal(3))
+            tang /= np.linalg.norm(tang)
+            d = -cos_t * gn + math.sqrt(1.0 - cos_t ** 2) * tang
+            # start on the plane's positive side, inside the box
+            o = -(c0 / (g @ g)) * g + rng.uniform(0.05, 0.6) * gn + rng.uniform(-0.2, 0.2) * tang
+            if np.abs(o).max() >= 0.98:
+                continue
+            ok, tn, tf = os_.slab(o, d)
+            t0 = max(tn, 0.0)
+            t_star = -(g @ o + c0) / (g @ d)
+            if not ok or t_star >= tf - 1e-3:
+                continue
+            want, margin = _budget_count(g, c0, o, d, t0, 1e-4)
+            if margin < 1e-6:
+                continue
+            r = os_.trace(o, d, want, 1e-4)
+            assert r["status"] == O.HIT and r["steps"] == want, (case, want, r)
+            r = os_.trace(o, d, want - 1, 1e-4)
+            assert r["status"] == O.BUDGET_MISS and r["steps"] == want - 1, (case, want, r)
+            r = os_.trace(o, d, want + 50, 1e-4)
+            assert r["status"] == O.HIT and r["steps"] == want
+            checked += 1
+    assert checked >= 40

@@ -90,7 +90,7 @@ def test_pow2_scale(qlib):
         assert b / s <= 448.0 < b / (s / 2)
 
 
-@pytest.mark.parametrize("fn", ["sdf_bf16", "sdf_fp8"])
+@pytest.mark.parametrize("fn", ["sdf_bf16", "sdf_bf16_kernel_form", "sdf_fp8"])
 def test_emulation_without_rounding_equals_oracle(fn):
     sc = synth.sphere_scene(4, 32, 0.5, 0.02, seed=9)
     rng = np.random.default_rng(3)
@@ -125,3 +125,70 @@ def test_fp8_activation_bound_holds():
         a1 = np.maximum(e @ W1.T + b1, 0) + np.log1p(np.exp(-sc.beta * np.abs(e @ W1.T + b1))) / sc.beta
         assert a1.max() / sa <= 448.0
         assert np.abs(W1).max() / s1 <= 448.0 and np.abs(W2).max() / s2 <= 448.0
+
+
+def test_fp64_forward_equals_c_oracle():
+    """quant.sdf_fp64 (eq. 3 in numpy float64, with its activations) equals the
+    C oracle's SDF value, and its activations are softplus of its
+    pre-activations."""
+    sc = synth.sphere_scene(4, 64, 0.5, 0.02, seed=21)
+    rng = np.random.default_rng(8)
+    pts = rng.uniform(-1, 1, (500, 3))
+    cells, xl = quant.point_cells(sc.N, pts)
+    f = quant.sdf_fp64(sc, cells, xl)
+    os_ = O.OracleScene.from_scene(sc)
+    ref = np.array([os_.sdf_eval(int(c), x)[0] for c, x in zip(cells, xl)])
+    assert np.abs(ref - f["d"]).max() < 1e-12
+    sp = np.vectorize(O.softplus)
+    assert np.abs(f["a2"][:50] - sp(f["u2"][:50])).max() < 1e-14
+
+
+@pytest.mark.parametrize("mode,fns", [("bf16", ("sdf_bf16", "sdf_bf16_kernel_form")), ("fp8", ("sdf_fp8",))])
+def test_rounding_bound_covers_the_emulations(mode, fns):
+    """Every emulation of a precision stays inside the worst-case per-point
+    rounding bound at every point (H = 32 and 64, random points and points on
+    cell faces).  The bound is loose by construction (sums of |terms|, no
+    cancellation: typically 0.1-1% of it is used), so it catches gross errors
+    (a wrong cell, layer or scale, a NaN); the sharp checks of the kernels are
+    the flip budget and the comparison with the plain reading."""
+    for H in (32, 64):
+        sc = synth.sphere_scene(8, H, 0.6, 0.02, seed=40 + H)
+        rng = np.random.default_rng(H)
+        pts = rng.uniform(-1, 1, (3000, 3))
+        pts[:64] = -1 + 2.0 * rng.integers(0, sc.N + 1, (64, 3)) / sc.N
+        pts = pts.astype(np.float32)
+        cells, xl = quant.point_cells(sc.N, pts)
+        f = quant.sdf_fp64(sc, cells, xl)
+        bound = quant.rounding_bound(sc, f, mode)
+        for fn in fns:
+            err = np.abs(getattr(quant, fn)(sc, pts).astype(np.float64) - f["d"])
+            r = err / bound
+            assert r.max() <= 1.0, (fn, H, r.max())
+            assert np.median(r) > 1e-4, (fn, H, np.median(r))
+
+
+def test_flip_budget_covers_a_reordered_evaluation():
+    """kernel_form_with_flips (numpy float32) against sdf_bf16_kernel_form
+    (torch float32, other summation order and exponentials): equal within
+    float32 slack on almost every point, and within the per-point flip budget
+    on every point.  A planted error, the SDF row without the low half of its
+    hi + lo pair (the row itself rounded to bfloat16), breaks the budget at
+    many points."""
+    sc = synth.sphere_scene(16, 64, 0.6, 0.02, seed=7)
+    rng = np.random.default_rng(3)
+    pts = rng.uniform(-1, 1, (4000, 3)).astype(np.float32)
+    val, budget, slack, nflip = quant.kernel_form_with_flips(sc, pts)
+    ref = quant.sdf_bf16_kernel_form(sc, pts).astype(np.float64)
+    diff = np.abs(val - ref)
+    assert (diff <= budget + slack).all()
+    assert np.mean(diff > slack) < 0.01
+    # planted: W3[0] / (2k) replaced by its bfloat16 rounding, so the kernel
+    # form's low half is (almost) zero
+    k = sc.beta / math.log(2.0)
+    bad = synth.Scene(N=sc.N, H=sc.H, sdf=sc.sdf.copy(), col=sc.col, beta=sc.beta)
+    row0 = 39 * sc.H + sc.H + sc.H * sc.H + sc.H
+    w = (bad.sdf[:, row0:row0 + sc.H].astype(np.float64) * (0.5 / k)).astype(np.float32)
+    hi = torch.from_numpy(w).to(torch.bfloat16).to(torch.float32).numpy().astype(np.float64)
+    bad.sdf[:, row0:row0 + sc.H] = (hi * 2.0 * k).astype(np.float32)
+    wrong = quant.sdf_bf16_kernel_form(bad, pts).astype(np.float64)
+    assert np.mean(np.abs(wrong - val) > budget + slack) > 0.2
