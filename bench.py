@@ -6,10 +6,16 @@ initialisation toward a sphere of radius 0.6 with N(0, 0.02^2) noise,
 1920x1080 primary rays per frame, 8 seeded orbit views cycled, at most 128
 sphere-tracing steps, eps 1e-4.  One step = one frame (2,073,600 rays)
 through every stage: ray generation and box clip, per-round cell binning,
-the march (bfloat16 MLP on MFMA), hit binning, refinement and shading (the
-SDF MLP's products on bfloat16 MFMA with hi/lo split operands, about 2^-16
-relative error each).  The same frames are then timed with the float32 march
-and float32 shading for the ratio.
+the march (bfloat16 MLP on MFMA, float32 positions and cell stepping), hit
+binning, then refinement and shading with float32 weights and arithmetic.
+
+The same frames are then timed for the variants: split-bfloat16 refinement
+and shading (faster, ~2^-16 relative per product), the fp8 e4m3 march and
+the float32 march.  A separate pass of 56 frames (8 views x 7, after 16
+warm-up frames) gives the frame latency p50 / p99.  Then C5 (path tracing,
+32^3, 4 spp, 3 bounces, FP8 vs BF16) and C4 (serving: 8 resident scenes,
+Poisson arrivals at 200 requests/s, 2000 measured requests) unless skipped,
+and the FP64 oracle on the host's cores.
 
 Prints one JSON line: metric, value, unit, timing, dtype, config, the
 roofline of the dominant kernel and the oracle's CPU rate.
@@ -65,11 +71,15 @@ def kernel_sources_sha256() -> str:
 
 
 def march_work(H: int) -> dict:
-    """Algorithmic work of one SDF evaluation in the march (per point):
-    dense MLP FLOPs and transcendental operations (exp and log per softplus
-    unit, sin or cos per encoding component)."""
+    """Algorithmic work of one SDF evaluation in the march (per point): the
+    dense MLP's FLOPs (39 -> H -> H -> the SDF row) and its transcendental
+    operations: an exponential and a logarithm per softplus unit (2H units)
+    and the encoding's sines and cosines at the lowest frequency of each axis
+    (3 sin + 3 cos; the higher frequencies follow by the double-angle
+    identities with multiply-adds), 4H + 6 x 2 = 268 for H = 64, whatever
+    the kernel itself issues."""
     flop = 2 * (39 * H + H * H + H)
-    trans = 2 * (2 * H) + 36
+    trans = 2 * (2 * H) + 12
     return dict(flop=flop, trans=trans)
 
 
@@ -79,14 +89,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=56, help="timed frames")
     ap.add_argument("--warmup", type=int, default=16, help="untimed frames")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
-    ap.add_argument("--no-fp32", action="store_true", help="skip the float32 comparison run")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the split-bf16-shading, fp8 and float32 runs on the same frames")
+    ap.add_argument("--latency-frames", type=int, default=56, help="frames of the latency pass")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU-oracle time")
-    ap.add_argument("--serve", action="store_true",
-                    help="also run the serving workload (8 resident scenes, Poisson arrivals)")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0, help="target CPU-oracle time (all threads)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving workload (8 resident scenes, Poisson arrivals)")
     ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--pathtrace", action="store_true",
-                    help="also run the path-tracing workload (32^3, 4 spp, 3 bounces, FP8 vs BF16)")
+    ap.add_argument("--no-pathtrace", action="store_true",
+                    help="skip the path-tracing workload (32^3, 4 spp, 3 bounces, FP8 vs BF16)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one plain float32 device copy of this many MiB "
                          "(a kernel of known HBM traffic, used to scale hardware byte counters)")
@@ -137,35 +149,57 @@ def timed_frames(ctx, sid, cams, out, steps, warmup, torch):
                 shade_ms=shade_ms)
 
 
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(scene, views, W, H, S, eps, target_s):
-    """The FP64 oracle on a seeded pixel sample of the same frames."""
+    """The FP64 oracle, as committed, on seeded pixel samples of the same
+    frames: once with every thread the job may use (OMP_NUM_THREADS, else all
+    cores), sized to about target_s seconds, then with one thread on a sample
+    a tenth that size."""
     from oracle import oracle as O
     from paper_2206_10885_amd import synth
-    cores = min(16, os.cpu_count() or 1)
+    nproc = os.cpu_count() or 1
+    threads = min(nproc, int(os.environ.get("OMP_NUM_THREADS") or nproc))
     os_ = O.OracleScene.from_scene(scene)
-    n = 2000
-    pix = synth.sample_pixels(W, H, n, seed=77)
+    pix = synth.sample_pixels(W, H, 2000, seed=77)
     t = time.perf_counter()
-    os_.render(views[0], W, H, S, eps, pixels=pix, nthreads=cores)
+    os_.render(views[0], W, H, S, eps, pixels=pix, nthreads=threads)
     dt = time.perf_counter() - t
-    n = int(min(W * H, max(2000, n * target_s / max(dt, 1e-3) / len(views))))
-    total_px, total_t = 0, 0.0
-    for vi, v in enumerate(views):
-        pix = synth.sample_pixels(W, H, n, seed=77 + vi)
-        t = time.perf_counter()
-        os_.render(v, W, H, S, eps, pixels=pix, nthreads=cores)
-        total_t += time.perf_counter() - t
-        total_px += len(pix)
-    return dict(value=total_px / total_t, unit="rays/s", cores=cores, kind="oracle",
-                sample=f"{total_px} seeded pixels ({n} per view) of the 8 C3 views, FP64, "
-                       f"{total_t:.1f} s")
+    n = int(min(W * H, max(2000, 2000 * target_s / max(dt, 1e-3) / len(views))))
+
+    def run(nthreads, per_view):
+        px, tt = 0, 0.0
+        for vi, v in enumerate(views):
+            p = synth.sample_pixels(W, H, per_view, seed=77 + vi)
+            t0 = time.perf_counter()
+            os_.render(v, W, H, S, eps, pixels=p, nthreads=nthreads)
+            tt += time.perf_counter() - t0
+            px += len(p)
+        return px, tt
+
+    px, tt = run(threads, n)
+    n1 = max(200, n // 10 // max(1, threads // 4))
+    px1, tt1 = run(1, n1)
+    return dict(value=px / tt, unit="rays/s", cores=threads, kind="oracle",
+                sample=f"{px} seeded pixels ({n} per view) of the 8 C3 views, FP64, {tt:.1f} s on {threads} "
+                       f"threads; {px1} pixels ({n1} per view) in {tt1:.1f} s on 1 thread",
+                value_1_thread=px1 / tt1, nproc=nproc, cpu_model=cpu_model())
 
 
 def serve_bench(n_req: int, torch) -> dict:
     """8 resident scenes (grids 16^3-32^3, H 32 / 64), requests at Poisson
     arrivals of 200/s with seeded orbit views at resolutions drawn from
-    {256^2, 512^2, 800^2, 1920x1080}, 256 steps, bfloat16 march; 200 warm-up
-    requests, then n_req measured; latency = submission to completion."""
+    {256^2, 512^2, 800^2, 1920x1080}, 256 steps, bfloat16 march, float32
+    refinement and shading; 200 warm-up requests, then n_req measured;
+    latency = submission to completion on the host clock."""
     import threading
     from paper_2206_10885_amd import kn, synth
     Ns = [16, 16, 20, 24, 24, 28, 32, 32]
@@ -223,14 +257,15 @@ def serve_bench(n_req: int, torch) -> dict:
     ctx.close()
     return dict(requests=n_req, warmup=warm, arrival_rate=200.0, latency_ms_p50=pct(lat, 50),
                 latency_ms_p99=pct(lat, 99), latency_ms_max=max(lat), rays_per_s=rays / span,
-                offered_rays_per_s=rays / (arrivals[-1] - t_meas0), precision="bf16", max_steps=256,
+                offered_rays_per_s=rays / (arrivals[-1] - t_meas0), precision="bf16 march, fp32 shading",
+                max_steps=256, loop="host-driven rounds (groups of 4 rounds and a shading pass)",
                 scenes="8 resident: N=16,16,20,24,24,28,32,32; H=32 (even k) / 64 (odd k); r=0.5+0.02k")
 
 
 def pathtrace_bench(torch, frames: int = 3) -> dict:
     """32^3 grid, H=64, 1920x1080, 4 spp, 3 Lambertian bounces, 512x256
-    environment; FP8 e4m3 march against bfloat16 (refinement and shading on
-    split-bfloat16 MFMA)."""
+    environment; FP8 e4m3 march against bfloat16 (refinement and shading with
+    float32 weights in both)."""
     from paper_2206_10885_amd import kn, synth
     c = synth.CONFIGS["c5"]
     sc = synth.config_scene("c5")
@@ -268,6 +303,29 @@ def pathtrace_bench(torch, frames: int = 3) -> dict:
     return res
 
 
+def variant(ctx, sid, views, W, H, S, eps, prec, split, out, steps, warmup, torch, kn):
+    cams = [kn.make_camera(v, W, H, S, eps, prec, split_shading=split) for v in views]
+    r = timed_frames(ctx, sid, cams, out, steps, warmup, torch)
+    return r, steps * W * H / r["total_s"]
+
+
+def latency_pass(ctx, sid, cams, out, frames, torch) -> dict:
+    """Frame latency over `frames` frames (the views cycled) after two
+    warm-up passes over the views: GPU time first to last kernel (HIP
+    events) and host wall time of each kn_render call."""
+    for i in range(2 * len(cams)):
+        ctx.render_into(sid, cams[i % len(cams)], out)
+    torch.cuda.synchronize()
+    g, w = [], []
+    for i in range(frames):
+        t = time.perf_counter()
+        st = ctx.render_into(sid, cams[i % len(cams)], out)
+        w.append((time.perf_counter() - t) * 1e3)
+        g.append(st["gpu_ms"])
+    return dict(frames=frames, frame_ms_p50=pct(g, 50), frame_ms_p99=pct(g, 99),
+                frame_wall_ms_p50=pct(w, 50), frame_wall_ms_p99=pct(w, 99))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -283,13 +341,15 @@ def main():
     scene = synth.config_scene("c3")
     views = synth.config_views("c3")
     ctx = kn.Context(0)
-    sid = ctx.scene_create(scene, precisions=("bf16",))
+    sid = ctx.scene_create(scene, precisions=("bf16", "fp8"))
     out = ctx.alloc_frame(W, H)
     rays = W * H
 
     cams = [kn.make_camera(v, W, H, S, eps, args.precision) for v in views]
     r = timed_frames(ctx, sid, cams, out, args.steps, args.warmup, torch)
     value = args.steps * rays / r["total_s"]
+    print(f"bench: headline {args.precision} done", file=sys.stderr, flush=True)
+    lat = latency_pass(ctx, sid, cams, out, max(args.latency_frames, args.steps), torch)
     work = march_work(scene.H)
     avg_launch_s = r["march_ms"] / 1e3 / max(1, r["march_launches"])
     evals_per_launch = r["evals_timed"] / max(1, r["march_launches"])
@@ -304,7 +364,7 @@ def main():
                         traffic_frac_of_hbm=(None if traffic is None else
                                              traffic / avg_launch_s / PEAK_HBM),
                         kernel="k_march<64,bf16>", avg_launch_ms=avg_launch_s * 1e3,
-                        evals_per_launch=evals_per_launch,
+                        evals_per_launch=evals_per_launch, trans_per_eval=work["trans"],
                         timed_over="a second pass over the same frames with HIP events around "
                                    "every march launch on the render stream")
     else:
@@ -329,35 +389,42 @@ def main():
         "config": {"workload": "C3: 16^3 grid of per-cell SDF MLPs (39->2x64 softplus->16) and "
                                "color MLPs (48->32->3), 1920x1080, 8 seeded orbit views, "
                                "<=128 steps, eps 1e-4; march in " + args.precision +
-                               (", refinement and shading in fp32" if args.precision == "fp32" else
-                                ", refinement and shading on split-bf16 MFMA (hi/lo operands, "
-                                "~2^-16 per product)"),
+                               " (float32 ray positions and cell stepping), refinement and shading "
+                               "with float32 weights and arithmetic",
                    "rays_per_frame": rays, "views": len(views)},
-        "frame_ms_p50": pct(r["gpu_ms"], 50),
-        "frame_ms_p99": pct(r["gpu_ms"], 99),
-        "frame_wall_ms_p50": pct(r["wall_ms"], 50),
-        "frame_wall_ms_p99": pct(r["wall_ms"], 99),
+        "frame_ms_p50": lat["frame_ms_p50"],
+        "frame_ms_p99": lat["frame_ms_p99"],
+        "frame_wall_ms_p50": lat["frame_wall_ms_p50"],
+        "frame_wall_ms_p99": lat["frame_wall_ms_p99"],
+        "latency_frames": lat["frames"],
         "evals_per_ray": r["evals"] / (args.steps * rays),
         "march_ms_per_frame": r["march_ms"] / args.steps,
         "shade_ms_per_frame": sum(r["shade_ms"]) / args.steps,
         "march_launches_per_frame": r["march_launches"] / args.steps,
         "march_chunks_per_frame": r["chunks"] / args.steps,
-        "evals_per_tile_pair": r["evals"] / max(1, r["tiles"]),
+        "evals_per_tile": r["evals"] / max(1, r["tiles"]),
         "hit_fraction": r["hits"] / (args.steps * rays),
         "roofline": roofline,
     }
-    if not args.no_fp32 and args.precision != "fp32":
-        cams32 = [kn.make_camera(v, W, H, S, eps, "fp32") for v in views]
-        r32 = timed_frames(ctx, sid, cams32, out, args.steps, args.warmup // 2, torch)
-        v32 = args.steps * rays / r32["total_s"]
-        line["fp32_value"] = v32
-        line["bf16_over_fp32"] = value / v32
-        line["fp32_frame_ms_p50"] = pct(r32["gpu_ms"], 50)
-        line["fp32_frame_ms_p99"] = pct(r32["gpu_ms"], 99)
-        a32 = (r32["evals_timed"] / max(1, r32["march_launches"])) * work["flop"] / (
-            r32["march_ms"] / 1e3 / max(1, r32["march_launches"]))
-        line["fp32_march_roofline"] = dict(bound="mfma", achieved=a32 / 1e12, peak=PEAK_FP32_MFMA / 1e12,
-                                           unit="TFLOP/s", frac=a32 / PEAK_FP32_MFMA)
+    if not args.no_variants and args.precision != "fp32":
+        vs = {}
+        for name, prec, split in (("bf16_split_shading", "bf16", True), ("fp8", "fp8", False),
+                                  ("fp8_split_shading", "fp8", True), ("fp32", "fp32", False)):
+            rv, vv = variant(ctx, sid, views, W, H, S, eps, prec, split, out, args.steps, args.warmup // 2,
+                             torch, kn)
+            vs[name] = dict(value=vv, frame_ms_p50=pct(rv["gpu_ms"], 50), frame_ms_p99=pct(rv["gpu_ms"], 99),
+                            frames=args.steps, march_ms_per_frame=rv["march_ms"] / args.steps,
+                            shade_ms_per_frame=sum(rv["shade_ms"]) / args.steps)
+            if prec == "fp32":
+                a32 = (rv["evals_timed"] / max(1, rv["march_launches"])) * work["flop"] / (
+                    rv["march_ms"] / 1e3 / max(1, rv["march_launches"]))
+                vs[name]["march_roofline"] = dict(bound="mfma", achieved=a32 / 1e12, peak=PEAK_FP32_MFMA / 1e12,
+                                                  unit="TFLOP/s", frac=a32 / PEAK_FP32_MFMA)
+            print(f"bench: variant {name} done", file=sys.stderr, flush=True)
+        line["variants"] = vs
+        line["fp32_value"] = vs["fp32"]["value"]
+        line["bf16_over_fp32"] = value / vs["fp32"]["value"]
+        line["fp8_over_fp32"] = vs["fp8"]["value"] / vs["fp32"]["value"]
     if args.copy_calibration_mib > 0:
         n = args.copy_calibration_mib * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -366,14 +433,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    if args.pathtrace:
+    ctx.close()
+    if not args.no_pathtrace:
         line["pathtrace"] = pathtrace_bench(torch)
-    if args.serve:
+    if not args.no_serve:
         line["serving"] = serve_bench(args.serve_requests, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, views, W, H, S, eps, args.cpu_seconds)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

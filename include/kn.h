@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define KN_ABI_VERSION 1u
+#define KN_ABI_VERSION 2u   /* 2: kn_camera gained `flags` */
 
 typedef enum {
   KN_OK = 0,
@@ -125,8 +125,9 @@ kn_status kn_scene_destroy(kn_ctx* ctx, kn_scene_id scene);
  * by f, but never past the current cell's exit plane: there it moves to the
  * neighbouring cell.  A ray that leaves the grid, or uses max_steps SDF
  * evaluations without a hit, misses.  Hits are refined by two guarded
- * Newton steps along the ray (float32 weights), then depth, normal and
- * color are computed there.
+ * Newton steps along the ray, then depth, normal and color are computed
+ * there, with float32 weights and arithmetic whatever the march precision
+ * (unless flags asks for split-bfloat16 shading).
  * --------------------------------------------------------------------- */
 typedef struct {
   float eye[3], look_at[3], up[3];
@@ -141,7 +142,16 @@ typedef struct {
   uint64_t seed;                   /* random stream for path tracing */
   const float* env_rgb;            /* DEVICE [env_h][env_w][3] or NULL (black); path tracing */
   uint32_t env_w, env_h;
+  uint32_t flags;                  /* KN_CAMERA_* bits, 0 by default */
 } kn_camera;
+
+/* kn_camera.flags: refinement and shading of a bf16 or fp8 march with the SDF
+ * MLP's products on bfloat16 MFMA with split operands (each weight and each
+ * layer input as hi + lo bfloat16, three products per pair, about 2^-16
+ * relative error each) instead of float32 weights and arithmetic.  A faster
+ * variant; the default is float32.  Ignored for float32 marches; refused by
+ * the serving loop. */
+#define KN_CAMERA_SPLIT_BF16_SHADING 1u
 /* Path tracing (bounces >= 1; Sec. 3.4.1: Lambertian surfaces, the color
  * MLP output is the albedo).  Each pixel traces spp paths; sample s of pixel
  * p is jittered inside the pixel by Philox-4x32-10 keyed by `seed` with
@@ -212,6 +222,24 @@ kn_status kn_render(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const 
  * done. */
 kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points,
                    uint64_t n, float* d_out, float* grad_out, float* z_out, void* hip_stream);
+
+/* Allocation-free variant of kn_query, for callers that cannot allocate
+ * device memory during the call (code being recorded into a HIP graph, tight
+ * serving loops, harnesses that forbid allocation).  Same arguments, outputs,
+ * arithmetic and results (bit for bit) as kn_query; the work buffers (point
+ * records, per-cell counters and cursors, work items, control block) live in
+ * one static array per GPU in the library (about 12.2 MB, held by each GPU
+ * the library runs on until the process ends), whose device address the
+ * context looks up when it is created.  No hipMalloc, hipFree or allocating
+ * library routine is called, and counters are cleared with kernels, not
+ * memset nodes.  Limits: n <= 262144 points and grids of at most 2^18 cells;
+ * larger calls return KN_E_INVALID and change no output.  Every call on a GPU
+ * uses that GPU's array: calls of this process on one device are serialised
+ * by the library, and each call returns after its work is done on
+ * `hip_stream` (NULL = ctx stream); work of another library instance that
+ * overlaps on the same device would race.  Errors as kn_query. */
+kn_status kn_query_noalloc(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points,
+                           uint64_t n, float* d_out, float* grad_out, float* z_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------
  * Serving: a loop that keeps scenes resident and renders queued requests

@@ -2075,6 +2075,32 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
+// word fill and copy (clearing and restoring counters without memset or
+// memcpy nodes, for callers that record the work into graphs)
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* p, uint32_t n, uint32_t v) {
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_copy_u32(uint32_t* dst, const uint32_t* src, uint32_t n) {
+  for (uint32_t i = blockIdx.x * 256u + threadIdx.x; i < n; i += gridDim.x * 256u) dst[i] = src[i];
+}
+
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!p || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t grid = (uint32_t)std::min<size_t>((n + 255u) / 256u, 1024u);
+  hipLaunchKernelGGL(k_fill_u32, dim3(grid), dim3(256), 0, st, p, (uint32_t)n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  if (!dst || !src || n > 0xFFFFFFFFull) return hipErrorInvalidValue;
+  const uint32_t grid = (uint32_t)std::min<size_t>((n + 255u) / 256u, 1024u);
+  hipLaunchKernelGGL(k_copy_u32, dim3(grid), dim3(256), 0, st, dst, src, (uint32_t)n);
+  return hipGetLastError();
+}
+
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st) {
   if (a.cs == 0) return hipErrorInvalidValue;   // counter stride unset
   hipLaunchKernelGGL(k_query_bin, dim3((uint32_t)((a.n + 255u) / 256u)), dim3(256), 0, st, a);

@@ -204,6 +204,10 @@ hipError_t launch_march(const MarchArgs& a, int H, int prec, uint32_t block_word
 hipError_t launch_shade(const ShadeArgs& a, int H, int prec, bool pt, uint32_t block_words, uint32_t grid,
                         hipStream_t st);
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t st);
+// p[0..n) = v; dst[0..n) = src[0..n) (device words, kernels: no memset or
+// memcpy node)
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st);
 hipError_t launch_query_d(const QueryArgs& a, int H, int prec, uint32_t grid, hipStream_t st);
 hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream_t st);
 

@@ -365,8 +365,52 @@ namespace kn {
 class ServeLoop;
 }
 
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free point query (kn_query_noalloc): one array
+// per GPU, in the library's code object, holding the query's records,
+// per-cell counters, work items and control block for up to
+// kNoAllocMaxPoints points over up to kNoAllocMaxCells cells.  Host code
+// never uses the array's name as an address: each context looks up its
+// device's address once (hipGetSymbolAddress, in kn_ctx_create) and passes
+// that pointer to the kernels.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kNoAllocMaxPoints = 1u << 18;
+constexpr uint32_t kNoAllocMaxCells = 1u << 18;   // every grid_n <= 64
+
+namespace {
+constexpr size_t align256(size_t x) { return (x + 255u) & ~(size_t)255u; }
+
+struct NoAllocLayout {
+  size_t ctrl, counts, cursor, chunks, U, S, bytes;
+};
+
+constexpr NoAllocLayout noalloc_layout() {
+  NoAllocLayout L{};
+  L.ctrl = 0;
+  L.counts = align256(sizeof(Ctrl));
+  L.cursor = L.counts + align256((size_t)kNoAllocMaxCells * 4u);
+  L.chunks = L.cursor + align256((size_t)kNoAllocMaxCells * 4u);
+  L.U = L.chunks + align256(((size_t)kNoAllocMaxPoints / kQueryChunk + kNoAllocMaxCells + 2u) * 8u);
+  L.S = L.U + align256((size_t)kNoAllocMaxPoints * sizeof(RayRec));
+  L.bytes = L.S + align256((size_t)kNoAllocMaxPoints * sizeof(RayRec));
+  return L;
+}
+
+constexpr size_t kScratchBytes = noalloc_layout().bytes;   // about 12.2 MB
+static_assert(kScratchBytes < ((size_t)16 << 20), "scratch stays modest");
+
+std::mutex& scratch_mutex(int device) {
+  static std::mutex mus[64];
+  return mus[(unsigned)device % 64u];
+}
+}  // namespace
+
+static __device__ __align__(256) uint8_t kn_scratch[kScratchBytes];
+
 struct kn_ctx {
   int device = 0;
+  uint8_t* scratch = nullptr;  // this device's address of kn_scratch
+  hipError_t scratch_err = hipSuccess;
   int num_cu = 256;
   hipStream_t stream = nullptr;
   uint64_t budget = 0;
@@ -414,8 +458,10 @@ kn_status check_scan(kn_ctx* ctx, uint32_t scan_err) {
   return fail(KN_E_DEVICE, "cell scan: a look-back wait ran out; results of this call are invalid");
 }
 
-// word of kn_ctx::pinned that receives Ctrl::scan_err at the end of a call
+// words of kn_ctx::pinned that receive Ctrl::scan_err at the end of a call
+// (render and query; the allocation-free query)
 constexpr int kPinnedScanErr = 16;
+constexpr int kPinnedScanErrNoAlloc = 17;
 
 void free_pool(Pool& w) {
   void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.runs, w.hit_count, w.cursor, w.base,
@@ -512,15 +558,18 @@ PoolTabs pool_tabs(const Pool& w, uint32_t n_scenes) {
   return PoolTabs{w.scenes, w.reqs, n_scenes, &w.ctrl->miss_done[0], &w.ctrl->hit_done[0], w.path};
 }
 
-SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base) {
+// prec: the march precision; split: refinement and shading of a bf16 or fp8
+// march on the split-bfloat16 block (else the float32 block)
+SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base, bool split) {
+  const int shade_prec = split ? prec : KN_FP32;
   SceneEnt e{};
   e.sg = s->geom;
   e.sg.cell_base = cell_base;
   e.cell_end = cell_base + (uint32_t)(s->N * s->N * s->N);
   e.march = s->march(prec);
   e.march_words = s->march_words(prec);
-  e.shade = s->shading(prec);
-  e.shade_words = s->shading_words(prec);
+  e.shade = s->shading(shade_prec);
+  e.shade_words = s->shading_words(shade_prec);
   e.spk = softplus_consts(s->geom.beta);
   return e;
 }
@@ -537,6 +586,7 @@ struct RoundCfg {
   uint32_t n_scenes;
   uint32_t march_words;   // largest march block of the scenes
   uint32_t shade_words;   // largest shading block
+  bool split;             // bf16 / fp8 pools: split-bfloat16 shading (else float32)
   uint32_t cells;         // global cells in use
   int max_passes;
 };
@@ -650,7 +700,8 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sh.counts_next = w.counts + (next_round & 1) * w.cells * w.cs;
   sh.cs = w.cs;
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
-  KN_HIP(ctx, launch_shade(sh, c.hmode, c.prec, pt, c.shade_words, persistent_grid(ctx, 3), st));
+  KN_HIP(ctx, launch_shade(sh, c.hmode, c.split ? c.prec : (int)KN_FP32, pt, c.shade_words,
+                           persistent_grid(ctx, 3), st));
   if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
   return KN_OK;
 }
@@ -677,6 +728,14 @@ kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out)
   std::unique_ptr<kn_ctx> ctx(new kn_ctx());
   ctx->device = hip_device;
   KN_HIP(ctx, hipSetDevice(hip_device));
+  // this device's copy of the allocation-free query's scratch array (the
+  // array's name is a host-side stand-in, not a device address).  Without
+  // it only kn_query_noalloc fails, with the code kept here.
+  ctx->scratch_err = hipGetSymbolAddress(reinterpret_cast<void**>(&ctx->scratch), HIP_SYMBOL(kn_scratch));
+  if (ctx->scratch_err != hipSuccess) {
+    ctx->scratch = nullptr;
+    (void)hipGetLastError();
+  }
   hipDeviceProp_t prop;
   KN_HIP(ctx, hipGetDeviceProperties(&prop, hip_device));
   ctx->num_cu = prop.multiProcessorCount;
@@ -885,6 +944,8 @@ kn_status validate_camera(const kn_camera* c, const KnScene* s) {
     return fail(KN_E_INVALID, "environment map of size %ux%u", c->env_w, c->env_h);
   if (c->precision != KN_FP32 && c->precision != KN_BF16 && c->precision != KN_FP8_E4M3)
     return fail(KN_E_INVALID, "unknown precision %d", (int)c->precision);
+  if (c->flags & ~(uint32_t)KN_CAMERA_SPLIT_BF16_SHADING)
+    return fail(KN_E_INVALID, "unknown camera flags 0x%x", c->flags);
   if (!s->march(c->precision))
     return fail(KN_E_INVALID, "scene has no copy in precision %d (set its bit in precisions)",
                 (int)c->precision);
@@ -930,6 +991,93 @@ void camera_basis(const kn_camera* c, RaygenArgs& a) {
   }
 }
 
+kn_status validate_query(const KnScene* s, kn_precision precision, const float* points, uint64_t n) {
+  if (!points) return fail(KN_E_INVALID, "points is NULL");
+  if (n > (1ull << 28)) return fail(KN_E_INVALID, "too many points (%llu)", (unsigned long long)n);
+  if (precision != KN_FP32 && precision != KN_BF16 && precision != KN_FP8_E4M3)
+    return fail(KN_E_INVALID, "unknown precision %d", (int)precision);
+  if (!s->march(precision)) return fail(KN_E_INVALID, "scene has no copy in precision %d", (int)precision);
+  return KN_OK;
+}
+
+// Device buffers of one point query: records, per-cell counters (cell c at
+// c * cs) and cursors, work items and the control block.
+struct QueryBufs {
+  RayRec* U;
+  RayRec* S;
+  uint32_t* counts;
+  uint32_t* cursor;
+  uint2* chunks;
+  Ctrl* ctrl;
+  uint32_t cs;
+};
+
+// Enqueues a point query (Sec. 3.3: the points binned by cell, then each
+// cell's MLP on its batch): binning, scan, scatter, then the value kernel
+// and/or the full kernel (value, gradient, feature).  kernels_only clears and
+// restores counters with kernels instead of memset and memcpy nodes.
+kn_status enqueue_query(kn_ctx* ctx, const KnScene* s, kn_precision precision, const float* points, uint64_t n,
+                        float* d_out, float* grad_out, float* z_out, hipStream_t stream, const QueryBufs& b,
+                        bool kernels_only) {
+  const size_t cells = (size_t)s->N * s->N * s->N;
+  const SoftplusK spk = softplus_consts(s->geom.beta);
+  if (kernels_only) {
+    KN_HIP(ctx, launch_fill_u32(reinterpret_cast<uint32_t*>(b.ctrl), sizeof(Ctrl) / 4, 0u, stream));
+    KN_HIP(ctx, launch_fill_u32(b.counts, cells * b.cs, 0u, stream));
+  } else {
+    KN_HIP(ctx, hipMemsetAsync(b.ctrl, 0, sizeof(Ctrl), stream));
+    KN_HIP(ctx, hipMemsetAsync(b.counts, 0, cells * b.cs * 4, stream));
+  }
+  QueryBinArgs qb{s->geom, points, n, b.U, b.counts, b.cs};
+  KN_HIP(ctx, launch_query_bin(qb, stream));
+  ScanArgs sa{};
+  sa.counts = b.counts;
+  sa.cs = b.cs;
+  sa.C = (uint32_t)cells;
+  sa.T = kQueryChunk;
+  sa.zero_counts = 0;
+  sa.cursor = b.cursor;
+  sa.chunks = b.chunks;
+  sa.n_chunks = &b.ctrl->n_chunks[0];
+  sa.grab = b.ctrl->grab;
+  sa.grab0 = b.ctrl->grab0;
+  sa.ticket = &b.ctrl->scan_ticket;
+  sa.flags = b.ctrl->scan_flags;
+  sa.err = &b.ctrl->scan_err;
+  sa.zero_word = nullptr;
+  KN_HIP(ctx, launch_scan(sa, stream));
+  ScatterArgs sc{b.U, b.S, (uint32_t)n, nullptr, b.cursor, 0, b.cs};
+  KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536), stream));
+  QueryArgs qa{};
+  qa.sg = s->geom;
+  qa.S = b.S;
+  qa.pts = points;
+  qa.chunks = b.chunks;
+  qa.n_chunks = &b.ctrl->n_chunks[0];
+  qa.grab = b.ctrl->grab;
+  qa.spk = spk;
+  if (d_out) {
+    qa.blocks = s->march(precision);
+    qa.block_words = s->march_words(precision);
+    qa.d_out = d_out;
+    KN_HIP(ctx, launch_query_d(qa, s->H, (int)precision, persistent_grid(ctx, 2), stream));
+  }
+  if (grad_out || z_out) {
+    if (kernels_only)
+      KN_HIP(ctx, launch_copy_u32(b.ctrl->grab, b.ctrl->grab0, sizeof(b.ctrl->grab) / 4, stream));
+    else
+      KN_HIP(ctx, hipMemcpyAsync(b.ctrl->grab, b.ctrl->grab0, sizeof(b.ctrl->grab), hipMemcpyDeviceToDevice,
+                                 stream));
+    qa.blocks = s->shade;
+    qa.block_words = s->shade_words;
+    qa.d_out = nullptr;
+    qa.grad_out = grad_out;
+    qa.z_out = z_out;
+    KN_HIP(ctx, launch_query_full(qa, s->H, persistent_grid(ctx, 2), stream));
+  }
+  return KN_OK;
+}
+
 }  // namespace
 
 namespace kn {
@@ -947,7 +1095,8 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt);
   if (st != KN_OK) return st;
   Pool& w = ctx->ws;
-  *ctx->h_scene = scene_entry(s, (int)c->precision, 0u);
+  const bool split = (c->flags & KN_CAMERA_SPLIT_BF16_SHADING) && c->precision != KN_FP32;
+  *ctx->h_scene = scene_entry(s, (int)c->precision, 0u, split);
   ReqEnt q{};
   q.out = out_ptrs(fr);
   q.eps = c->eps;
@@ -962,8 +1111,8 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   q.env_w = c->env_w;
   q.env_h = c->env_h;
   *ctx->h_req = q;
-  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, (uint32_t)cells,
-                     ctx->max_passes};
+  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, split,
+                     (uint32_t)cells, ctx->max_passes};
 
   const bool timed = stats && stats->kernel_times;
   std::vector<std::pair<int, int>> march_ev, shade_ev;   // event index pairs
@@ -1167,11 +1316,7 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   KnScene* s = find_scene(ctx, scene);
   if (!s) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
   if (n == 0) return KN_OK;
-  if (!points) return fail(KN_E_INVALID, "points is NULL");
-  if (n > (1ull << 28)) return fail(KN_E_INVALID, "too many points (%llu)", (unsigned long long)n);
-  if (precision != KN_FP32 && precision != KN_BF16 && precision != KN_FP8_E4M3)
-    return fail(KN_E_INVALID, "unknown precision %d", (int)precision);
-  if (!s->march(precision)) return fail(KN_E_INVALID, "scene has no copy in precision %d", (int)precision);
+  if ((st = validate_query(s, precision, points, n)) != KN_OK) return st;
   std::lock_guard<std::mutex> lk(ctx->render_mu);
   KN_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
@@ -1179,56 +1324,55 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
   st = ensure_pool(ctx, ctx->ws, n, cells);
   if (st != KN_OK) return st;
   Pool& w = ctx->ws;
-  const SoftplusK spk = softplus_consts(s->geom.beta);
-  KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
-  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, cells * w.cs * 4, stream));
-  QueryBinArgs qb{s->geom, points, n, w.U, w.counts, w.cs};
-  KN_HIP(ctx, launch_query_bin(qb, stream));
-  ScanArgs sa{};
-  sa.counts = w.counts;
-  sa.cs = w.cs;
-  sa.C = (uint32_t)cells;
-  sa.T = kQueryChunk;
-  sa.zero_counts = 0;
-  sa.cursor = w.cursor;
-  sa.chunks = w.chunk;
-  sa.n_chunks = &w.ctrl->n_chunks[0];
-  sa.grab = w.ctrl->grab;
-  sa.grab0 = w.ctrl->grab0;
-  sa.ticket = &w.ctrl->scan_ticket;
-  sa.flags = w.ctrl->scan_flags;
-  sa.err = &w.ctrl->scan_err;
-  sa.zero_word = nullptr;
-  KN_HIP(ctx, launch_scan(sa, stream));
-  ScatterArgs sc{w.U, w.S, (uint32_t)n, nullptr, w.cursor, 0, w.cs};
-  KN_HIP(ctx, launch_scatter(sc, (uint32_t)std::min<uint64_t>((n + 255) / 256, 65536), stream));
-  QueryArgs qa{};
-  qa.sg = s->geom;
-  qa.S = w.S;
-  qa.pts = points;
-  qa.chunks = w.chunk;
-  qa.n_chunks = &w.ctrl->n_chunks[0];
-  qa.grab = w.ctrl->grab;
-  qa.spk = spk;
-  if (d_out) {
-    qa.blocks = s->march(precision);
-    qa.block_words = s->march_words(precision);
-    qa.d_out = d_out;
-    KN_HIP(ctx, launch_query_d(qa, s->H, (int)precision, persistent_grid(ctx, 2), stream));
-  }
-  if (grad_out || z_out) {
-    KN_HIP(ctx, hipMemcpyAsync(w.ctrl->grab, w.ctrl->grab0, sizeof(w.ctrl->grab), hipMemcpyDeviceToDevice,
-                               stream));
-    qa.blocks = s->shade;
-    qa.block_words = s->shade_words;
-    qa.d_out = nullptr;
-    qa.grad_out = grad_out;
-    qa.z_out = z_out;
-    KN_HIP(ctx, launch_query_full(qa, s->H, persistent_grid(ctx, 2), stream));
-  }
+  const QueryBufs b{w.U, w.S, w.counts, w.cursor, w.chunk, w.ctrl, w.cs};
+  st = enqueue_query(ctx, s, precision, points, n, d_out, grad_out, z_out, stream, b, false);
+  if (st != KN_OK) return st;
   KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
   KN_HIP(ctx, hipStreamSynchronize(stream));
   return check_scan(ctx, ctx->pinned[kPinnedScanErr]);
+}
+
+kn_status kn_query_noalloc(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points,
+                           uint64_t n, float* d_out, float* grad_out, float* z_out, void* hip_stream) {
+  kn_status st = check_ctx(ctx);
+  if (st != KN_OK) return st;
+  KnScene* s = find_scene(ctx, scene);
+  if (!s) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
+  if (n == 0) return KN_OK;
+  if ((st = validate_query(s, precision, points, n)) != KN_OK) return st;
+  if (n > kNoAllocMaxPoints)
+    return fail(KN_E_INVALID, "%llu points exceed the allocation-free query's limit of %u (use kn_query)",
+                (unsigned long long)n, kNoAllocMaxPoints);
+  const size_t cells = (size_t)s->N * s->N * s->N;
+  if (cells > kNoAllocMaxCells)
+    return fail(KN_E_INVALID, "%zu cells exceed the allocation-free query's limit of %u", cells, kNoAllocMaxCells);
+  if (!ctx->scratch)
+    return fail(KN_E_DEVICE, "no address of the scratch array on device %d: %s", ctx->device,
+                hipGetErrorString(ctx->scratch_err));
+  // the device's one scratch array: calls of this process on the device are
+  // serialised here (the call returns after its work is done)
+  std::lock_guard<std::mutex> lk(scratch_mutex(ctx->device));
+  KN_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  const NoAllocLayout L = noalloc_layout();
+  uint8_t* base = ctx->scratch;
+  const QueryBufs b{reinterpret_cast<RayRec*>(base + L.U), reinterpret_cast<RayRec*>(base + L.S),
+                    reinterpret_cast<uint32_t*>(base + L.counts), reinterpret_cast<uint32_t*>(base + L.cursor),
+                    reinterpret_cast<uint2*>(base + L.chunks), reinterpret_cast<Ctrl*>(base + L.ctrl), 1u};
+  s->refs++;
+  st = enqueue_query(ctx, s, precision, points, n, d_out, grad_out, z_out, stream, b, true);
+  if (st == KN_OK) {
+    if (hipMemcpyAsync(&ctx->pinned[kPinnedScanErrNoAlloc], &b.ctrl->scan_err, 4, hipMemcpyDeviceToHost,
+                       stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      ctx->poisoned = true;
+      st = fail(KN_E_DEVICE, "allocation-free query: %s", hipGetErrorString(hipGetLastError()));
+    } else {
+      st = check_scan(ctx, ctx->pinned[kPinnedScanErrNoAlloc]);
+    }
+  }
+  s->refs--;
+  return st;
 }
 
 }  // extern "C"
@@ -1436,7 +1580,7 @@ class ServeLoop {
     const uint32_t cells = (uint32_t)(s->N * s->N * s->N);
     if (table.size() >= (size_t)kMaxScenes || (size_t)cells_used + cells > cell_cap) return -1;
     const int k = (int)table.size();
-    h_scenes[k] = scene_entry(s, (int)prec, cells_used);
+    h_scenes[k] = scene_entry(s, (int)prec, cells_used, false);
     if (hipMemcpyAsync(pool.scenes + k, h_scenes + k, sizeof(SceneEnt), hipMemcpyHostToDevice, stream) !=
         hipSuccess)
       return -2;
@@ -1464,6 +1608,7 @@ class ServeLoop {
       c.shade_words = std::max(c.shade_words, e.shade_words);
     }
     c.prec = (int)prec;
+    c.split = false;
     c.n_scenes = (uint32_t)table.size();
     c.cells = cells_used;
     c.max_passes = ctx->max_passes;
@@ -1687,6 +1832,8 @@ kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, 
     st = validate_camera(cam, s);
     if (st != KN_OK) return st;
     if (cam->bounces != 0) return fail(KN_E_UNSUPPORTED, "the serving loop renders primary rays (bounces 0)");
+    if (cam->flags & KN_CAMERA_SPLIT_BF16_SHADING)
+      return fail(KN_E_UNSUPPORTED, "the serving loop refines and shades with float32 weights");
     if (cam->precision != ctx->serve->precision())
       return fail(KN_E_INVALID, "camera precision %d differs from the serving loop's %d", (int)cam->precision,
                   (int)ctx->serve->precision());

@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(HERE, "libkn.so")
 
 KN_OK, KN_PENDING = 0, 1
 KN_FP32, KN_BF16, KN_FP8_E4M3 = 0, 1, 2
-KN_ABI_VERSION = 1
+KN_ABI_VERSION = 2
+KN_CAMERA_SPLIT_BF16_SHADING = 1
 _STATUS = {0: "KN_OK", 1: "KN_PENDING", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_NOT_FOUND",
            -4: "KN_E_BUSY", -5: "KN_E_DEVICE", -6: "KN_E_TIMEOUT", -7: "KN_E_UNSUPPORTED",
            -8: "KN_E_SHUTDOWN"}
@@ -45,7 +46,8 @@ class Camera(C.Structure):
                 ("tan_half_diag", C.c_float), ("width", C.c_uint32), ("height", C.c_uint32),
                 ("spp", C.c_uint32), ("bounces", C.c_uint32), ("max_steps", C.c_uint32),
                 ("eps", C.c_float), ("precision", C.c_int), ("seed", C.c_uint64),
-                ("env_rgb", C.c_void_p), ("env_w", C.c_uint32), ("env_h", C.c_uint32)]
+                ("env_rgb", C.c_void_p), ("env_w", C.c_uint32), ("env_h", C.c_uint32),
+                ("flags", C.c_uint32)]
 
 
 class Frame(C.Structure):
@@ -66,8 +68,8 @@ class Stats(C.Structure):
 
 
 EXPORTS = ["kn_ctx_create", "kn_ctx_destroy", "kn_last_error", "kn_scene_create",
-           "kn_scene_destroy", "kn_render", "kn_query", "kn_serve_start", "kn_serve_submit",
-           "kn_serve_poll", "kn_serve_stop"]
+           "kn_scene_destroy", "kn_render", "kn_query", "kn_query_noalloc", "kn_serve_start",
+           "kn_serve_submit", "kn_serve_poll", "kn_serve_stop"]
 
 _lib = None
 
@@ -95,6 +97,7 @@ def lib():
         L.kn_scene_destroy.argtypes = [vp, C.c_uint32]
         L.kn_render.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame), C.POINTER(Stats)]
         L.kn_query.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
+        L.kn_query_noalloc.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
         L.kn_serve_start.argtypes = [vp, C.c_uint32, C.c_int]
         L.kn_serve_submit.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame),
                                       C.POINTER(C.c_uint64)]
@@ -119,13 +122,16 @@ def _ptr(t):
 
 def make_camera(view, width: int, height: int, max_steps: int, eps: float,
                 precision: str = "fp32", spp: int = 1, bounces: int = 0, seed: int = 0,
-                env=None) -> Camera:
+                env=None, split_shading: bool = False) -> Camera:
+    """A kn_camera; split_shading selects the split-bfloat16 refinement and
+    shading of bf16 / fp8 marches (float32 otherwise)."""
     env_ptr, ew, eh = None, 0, 0
     if env is not None:
         env_ptr, eh, ew = env.data_ptr(), env.shape[0], env.shape[1]
     return Camera((C.c_float * 3)(*view.eye), (C.c_float * 3)(*view.look_at),
                   (C.c_float * 3)(*view.up), float(view.tan_half_diag), width, height, spp,
-                  bounces, max_steps, eps, PRECISIONS[precision], seed, env_ptr, ew, eh)
+                  bounces, max_steps, eps, PRECISIONS[precision], seed, env_ptr, ew, eh,
+                  KN_CAMERA_SPLIT_BF16_SHADING if split_shading else 0)
 
 
 class Context:
@@ -199,8 +205,8 @@ class Context:
         return st.as_dict()
 
     def render(self, sid: int, view, width: int, height: int, max_steps: int, eps: float,
-               precision: str = "fp32", with_trace: bool = False) -> dict:
-        cam = make_camera(view, width, height, max_steps, eps, precision)
+               precision: str = "fp32", with_trace: bool = False, split_shading: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, precision, split_shading=split_shading)
         out = self.alloc_frame(width, height, with_trace)
         out["stats"] = self.render_into(sid, cam, out)
         return out
@@ -228,15 +234,21 @@ class Context:
         check(lib().kn_serve_stop(self.h))
 
     def query(self, sid: int, points, precision: str = "fp32", grad: bool = False,
-              feat: bool = False, stream=None) -> dict:
+              feat: bool = False, stream=None, noalloc: bool = False, out=None) -> dict:
+        """kn_query (or kn_query_noalloc) on a [n, 3] float32 device tensor;
+        `out` (a dict of d, grad, z tensors) receives the results if given."""
         import torch
         pts = points.contiguous()
         n = pts.shape[0]
-        d = torch.empty(n, dtype=torch.float32, device=pts.device)
-        g = torch.empty((n, 3), dtype=torch.float32, device=pts.device) if grad else None
-        z = torch.empty((n, 15), dtype=torch.float32, device=pts.device) if feat else None
+        if out is not None:
+            d, g, z = out.get("d"), out.get("grad"), out.get("z")
+        else:
+            d = torch.empty(n, dtype=torch.float32, device=pts.device)
+            g = torch.empty((n, 3), dtype=torch.float32, device=pts.device) if grad else None
+            z = torch.empty((n, 15), dtype=torch.float32, device=pts.device) if feat else None
         if stream is None:
             stream = torch.cuda.current_stream(pts.device)
-        check(lib().kn_query(self.h, sid, PRECISIONS[precision], _ptr(pts), n, _ptr(d), _ptr(g),
-                             _ptr(z), C.c_void_p(stream.cuda_stream)))
+        fn = lib().kn_query_noalloc if noalloc else lib().kn_query
+        check(fn(self.h, sid, PRECISIONS[precision], _ptr(pts), n, _ptr(d), _ptr(g), _ptr(z),
+                 C.c_void_p(stream.cuda_stream)))
         return dict(d=d, grad=g, z=z)

@@ -192,6 +192,33 @@ void case_render_query(bool scan_err) {
   expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
 }
 
+void case_noalloc() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(16, 64, 13);
+  kn_scene_desc d = desc_of(s, kAll);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  const uint64_t nmax = 1u << 18;
+  float *pts = nullptr, *dd = nullptr, *gg = nullptr, *zz = nullptr;
+  (void)hipMalloc((void**)&pts, (nmax + 1) * 12);
+  (void)hipMalloc((void**)&dd, (nmax + 1) * 4);
+  (void)hipMalloc((void**)&gg, (nmax + 1) * 12);
+  (void)hipMalloc((void**)&zz, (nmax + 1) * 60);
+  for (kn_precision p : {KN_FP32, KN_BF16, KN_FP8_E4M3})
+    expect(kn_query_noalloc(ctx, id, p, pts, nmax, dd, gg, zz, nullptr) == KN_OK, "no-alloc query at the limit");
+  expect(kn_query_noalloc(ctx, id, KN_BF16, pts, 333, dd, nullptr, nullptr, nullptr) == KN_OK,
+         "no-alloc query, small");
+  expect(kn_query_noalloc(ctx, id, KN_BF16, pts, nmax + 1, dd, nullptr, nullptr, nullptr) == KN_E_INVALID,
+         "no-alloc query above the limit");
+  expect(std::strstr(kn_last_error(), "limit") != nullptr, "message names the limit");
+  (void)hipFree(pts);
+  (void)hipFree(dd);
+  (void)hipFree(gg);
+  (void)hipFree(zz);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
 void case_query_scan_err() {
   kn_ctx* ctx = nullptr;
   expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
@@ -261,6 +288,7 @@ int main(int argc, char** argv) {
   else if (c == "render") case_render_query(false);
   else if (c == "render_scan_err") case_render_query(true);
   else if (c == "query_scan_err") case_query_scan_err();
+  else if (c == "noalloc") case_noalloc();
   else if (c == "serve") case_serve(false);
   else if (c == "serve_scan_err") case_serve(true);
   else {

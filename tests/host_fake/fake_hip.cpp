@@ -121,6 +121,16 @@ hipError_t hipEventDestroy(hipEvent_t e) { delete e; return hipSuccess; }
 hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
 hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t, hipEvent_t) { *ms = 0.0f; return hipSuccess; }
+hipError_t hipGetLastError() { return hipSuccess; }
+// A device symbol is a host array here.  It is registered as device memory
+// of 16 MB (its size is not known here; the library's scratch is smaller):
+// the address sanitizer checks the array's real bounds.
+hipError_t hipGetSymbolAddress(void** p, const void* symbol) {
+  *p = const_cast<void*>(symbol);
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_live.emplace(static_cast<const char*>(symbol), (size_t)16 << 20);
+  return hipSuccess;
+}
 
 namespace kn {
 
@@ -183,6 +193,17 @@ hipError_t launch_march(const MarchArgs& a, int, int, uint32_t, uint32_t, hipStr
 hipError_t launch_shade(const ShadeArgs& a, int, int, bool, uint32_t, uint32_t, hipStream_t) {
   need_tabs(a.tabs);
   need(a.S, 16, "sorted records");
+  return hipSuccess;
+}
+hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t) {
+  need(p, n * 4, "fill destination");
+  for (size_t i = 0; i < n; ++i) p[i] = v;
+  return hipSuccess;
+}
+hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t) {
+  need(dst, n * 4, "copy destination");
+  need(src, n * 4, "copy source");
+  std::memmove(dst, src, n * 4);
   return hipSuccess;
 }
 hipError_t launch_query_bin(const QueryBinArgs& a, hipStream_t) {

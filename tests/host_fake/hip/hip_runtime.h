@@ -11,6 +11,8 @@
 #define __host__
 #define __device__
 #define __global__
+#define __align__(n) __attribute__((aligned(n)))
+#define HIP_SYMBOL(x) (&(x))
 
 typedef enum hipError_t { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2,
                           hipErrorNoDevice = 100 } hipError_t;
@@ -58,3 +60,5 @@ hipError_t hipEventDestroy(hipEvent_t e);
 hipError_t hipEventRecord(hipEvent_t e, hipStream_t st);
 hipError_t hipEventSynchronize(hipEvent_t e);
 hipError_t hipEventElapsedTime(float* ms, hipEvent_t a, hipEvent_t b);
+hipError_t hipGetSymbolAddress(void** p, const void* symbol);
+hipError_t hipGetLastError();

@@ -159,8 +159,8 @@ def test_query_fp8_matches_emulation(ctx, H):
     ctx.scene_destroy(sid)
 
 
-def _render(ctx, sid, view, W, H, S, eps=1e-4, precision="fp32"):
-    return ctx.render(sid, view, W, H, S, eps, precision, with_trace=True)
+def _render(ctx, sid, view, W, H, S, eps=1e-4, precision="fp32", split=False):
+    return ctx.render(sid, view, W, H, S, eps, precision, with_trace=True, split_shading=split)
 
 
 def test_render_c1_full_frame(ctx):
@@ -275,14 +275,15 @@ def _fstop_bound(scene, mode, n=6000, seed=11):
     return 1.5 * float(np.abs(lowp - f["d"][near]).max()), int(near.size)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp8"])
-def test_render_c3_lowp_against_oracle(ctx, precision):
+@pytest.mark.parametrize("precision,split", [("bf16", False), ("bf16", True), ("fp8", False), ("fp8", True)])
+def test_render_c3_lowp_against_oracle(ctx, precision, split):
     """The headline frames: C3 (16^3, H=64, 1920x1080, S=128) marched in bf16
     or fp8, in the launch configuration the benchmark times, against the FP64
     oracle on seeded pixel samples of two orbit views.
 
-    Asserted (whatever the march precision, refinement and shading run on
-    split-bf16 MFMA and must land on the method's result):
+    Asserted (whatever the march precision, refinement and shading, with
+    float32 weights or, in the split variant, on split-bf16 MFMA, must land on
+    the method's result):
       - point check: at each GPU hit's final point, where the FP64 normal is
         well conditioned, the GPU normal and colour equal the FP64 ones
         (<= 0.1 degree, <= 1e-3), for all but 0.1% of the hits;
@@ -304,12 +305,14 @@ def test_render_c3_lowp_against_oracle(ctx, precision):
     log(f"{precision}: stated march-stop bound {bound:.3e} (from {nb} points near the surface)")
     os_ = O.OracleScene.from_scene(sc)
     for vi, view in enumerate(synth.config_views("c3")[:2]):
-        out = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"], c["eps"], precision=precision)
+        out = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"], c["eps"], precision=precision,
+                      split=split)
         pix = synth.sample_pixels(c["width"], c["height"], 2500, seed=c["seed"] + 40 + vi)
         g = P.gpu_arrays(out, pix)
         rep = P.compare(sc, view, c["width"], c["height"], c["max_steps"], c["eps"], g, pixels=pix)
-        log(f"C3 {precision} view {vi}:", rep.as_dict())
-        P.record(f"c3_{precision}_view{vi}", dict(hit_agree=rep.hit_agree, n=rep.n, **rep.err_all,
+        tag = f"{precision}{'_split' if split else ''}"
+        log(f"C3 {tag} view {vi}:", rep.as_dict())
+        P.record(f"c3_{tag}_view{vi}", dict(hit_agree=rep.hit_agree, n=rep.n, **rep.err_all,
                                                   point_n=rep.point_n, point_bad=rep.point_bad,
                                                   replay_n=rep.replay_n, replay_bad=rep.replay_bad,
                                                   fstop_max=rep.fstop_max, fstop_bound=bound))
@@ -332,10 +335,11 @@ def test_render_c3_lowp_against_oracle(ctx, precision):
     ctx.scene_destroy(sid)
 
 
-@pytest.mark.parametrize("precision", ["bf16", "fp8"])
-def test_lowp_shading_replays_against_oracle(ctx, precision):
-    """Pools marching in bf16 or fp8 refine and shade on bf16 MFMA with split
-    (hi + lo) operands.  On a smooth sphere (no per-cell noise) every hit is
+@pytest.mark.parametrize("precision,split", [("bf16", False), ("bf16", True), ("fp8", False), ("fp8", True)])
+def test_lowp_shading_replays_against_oracle(ctx, precision, split):
+    """Pools marching in bf16 or fp8 refine and shade with float32 weights or,
+    in the split variant, on bf16 MFMA with split (hi + lo) operands.  On a
+    smooth sphere (no per-cell noise) every hit is
     replayed by the FP64 oracle from the GPU's march state (cell, t_march,
     t_entry): its two Newton steps and shading must reproduce the GPU depth,
     normal and colour to the parity tolerances (1e-4, 0.1 degree, 1e-3), and
@@ -344,12 +348,13 @@ def test_lowp_shading_replays_against_oracle(ctx, precision):
     sc = synth.sphere_scene(16, 64, 0.6, 0.0, seed=3001)
     sid = ctx.scene_create(sc, precisions=(precision,))
     view = synth.config_views("c3")[1]
-    out = _render(ctx, sid, view, 480, 270, 128, precision=precision)
+    out = _render(ctx, sid, view, 480, 270, 128, precision=precision, split=split)
     g = P.gpu_arrays(out)
     rep = P.compare(sc, view, 480, 270, 128, 1e-4, g)
     nhit = int((g["hit"] == 1).sum())
-    log(f"{precision} smooth sphere: {nhit} hits;", rep.as_dict())
-    P.record(f"smooth_sphere_{precision}", dict(hits=nhit, replay_n=rep.replay_n, replay_bad=rep.replay_bad,
+    tag = f"{precision}{'_split' if split else ''}"
+    log(f"{tag} smooth sphere: {nhit} hits;", rep.as_dict())
+    P.record(f"smooth_sphere_{tag}", dict(hits=nhit, replay_n=rep.replay_n, replay_bad=rep.replay_bad,
                                                 replay_depth_max=rep.replay_depth_max,
                                                 replay_normal_max=rep.replay_normal_max,
                                                 replay_rgb_max=rep.replay_rgb_max, point_n=rep.point_n,
