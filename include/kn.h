@@ -29,7 +29,7 @@
 extern "C" {
 #endif
 
-#define KN_ABI_VERSION 2u   /* 2: kn_camera gained `flags` */
+#define KN_ABI_VERSION 2u   /* 2: kn_camera gained `flags`, kn_frame `segments` */
 
 typedef enum {
   KN_OK = 0,
@@ -177,6 +177,28 @@ typedef struct {
   int32_t status;
 } kn_trace_record;
 
+/* Per-segment record of a path-traced frame (diagnostics and per-segment
+ * checks): path p = pixel * spp + sample, segment k = 0..bounces at index
+ * p * (bounces + 1) + k.  Segment 0 is the camera ray; segment k >= 1 starts
+ * at the previous hit (x + 1e-3 n) in the scattered direction.  Written when
+ * the segment starts (origin, dir; status -1 until it ends) and when it ends:
+ * status 0 = it misses the box, 1 = hit (t = refined distance along dir,
+ * normal, albedo = color MLP output), 2 = left the grid, 3 = step budget used
+ * up; t_march, t_entry, cell and steps describe where the march stopped, as
+ * in kn_trace_record.  Segments a path never reaches keep status -1. */
+typedef struct {
+  float origin[3];
+  float dir[3];
+  float t_march, t_entry;
+  float t;
+  float normal[3];
+  float albedo[3];
+  int32_t cell;
+  int32_t status;
+  uint32_t steps;
+  uint32_t pad[2];
+} kn_segment_record;   /* 80 bytes */
+
 /* Output buffers, all DEVICE pointers owned by the caller, row-major
  * [height][width] (rgb and normal with 3 floats per pixel).  Only rgb is
  * required; NULL skips an output.  Misses get rgb = background (black, or
@@ -189,6 +211,7 @@ typedef struct {
   uint8_t* hit;
   uint16_t* steps;                 /* SDF evaluations of the march */
   kn_trace_record* trace;          /* optional diagnostics */
+  kn_segment_record* segments;     /* optional, path tracing: [W*H*spp][bounces + 1] */
   void* hip_stream;                /* hipStream_t to run on; NULL = ctx stream */
 } kn_frame;
 

@@ -229,6 +229,15 @@ __global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
     float t0, tf;
     inbox = slab(a.sg, a.eye, d, &t0, &tf);
     PathRec pr{{1.0f, 1.0f, 1.0f}, {0.0f, 0.0f, 0.0f}, 0u, 0u};
+    if (a.out.seg) {
+      SegRec* sr = a.out.seg + (size_t)id * (a.bounces + 1u);
+      for (uint32_t k = 0; k <= a.bounces; ++k)
+        sr[k] = SegRec{{0.0f, 0.0f, 0.0f}, {0.0f, 0.0f, 0.0f}, 0.0f, 0.0f, 0.0f, {0.0f, 0.0f, 0.0f},
+                       {0.0f, 0.0f, 0.0f}, -1, -1, 0u, {0u, 0u}};
+      sr[0].o[0] = a.eye[0]; sr[0].o[1] = a.eye[1]; sr[0].o[2] = a.eye[2];
+      sr[0].d[0] = d[0]; sr[0].d[1] = d[1]; sr[0].d[2] = d[2];
+      if (!inbox) sr[0].status = kBoxMiss;
+    }
     if (inbox) {
       cell = entry_cell(a.sg, a.eye, d, t0);
       a.rs[id] = RayStatic{a.eye[0], a.eye[1], a.eye[2], tf, d[0], d[1], d[2], (a.slot << kPixBits) | pix};
@@ -1430,6 +1439,14 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
           for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
           if (pr.bounce == 0 && rid % q.spp == 0)
             write_miss(q.out, px & kPixMask, (int)steps, t, t_entry, (int32_t)cell, mst, false);
+          if (q.out.seg) {
+            SegRec& sr = q.out.seg[(size_t)rid * (q.bounces + 1u) + pr.bounce];
+            sr.t_march = t;
+            sr.t_entry = t_entry;
+            sr.cell = (int32_t)cell;
+            sr.status = mst;
+            sr.steps = steps;
+          }
         } else {
           write_miss(q.out, px & kPixMask, (int)steps, t, t_entry, (int32_t)cell, mst);
         }
@@ -1826,6 +1843,19 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           if (out.trace) out.trace[px] = TraceRec{r.t, r.t_entry, (int32_t)cell, kHit};
         }
         if constexpr (PT) {
+          if (out.seg) {
+            SegRec& sr = out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce];
+            sr.t_march = r.t;
+            sr.t_entry = r.t_entry;
+            sr.t = t;
+            for (int c = 0; c < 3; ++c) {
+              sr.n[c] = n[c];
+              sr.albedo[c] = rgb[c];
+            }
+            sr.cell = (int32_t)cell;
+            sr.status = kHit;
+            sr.steps = r.key >> kCellBits;
+          }
           if (pr.bounce < q.bounces) {
             // scatter: cosine-weighted about n, throughput x albedo, the new
             // segment starts 1e-3 off the surface
@@ -1835,6 +1865,13 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
             cosine_dir(n, u1, u2, nd);
             for (int c = 0; c < 3; ++c) no[c] = o[c] + t * d[c] + 1e-3f * n[c];
             ++pr.bounce;
+            if (out.seg) {
+              SegRec& sn = out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce];
+              for (int c = 0; c < 3; ++c) {
+                sn.o[c] = no[c];
+                sn.d[c] = nd[c];
+              }
+            }
             float t0, tf;
             if (slab(sg, no, nd, &t0, &tf)) {
               ncell = entry_cell(sg, no, nd, t0);
@@ -1846,6 +1883,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
               float e[3];
               env_lookup(q.env, q.env_w, q.env_h, nd, e);
               for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
+              if (out.seg) out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce].status = kBoxMiss;
             }
           }
           a.tabs.path[r.rid] = pr;

@@ -13,6 +13,7 @@ struct OutPtrs {
   uint8_t* hit;
   uint16_t* steps;
   TraceRec* trace;
+  SegRec* seg;             // path tracing: [paths][bounces + 1] or null
   float bg[3];
 };
 
@@ -71,7 +72,7 @@ struct RaygenPtArgs {
   float eye[3], fwd[3], right[3], up[3];
   float tx, ty;
   int W, Hh;
-  uint32_t spp;
+  uint32_t spp, bounces;
   uint32_t seed_lo, seed_hi;
   const float* env;
   uint32_t env_w, env_h;

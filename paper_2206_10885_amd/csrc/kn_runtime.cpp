@@ -576,7 +576,8 @@ SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base, bool split)
 
 OutPtrs out_ptrs(const kn_frame* fr) {
   return OutPtrs{fr->rgb, fr->depth, fr->normal, fr->hit, fr->steps,
-                 reinterpret_cast<TraceRec*>(fr->trace), {0.0f, 0.0f, 0.0f}};
+                 reinterpret_cast<TraceRec*>(fr->trace), reinterpret_cast<SegRec*>(fr->segments),
+                 {0.0f, 0.0f, 0.0f}};
 }
 
 // What the kernels of one pool round need to know about its tables.
@@ -1099,6 +1100,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   *ctx->h_scene = scene_entry(s, (int)c->precision, 0u, split);
   ReqEnt q{};
   q.out = out_ptrs(fr);
+  if (!pt) q.out.seg = nullptr;   // segment records describe path-traced frames only
   q.eps = c->eps;
   q.max_steps = c->max_steps;
   q.npix = (uint32_t)npix;
@@ -1200,6 +1202,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     rp.W = (int)c->width;
     rp.Hh = (int)c->height;
     rp.spp = spp;
+    rp.bounces = c->bounces;
     rp.seed_lo = q.seed_lo;
     rp.seed_hi = q.seed_hi;
     rp.env = q.env;
@@ -1467,6 +1470,7 @@ class ServeLoop {
     q->scene = s;
     q->cam = *cam;
     q->out = out_ptrs(fr);
+    q->out.seg = nullptr;   // primary rays only: no path segments
     q->npix = npix;
     q->t_submit = std::chrono::steady_clock::now();
     {

@@ -53,7 +53,23 @@ class Camera(C.Structure):
 class Frame(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("normal", C.c_void_p),
                 ("hit", C.c_void_p), ("steps", C.c_void_p), ("trace", C.c_void_p),
-                ("hip_stream", C.c_void_p)]
+                ("segments", C.c_void_p), ("hip_stream", C.c_void_p)]
+
+
+SEGMENT_WORDS = 20   # kn_segment_record: 80 bytes
+
+
+def segment_fields(seg) -> dict:
+    """Fields of kn_segment_record from a [..., 20] int32 tensor / array (as
+    numpy): origin, dir, t_march, t_entry, t, normal, albedo, cell, status,
+    steps."""
+    a = seg.cpu().numpy() if hasattr(seg, "cpu") else np.asarray(seg)
+    f = a.view(np.float32)
+    return dict(origin=f[..., 0:3].astype(np.float64), dir=f[..., 3:6].astype(np.float64),
+                t_march=f[..., 6].astype(np.float64), t_entry=f[..., 7].astype(np.float64),
+                t=f[..., 8].astype(np.float64), normal=f[..., 9:12].astype(np.float64),
+                albedo=f[..., 12:15].astype(np.float64), cell=a[..., 15].astype(np.int64),
+                status=a[..., 16].astype(np.int64), steps=a[..., 17].astype(np.int64))
 
 
 class Stats(C.Structure):
@@ -198,7 +214,7 @@ class Context:
             stream = torch.cuda.current_stream(self.device)
         fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
                    _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
-                   C.c_void_p(stream.cuda_stream))
+                   _ptr(out.get("segments")), C.c_void_p(stream.cuda_stream))
         st = Stats()
         st.kernel_times = 1 if kernel_times else 0
         check(lib().kn_render(self.h, sid, C.byref(cam), C.byref(fr), C.byref(st)))
@@ -219,7 +235,8 @@ class Context:
         """Queues a frame; `out` (from alloc_frame) must stay alive until
         serve_poll reports it finished."""
         fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
-                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")), None)
+                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
+                   _ptr(out.get("segments")), None)
         rid = C.c_uint64()
         check(lib().kn_serve_submit(self.h, sid, C.byref(cam), C.byref(fr), C.byref(rid)))
         return rid.value

@@ -126,3 +126,156 @@ def test_path_tracing_argument_errors(ctx):
     with pytest.raises(kn.KnError, match="E_INVALID"):
         ctx.render_into(sid, kn.make_camera(v, 8, 8, 64, 1e-4, spp=0, bounces=1), out)
     ctx.scene_destroy(sid)
+
+
+@pytest.fixture(scope="module")
+def c5_scene(ctx):
+    """The C5 scene (32^3 grid, H = 64) resident in every precision."""
+    sc = synth.config_scene("c5")
+    sid = ctx.scene_create(sc, precisions=("bf16", "fp8"))
+    yield sc, sid
+    ctx.scene_destroy(sid)
+
+
+def _uniforms(seed, pixel, sample, k):
+    """The path's two uniforms at event k: Philox-4x32-10 keyed by the seed
+    with counter (pixel, sample, k, 0), top 24 bits of the first two words
+    times 2^-24 (the oracle's generator)."""
+    x = O.philox4x32_10([pixel, sample, k, 0], [seed & 0xFFFFFFFF, seed >> 32])
+    return (int(x[0]) >> 8) * 2.0 ** -24, (int(x[1]) >> 8) * 2.0 ** -24
+
+
+@pytest.mark.parametrize("precision", ["fp8", "bf16", "fp32"])
+def test_c5_per_segment_against_oracle(ctx, c5_scene, precision):
+    """C5 (32^3, H = 64, 1920x1080, 4 spp, 3 bounces, 512x256 environment),
+    path traced on the GPU with per-segment records, compared with the FP64
+    oracle segment by segment on the paths of 120 sampled pixels (480 paths),
+    each segment from the GPU's own origin and direction (identical rays, so
+    FP32/FP64 differences do not compound over bounces):
+      - segment 0 is the oracle's camera ray through the Philox jitter;
+        segment k >= 1 starts 1e-3 above the GPU's previous hit along its
+        normal, in the oracle's cosine-weighted direction about that normal
+        for the Philox uniforms of event k;
+      - every GPU hit is replayed by the oracle from the GPU's march state:
+        where the replay is well conditioned, depth (along the segment),
+        normal and albedo match it (1e-4, 0.1 degree, 1e-3) on all but 0.1%;
+      - the FP64 SDF where each hit's march stopped is below eps plus the
+        precision's stated bound (float32: 1e-5);
+      - the oracle's own trace of the segment agrees on hit / miss (reported;
+        float32: >= 99% of the segments whose oracle trace is stable);
+      - each pixel's colour equals the mean over its samples of the radiance
+        the GPU's own segments define (throughput = product of albedos, an
+        escaping segment adds throughput x env(dir)), to 1e-4 relative.
+    Image-level agreement with the oracle's independent paths is parity
+    unpinned (compounding differences)."""
+    from paper_2206_10885_amd import kn
+    sc, sid = c5_scene
+    c = synth.CONFIGS["c5"]
+    W, H, spp, B, S, eps = c["width"], c["height"], c["spp"], c["bounces"], c["max_steps"], c["eps"]
+    seed = c["path_seed"]
+    env = synth.env_map(512, 256, seed=c["env_seed"])
+    envt = torch.tensor(env, device="cuda")
+    view = synth.orbit_views(1, c["seed"] + 500)[0]
+    cam = kn.make_camera(view, W, H, S, eps, precision, spp=spp, bounces=B, seed=seed, env=envt)
+    out = ctx.alloc_frame(W, H)
+    log(f"c5 segments {precision}: allocating {W * H * spp * (B + 1) * 80 / 1e9:.2f} GB of records")
+    out["segments"] = torch.empty((W * H * spp * (B + 1), kn.SEGMENT_WORDS), dtype=torch.int32, device="cuda")
+    st = ctx.render_into(sid, cam, out)
+    torch.cuda.synchronize()
+    pix = synth.sample_pixels(W, H, 120, seed=c["seed"] + 77)
+    paths = (pix[:, None] * spp + np.arange(spp)[None, :]).ravel()
+    rows = (paths[:, None] * (B + 1) + np.arange(B + 1)[None, :]).ravel()
+    seg = kn.segment_fields(out["segments"][torch.tensor(rows, device="cuda")].view(len(paths), B + 1, -1))
+    rgb = out["rgb"].cpu().numpy().reshape(-1, 3)[pix].astype(np.float64)
+    del out
+    os_ = O.OracleScene.from_scene(sc)
+    pert = [O.OracleScene.from_scene(P.perturbed(sc, 1e-6, 700 + k)) for k in range(3)]
+    rng = np.random.default_rng(9)
+    half = 1.0 / sc.N
+    centers = synth.cell_centers(sc.N)
+    bound = {"fp32": 1e-5}.get(precision)
+    if bound is None:
+        from tests.test_gpu_parity import _fstop_bound
+        bound, _ = _fstop_bound(sc, precision, n=3000)
+    n_seg = n_hit = n_rep = rep_bad = chain_bad = fstop_bad = agree_n = agree_ok = 0
+    worst = dict(depth=0.0, normal=0.0, albedo=0.0, origin=0.0, dir=0.0, rgb=0.0)
+    Lpix = np.zeros((len(pix), 3))
+    for q, pth in enumerate(paths):
+        p, smp = divmod(int(pth), spp)
+        T = np.ones(3)
+        L = np.zeros(3)
+        for k in range(B + 1):
+            o, d = seg["origin"][q, k], seg["dir"][q, k]
+            status = int(seg["status"][q, k])
+            if k == 0:
+                xi = _uniforms(seed, p, smp, 0) if spp > 1 else (0.5, 0.5)
+                oo, od = O.camera_ray(view, W, H, p // W, p % W, *xi)
+            else:
+                prev = {f: seg[f][q, k - 1] for f in ("origin", "dir", "t", "normal")}
+                u1, u2 = _uniforms(seed, p, smp, k)
+                od = O.cosine_dir(prev["normal"], u1, u2)
+                oo = prev["origin"] + prev["t"] * prev["dir"] + 1e-3 * prev["normal"]
+            eo, ed = float(np.abs(o - oo).max()), float(P.angle_deg(d, od))
+            worst["origin"], worst["dir"] = max(worst["origin"], eo), max(worst["dir"], ed)
+            if eo > 1e-5 or ed > 1e-3:
+                chain_bad += 1
+            assert status in (0, 1, 2, 3), (q, k, status)
+            n_seg += 1
+            if status != 1:
+                L += T * O.env_lookup(env, d)
+                break
+            n_hit += 1
+            cell = int(seg["cell"][q, k])
+            idx = (cell % sc.N, (cell // sc.N) % sc.N, cell // (sc.N * sc.N))
+            cc = centers[cell]
+            xs = o + seg["t_march"][q, k] * d
+            if os_.sdf_eval(cell, (xs - cc) / half)[0] - eps > bound:
+                fstop_bad += 1
+            tr = P._trace_struct(idx, seg["t_march"][q, k], seg["t_entry"][q, k])
+            sh = os_.shade(o, d, tr)
+            stable = True
+            for ps in pert:
+                dj = d + 1e-7 * rng.standard_normal(3)
+                dj /= np.linalg.norm(dj)
+                s2 = ps.shade(o, dj, P._trace_struct(idx, seg["t_march"][q, k] * (1 + 1e-6 * rng.standard_normal()),
+                                                     seg["t_entry"][q, k]))
+                if (abs(s2["depth"] - sh["depth"]) > P.TOL_DEPTH / 2
+                        or P.angle_deg(s2["normal"], sh["normal"]) > P.TOL_NORMAL_DEG / 2
+                        or np.abs(s2["rgb"] - sh["rgb"]).max() > P.TOL_RGB / 2):
+                    stable = False
+                    break
+            if stable:
+                n_rep += 1
+                e_d = abs(sh["depth"] - seg["t"][q, k])
+                e_n = float(P.angle_deg(sh["normal"], seg["normal"][q, k]))
+                e_c = float(np.abs(sh["rgb"] - seg["albedo"][q, k]).max())
+                worst["depth"], worst["normal"] = max(worst["depth"], e_d), max(worst["normal"], e_n)
+                worst["albedo"] = max(worst["albedo"], e_c)
+                if e_d > P.TOL_DEPTH or e_n > P.TOL_NORMAL_DEG or e_c > P.TOL_RGB:
+                    rep_bad += 1
+            if k == B:
+                break
+            T = T * seg["albedo"][q, k]
+        # the oracle's own trace of this path's first segment (hit / miss)
+        r0 = os_.trace(seg["origin"][q, 0], seg["dir"][q, 0], S, eps)
+        r1 = pert[0].trace(seg["origin"][q, 0], seg["dir"][q, 0], S, eps)
+        if (r0["status"] == O.HIT) == (r1["status"] == O.HIT):
+            agree_n += 1
+            agree_ok += int((r0["status"] == O.HIT) == (seg["status"][q, 0] == 1))
+        Lpix[q // spp] += L / spp
+    erel = np.abs(Lpix - rgb).max(1) / (1.0 + np.abs(Lpix).max(1))
+    worst["rgb"] = float(erel.max())
+    agree = agree_ok / max(1, agree_n)
+    log(f"c5 {precision}: {n_seg} segments ({n_hit} hits), chain errors {chain_bad}, replays {n_rep} "
+        f"(bad {rep_bad}), stop over bound {fstop_bad}, primary hit agreement with the oracle {agree:.4f}; "
+        f"worst {worst}; frame stats {st}")
+    P.record(f"c5_segments_{precision}", dict(segments=n_seg, hits=n_hit, replays=n_rep, replay_bad=rep_bad,
+                                              chain_bad=chain_bad, fstop_bad=fstop_bad, fstop_bound=bound,
+                                              primary_hit_agreement=agree, worst=worst))
+    assert n_hit > 300 and n_rep > 0.5 * n_hit
+    assert chain_bad == 0
+    assert rep_bad <= 1e-3 * n_rep
+    assert fstop_bad == 0
+    assert worst["rgb"] < 1e-4
+    if precision == "fp32":
+        assert agree >= 0.99

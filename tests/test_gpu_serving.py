@@ -181,3 +181,49 @@ def test_serving_errors():
             ctx.serve_poll(rid, 0)
         ctx.serve_stop()
         ctx.scene_destroy(sid)
+
+
+def test_serving_c4_scenes_mix_equals_alone():
+    """C4's eight resident scenes (grids 16^3, 16^3, 20^3, 24^3, 24^3, 28^3,
+    32^3, 32^3; H = 32 for even k, 64 for odd k; r = 0.5 + 0.02 k; sigma
+    0.02) in one serving pool, bf16, 256 steps: 24 requests at C4's
+    resolutions {256^2, 512^2, 800^2, 1920x1080} submitted together, each
+    equal bit for bit to the same frame rendered alone."""
+    kn = _kn()
+    Ns = [16, 16, 20, 24, 24, 28, 32, 32]
+    scenes = [synth.sphere_scene(Ns[k], 32 if k % 2 == 0 else 64, 0.5 + 0.02 * k, 0.02, 4000 + k)
+              for k in range(8)]
+    sizes = [(256, 256), (512, 512), (800, 800), (1920, 1080)]
+    rng = np.random.default_rng(44)
+    with kn.Context(0) as ctx:
+        sids = [ctx.scene_create(s, precisions=("bf16",)) for s in scenes]
+        del scenes
+        log("c4 scenes resident")
+        reqs = []
+        for i in range(24):
+            k = i % 8
+            v = synth.orbit_views(64, 4000 + k + 500)[int(rng.integers(0, 64))]
+            reqs.append((k, v, *sizes[(i // 8 + i) % 4]))
+        alone = []
+        for k, v, W, H in reqs:
+            out = ctx.alloc_frame(W, H)
+            ctx.render_into(sids[k], kn.make_camera(v, W, H, 256, 1e-4, "bf16"), out)
+            alone.append(out)
+        torch.cuda.synchronize()
+        log(f"c4: {len(reqs)} requests rendered alone")
+        ctx.serve_start(max_inflight=32, precision="bf16")
+        mixed, ids = [], []
+        for k, v, W, H in reqs:
+            out = ctx.alloc_frame(W, H)
+            for f in FIELDS:
+                out[f].fill_(7)
+            torch.cuda.synchronize()
+            ids.append(ctx.serve_submit(sids[k], kn.make_camera(v, W, H, 256, 1e-4, "bf16"), out))
+            mixed.append(out)
+        stats = [ctx.serve_poll(i, timeout_us=120_000_000) for i in ids]
+        log(f"c4 served; latencies ms: {[round(s['wall_ms'], 1) for s in stats]}")
+        for (k, v, W, H), a, m, st in zip(reqs, alone, mixed, stats):
+            assert st["rays"] == W * H
+            msg = _same(a, m)
+            assert msg is None, f"scene {k} {W}x{H}: {msg}"
+        ctx.serve_stop()
