@@ -589,3 +589,113 @@ void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, c
     if (hit) hit[q] = (uint8_t)h;
   }
 }
+
+/* ------------------------------------------------------------------------
+ * Point-query workloads built on the per-cell evaluation (Sec. 3.3: the
+ * cell MLPs are evaluated on per-cell batches of points).
+ * ------------------------------------------------------------------------ */
+
+/* SDF value, world-space gradient and feature of the global, piecewise
+ * KiloSDF at world point x: the MLP of the cell that contains x (cell map m
+ * of Sec. 3.1: floor of the box-relative position over the cell side,
+ * clamped to the grid), in that cell's local frame. */
+static void sdf_at_point(const kno_scene* s, const double x[3], double* d, double grad[3], double z[15]) {
+  int idx[3];
+  for (int a = 0; a < 3; ++a) {
+    int i = (int)floor((x[a] - s->bmin[a]) / cell_side(s, a));
+    idx[a] = i < 0 ? 0 : (i > s->N - 1 ? s->N - 1 : i);
+  }
+  double xl[3], y[16], gl[3];
+  local_coords(s, idx, x, xl);
+  kno_sdf_eval(s, cell_index(s, idx), xl, y, grad ? gl : NULL);
+  *d = y[0];
+  if (grad)
+    for (int a = 0; a < 3; ++a) grad[a] = gl[a] / (0.5 * cell_side(s, a));
+  if (z)
+    for (int i = 0; i < FEAT; ++i) z[i] = y[1 + i];
+}
+
+void kno_query(const kno_scene* s, const double* pts, int64_t n, double* d, double* grad, double* z,
+               int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+  for (int64_t q = 0; q < n; ++q)
+    sdf_at_point(s, pts + 3 * q, d + q, grad ? grad + 3 * q : NULL, z ? z + 15 * q : NULL);
+}
+
+/* Dense lattice sampling of the KiloSDF, the input of marching-cubes mesh
+ * extraction (Sec. 4.1 extracts meshes at resolution 512).  Lattice point
+ * (i, j, k), 0 <= i, j, k < R, lies at bmin + (bmax - bmin) (i, j, k) / (R - 1).
+ * Its cell along an axis is floor(i N / (R - 1)) in integer arithmetic,
+ * clamped to N - 1, so the last lattice plane (on the box face) belongs to
+ * the last cell and a lattice point on an inner cell face to the cell above
+ * it, as floor() of the exact position would give.  The point is evaluated
+ * with that cell's MLP in the cell's local frame.  `lin` lists flattened
+ * indices i + R (j + R k); outputs are per listed point. */
+void kno_grid_sample(const kno_scene* s, int R, const int64_t* lin, int64_t n, double* d, double* grad,
+                     double* z, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+  for (int64_t q = 0; q < n; ++q) {
+    const int64_t l = lin[q];
+    const int64_t ijk[3] = {l % R, (l / R) % R, l / ((int64_t)R * R)};
+    int idx[3];
+    double x[3];
+    for (int a = 0; a < 3; ++a) {
+      const int64_t c = ijk[a] * s->N / (R - 1);
+      idx[a] = (int)(c > s->N - 1 ? s->N - 1 : c);
+      x[a] = s->bmin[a] + (s->bmax[a] - s->bmin[a]) * (double)ijk[a] / (double)(R - 1);
+    }
+    double xl[3], y[16], gl[3];
+    local_coords(s, idx, x, xl);
+    kno_sdf_eval(s, cell_index(s, idx), xl, y, grad ? gl : NULL);
+    d[q] = y[0];
+    if (grad)
+      for (int a = 0; a < 3; ++a) grad[3 * q + a] = gl[a] / (0.5 * cell_side(s, a));
+    if (z)
+      for (int i = 0; i < FEAT; ++i) z[15 * q + i] = y[1 + i];
+  }
+}
+
+/* Eikonal term by central finite differences (Sec. 3.2, the eikonal loss;
+ * Sec. 3.3 explains that the gradient is taken by finite differences of the
+ * global piecewise SDF rather than by autodiff of single cell MLPs, which
+ * is what couples neighbouring cells at their seams).  For each point x:
+ * g_a = (d(x + delta e_a) - d(x - delta e_a)) / (2 delta), a = x, y, z, each
+ * of the six stencil values taken with the MLP of the cell that contains the
+ * stencil point; gnorm = |g|; the loss is the mean of (gnorm - 1)^2 over the
+ * points.  stencil (may be NULL) receives the six values per point in the
+ * order (+x, -x, +y, -y, +z, -z). */
+void kno_eikonal_fd(const kno_scene* s, const double* pts, int64_t n, double delta, double* gnorm,
+                    double* stencil, double* loss, int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+  for (int64_t q = 0; q < n; ++q) {
+    double g2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      double xp[3] = {pts[3 * q], pts[3 * q + 1], pts[3 * q + 2]};
+      double xm[3] = {pts[3 * q], pts[3 * q + 1], pts[3 * q + 2]};
+      xp[a] += delta;
+      xm[a] -= delta;
+      double dp, dm;
+      sdf_at_point(s, xp, &dp, NULL, NULL);
+      sdf_at_point(s, xm, &dm, NULL, NULL);
+      if (stencil) {
+        stencil[6 * q + 2 * a] = dp;
+        stencil[6 * q + 2 * a + 1] = dm;
+      }
+      const double ga = (dp - dm) / (2.0 * delta);
+      g2 += ga * ga;
+    }
+    gnorm[q] = sqrt(g2);
+  }
+  double acc = 0.0;
+  for (int64_t q = 0; q < n; ++q) acc += (gnorm[q] - 1.0) * (gnorm[q] - 1.0);
+  *loss = n > 0 ? acc / (double)n : 0.0;
+}

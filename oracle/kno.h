@@ -106,6 +106,16 @@ void kno_env_lookup(const kno_env* e, const double d[3], double rgb[3]);
 void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
                     int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit, int nthreads);
 
+/* point-query workloads (Sec. 3.3): the global piecewise SDF at world
+ * points, on a dense lattice (mesh extraction, Sec. 4.1) and the eikonal
+ * term by central finite differences (Sec. 3.2, 3.3) */
+void kno_query(const kno_scene* s, const double* pts, int64_t n, double* d, double* grad, double* z,
+               int nthreads);
+void kno_grid_sample(const kno_scene* s, int R, const int64_t* lin, int64_t n, double* d, double* grad,
+                     double* z, int nthreads);
+void kno_eikonal_fd(const kno_scene* s, const double* pts, int64_t n, double delta, double* gnorm,
+                    double* stencil, double* loss, int nthreads);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,6 +93,10 @@ def lib():
         L.kno_env_lookup.argtypes = [C.POINTER(_Env), dp, dp]
         L.kno_path_trace.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_PT), C.c_void_p,
                                      C.c_int64, dp, dp, dp, C.POINTER(C.c_uint8), C.c_int]
+        L.kno_query.argtypes = [C.POINTER(_Scene), dp, C.c_int64, dp, dp, dp, C.c_int]
+        L.kno_grid_sample.argtypes = [C.POINTER(_Scene), C.c_int, C.POINTER(C.c_int64), C.c_int64,
+                                      dp, dp, dp, C.c_int]
+        L.kno_eikonal_fd.argtypes = [C.POINTER(_Scene), dp, C.c_int64, C.c_double, dp, dp, dp, C.c_int]
         _lib = L
     return _lib
 
@@ -188,6 +192,52 @@ class OracleScene:
         return dict(rgb=rgb, depth=depth, normal=normal, hit=hit, steps=steps,
                     status=status, fmin=fmin)
 
+
+    def query(self, pts, grad: bool = False, feat: bool = False, nthreads: int = 0) -> dict:
+        """The global piecewise SDF at world points [n, 3]: d, and on request
+        the world gradient of the containing cell's MLP and the feature."""
+        p = np.ascontiguousarray(pts, np.float64).reshape(-1, 3)
+        n = p.shape[0]
+        d = np.zeros(n)
+        g = np.zeros((n, 3)) if grad else None
+        z = np.zeros((n, 15)) if feat else None
+        lib().kno_query(C.byref(self.c), _dp(p), n, _dp(d), _dp(g) if grad else None,
+                        _dp(z) if feat else None, nthreads)
+        out = dict(d=d)
+        if grad:
+            out["grad"] = g
+        if feat:
+            out["z"] = z
+        return out
+
+    def grid_sample(self, R: int, lin, grad: bool = False, feat: bool = False, nthreads: int = 0) -> dict:
+        """The SDF at lattice points (flattened indices i + R (j + R k)) of
+        the R^3 lattice spanning the box, corners included."""
+        lin = np.ascontiguousarray(lin, np.int64).ravel()
+        n = lin.size
+        d = np.zeros(n)
+        g = np.zeros((n, 3)) if grad else None
+        z = np.zeros((n, 15)) if feat else None
+        lib().kno_grid_sample(C.byref(self.c), int(R), lin.ctypes.data_as(C.POINTER(C.c_int64)), n, _dp(d),
+                              _dp(g) if grad else None, _dp(z) if feat else None, nthreads)
+        out = dict(d=d)
+        if grad:
+            out["grad"] = g
+        if feat:
+            out["z"] = z
+        return out
+
+    def eikonal_fd(self, pts, delta: float, nthreads: int = 0) -> dict:
+        """Central-difference gradient norms of the global SDF at points
+        [n, 3], the six stencil values per point (+x, -x, +y, -y, +z, -z)
+        and the mean squared eikonal residual."""
+        p = np.ascontiguousarray(pts, np.float64).reshape(-1, 3)
+        n = p.shape[0]
+        gn = np.zeros(n)
+        st = np.zeros((n, 6))
+        loss = C.c_double()
+        lib().kno_eikonal_fd(C.byref(self.c), _dp(p), n, float(delta), _dp(gn), _dp(st), C.byref(loss), nthreads)
+        return dict(gnorm=gn, stencil=st, loss=loss.value)
 
     def path_trace(self, view, width: int, height: int, max_steps: int, eps: float, spp: int,
                    bounces: int, seed: int, env=None, pixels=None, nthreads: int = 0) -> dict:
