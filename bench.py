@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--no-pathtrace", action="store_true",
                     help="skip the path-tracing workload (32^3, 4 spp, 3 bounces, FP8 vs BF16)")
+    ap.add_argument("--no-query", action="store_true",
+                    help="skip the point-query workloads (512^3 lattice, eikonal term, random points)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="after timing, run one plain float32 device copy of this many MiB "
                          "(a kernel of known HBM traffic, used to scale hardware byte counters)")
@@ -303,6 +305,58 @@ def pathtrace_bench(torch, frames: int = 3) -> dict:
     return res
 
 
+def query_bench(torch, reps: int = 3) -> dict:
+    """Point-query workloads on the C3 scene (16^3, H=64): dense lattice
+    sampling at 512^3 (the mesh-extraction input; 134 M points) in float32,
+    bfloat16 and fp8, and with world gradients (float32); the finite-
+    difference eikonal term over the paper's M = 16384 uniform points
+    (6 stencil evaluations each, delta 1e-3); random points through the
+    binned query (1 M points).  Times: HIP events on the call's stream."""
+    from paper_2206_10885_amd import kn, synth
+    sc = synth.config_scene("c3")
+    ctx = kn.Context(0)
+    sid = ctx.scene_create(sc, precisions=("bf16", "fp8"))
+    R = 512
+    d = torch.empty((R, R, R), dtype=torch.float32, device="cuda")
+    g = torch.empty((R, R, R, 3), dtype=torch.float32, device="cuda")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            ev0.record()
+            fn()
+            ev1.record()
+            torch.cuda.synchronize()
+            ms.append(ev0.elapsed_time(ev1))
+        return min(ms)
+
+    res = {}
+    for prec in ("fp32", "bf16", "fp8"):
+        ms = timed(lambda: ctx.grid_sample(sid, R, prec, out=dict(d=d)))
+        res[f"grid512_{prec}"] = dict(ms=ms, points_per_s=R ** 3 / (ms / 1e3))
+        print(f"query: grid 512 {prec} done", file=sys.stderr, flush=True)
+    ms = timed(lambda: ctx.grid_sample(sid, R, "fp32", out=dict(d=d, grad=g)))
+    res["grid512_fp32_grad"] = dict(ms=ms, points_per_s=R ** 3 / (ms / 1e3))
+    del d, g
+    rng = np.random.default_rng(4242)
+    pts = torch.tensor(rng.uniform(-1, 1, (16384, 3)).astype(np.float32), device="cuda")
+    for prec in ("fp32", "bf16"):
+        ms = timed(lambda: ctx.eikonal_fd(sid, pts, 1e-3, prec))
+        res[f"eikonal_16384_{prec}"] = dict(ms=ms, points_per_s=16384 / (ms / 1e3))
+    pts = torch.tensor(rng.uniform(-1, 1, (1 << 20, 3)).astype(np.float32), device="cuda")
+    for prec in ("fp32", "bf16"):
+        ms = timed(lambda: ctx.query(sid, pts, prec))
+        res[f"query_1M_{prec}"] = dict(ms=ms, points_per_s=(1 << 20) / (ms / 1e3))
+    ctx.close()
+    res["workload"] = ("C3 scene (16^3, SDF 39->2x64->16): 512^3 lattice (kn_grid_sample); eikonal term by "
+                       "central differences at 16384 uniform points, delta 1e-3 (kn_eikonal_fd); "
+                       "2^20 uniform random points (kn_query, d only)")
+    print("query: done", file=sys.stderr, flush=True)
+    return res
+
+
 def variant(ctx, sid, views, W, H, S, eps, prec, split, out, steps, warmup, torch, kn):
     cams = [kn.make_camera(v, W, H, S, eps, prec, split_shading=split) for v in views]
     r = timed_frames(ctx, sid, cams, out, steps, warmup, torch)
@@ -438,6 +492,8 @@ def main():
         line["pathtrace"] = pathtrace_bench(torch)
     if not args.no_serve:
         line["serving"] = serve_bench(args.serve_requests, torch)
+    if not args.no_query:
+        line["point_query"] = query_bench(torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(scene, views, W, H, S, eps, args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -152,6 +152,19 @@ typedef struct {
  * variant; the default is float32.  Ignored for float32 marches; refused by
  * the serving loop. */
 #define KN_CAMERA_SPLIT_BF16_SHADING 1u
+/* kn_camera.flags: Hart's unclamped sphere-tracing steps (Sec. 3.4.1 traces
+ * the SDF inside the bounding interval; the step rule at cell faces is a
+ * reading).  By default a step never crosses the current cell's exit plane:
+ * it stops there and the ray continues in the face neighbour, so every cell
+ * the ray crosses is evaluated and each MLP is used only inside its own
+ * cell.  With this flag t always advances by the full SDF value; a step that
+ * leaves the cell continues in the cell that contains the new point (any
+ * cell, so cells inside a step are skipped without an evaluation), and the
+ * hit cell's entry parameter is the t of its first evaluation.  Fewer
+ * evaluations on fields that are coherent across cells; results differ from
+ * the default where the per-cell fields disagree at seams.  kn_render only;
+ * refused by the serving loop. */
+#define KN_CAMERA_UNCLAMPED_STEPS 2u
 /* Path tracing (bounces >= 1; Sec. 3.4.1: Lambertian surfaces, the color
  * MLP output is the albedo).  Each pixel traces spp paths; sample s of pixel
  * p is jittered inside the pixel by Philox-4x32-10 keyed by `seed` with
@@ -235,8 +248,8 @@ typedef struct {
 kn_status kn_render(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const kn_frame* frame,
                     kn_stats* stats_opt);
 
-/* Batched point query (the paper's "n MLPs on n batches of m points",
- * Sec. 3.3): for each world point x (DEVICE float [n][3]) evaluates the
+/* Batched point query (per-cell MLPs evaluated on per-cell batches of
+ * points, Sec. 3.3): for each world point x (DEVICE float [n][3]) evaluates the
  * SDF MLP of the cell containing x (points outside the box are clamped to
  * the nearest cell): d (DEVICE float [n]), and optionally the world-space
  * gradient of d (DEVICE float [n][3]) and the feature z (DEVICE float
@@ -263,6 +276,42 @@ kn_status kn_query(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const
  * overlaps on the same device would race.  Errors as kn_query. */
 kn_status kn_query_noalloc(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points,
                            uint64_t n, float* d_out, float* grad_out, float* z_out, void* hip_stream);
+
+/* Dense lattice sampling of the SDF, the input of marching-cubes mesh
+ * extraction (Sec. 4.1 extracts meshes on a 512^3 lattice).  The lattice has
+ * R points per axis spanning the scene box: point (i, j, k) lies at
+ * bbox_min + (bbox_max - bbox_min) (i, j, k) / (R - 1).  Along each axis its
+ * cell is floor(i N / (R - 1)) in integer arithmetic, clamped to N - 1, so a
+ * point on an inner cell face belongs to the cell above it and the last
+ * lattice plane to the last cell (the cell map of Sec. 3.1 at the exact
+ * position); it is evaluated with that cell's SDF MLP.
+ * d_out: DEVICE float [R^3], caller-owned, index i + R (j + R k).
+ * grad_out: NULL, or DEVICE float [R^3][3] for the world-space gradient of d;
+ * gradients need precision KN_FP32 (the float32 weights).
+ * 2 <= R <= 4096, with at most 2^31 lattice points in a cell.  Runs on `hip_stream` (NULL = ctx stream) and returns when
+ * done.  Errors: KN_E_INVALID (outputs untouched), KN_E_NOT_FOUND,
+ * KN_E_DEVICE. */
+kn_status kn_grid_sample(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, uint32_t R, float* d_out,
+                         float* grad_out, void* hip_stream);
+
+/* Eikonal term by central finite differences of the global, piecewise SDF
+ * (Sec. 3.2 defines the eikonal loss as the mean of (|grad d| - 1)^2 over
+ * sampled points; Sec. 3.3 takes the gradient by finite differences, each
+ * stencil value from the MLP of the cell containing the stencil point, which
+ * couples neighbouring cells at their seams).  For each point x (DEVICE float
+ * [n][3]): the six stencil points x +- delta e_a are formed in float32 (order
+ * +x, -x, +y, -y, +z, -z) and evaluated as by kn_query with `precision`;
+ * g_a = (d(x + delta e_a) - d(x - delta e_a)) / (2 delta) and
+ * gnorm_out[q] = |g| (DEVICE float [n]).  stencil_out: NULL, or DEVICE float
+ * [n][6] receiving the six stencil values.  loss_out: NULL, or a DEVICE
+ * double receiving the mean of (gnorm - 1)^2 over the n points, summed in
+ * double in a fixed order (the same on every run).  delta > 0 in world units;
+ * n <= 2^28 / 6.  The context's work buffers grow to about 750 bytes per
+ * point and are kept between calls (counted against the HBM budget).
+ * Returns when done on `hip_stream`.  Errors: KN_E_INVALID, KN_E_NOT_FOUND, KN_E_NOMEM,
+ * KN_E_DEVICE. */
+kn_status kn_eikonal_fd(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points, uint64_t n,
+                        float delta, float* gnorm_out, float* stencil_out, double* loss_out, void* hip_stream);
 
 /* ---------------------------------------------------------------------
  * Serving: a loop that keeps scenes resident and renders queued requests

@@ -295,6 +295,18 @@ int kno_cells_along_ray(const kno_scene* s, const double o[3], const double d[3]
  * ray leaves the grid or the box interval, or after max_steps evaluations. */
 void kno_trace(const kno_scene* s, const double o[3], const double d[3], int max_steps,
                double eps, kno_trace_result* r) {
+  kno_trace_mode(s, o, d, max_steps, eps, KNO_STEP_CLAMPED, r);
+}
+
+/* The same march with a choice of step rule.  KNO_STEP_UNCLAMPED is Hart's
+ * rule without the cell-boundary clamp: t always advances by the SDF value;
+ * when the new point lies past the current cell's exit plane the ray goes on
+ * in the cell that contains the new point (cell map m of Sec. 3.1), which
+ * need not be a neighbour, so cells inside a step are never evaluated.  The
+ * cell's entry parameter (the refinement's lower bound) is the t of its
+ * first evaluation. */
+void kno_trace_mode(const kno_scene* s, const double o[3], const double d[3], int max_steps,
+                    double eps, int step_mode, kno_trace_result* r) {
   memset(r, 0, sizeof(*r));
   r->fmin = INFINITY;
   double tn, tf;
@@ -325,6 +337,15 @@ void kno_trace(const kno_scene* s, const double o[3], const double d[3], int max
     double t_exit = fmax(t, cell_exit(s, o, d, idx, &ax));
     if (t + f < t_exit) {
       t = t + f;
+    } else if (step_mode == KNO_STEP_UNCLAMPED) {
+      t = t + f;
+      t_entry = t;
+      if (t > tf) {
+        r->status = KNO_EXIT_MISS;
+        r->t = t;
+        return;
+      }
+      cell_at(s, o, d, t, idx);
     } else {
       t = t_exit;
       idx[ax] += d[ax] > 0 ? 1 : -1;
@@ -400,7 +421,7 @@ void kno_render(const kno_scene* s, const kno_camera* c, const int64_t* pixels, 
     double o[3], d[3];
     kno_camera_ray(c, row, colm, 0.5, 0.5, o, d);
     kno_trace_result r;
-    kno_trace(s, o, d, c->max_steps, c->eps, &r);
+    kno_trace_mode(s, o, d, c->max_steps, c->eps, c->step_mode, &r);
     double dep = 0, n[3] = {0, 0, 0}, col[3], z[15];
     if (r.status == KNO_HIT) {
       kno_shade(s, o, d, &r, &dep, n, col, z);
@@ -537,7 +558,7 @@ static void trace_path(const kno_scene* s, const kno_camera* c, const kno_pt* pt
   L[0] = L[1] = L[2] = 0.0;
   for (int k = 0;; ++k) {
     kno_trace_result r;
-    kno_trace(s, o, d, c->max_steps, c->eps, &r);
+    kno_trace_mode(s, o, d, c->max_steps, c->eps, c->step_mode, &r);
     if (k == 0 && first) *first = r;
     if (r.status != KNO_HIT) {
       double env[3];

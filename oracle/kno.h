@@ -48,7 +48,12 @@ typedef struct {
   int32_t max_steps;      /* S: SDF evaluations allowed per ray */
   double eps;             /* hit threshold */
   double background[3];   /* rgb of rays that miss */
+  int32_t step_mode;      /* KNO_STEP_CLAMPED or KNO_STEP_UNCLAMPED */
 } kno_camera;
+
+/* sphere-tracing step rule: clamp each step at the cell's exit plane and
+ * move to the face neighbour, or take Hart's full step across cells */
+enum { KNO_STEP_CLAMPED = 0, KNO_STEP_UNCLAMPED = 1 };
 
 /* march outcome */
 enum { KNO_BOX_MISS = 0, KNO_HIT = 1, KNO_EXIT_MISS = 2, KNO_BUDGET_MISS = 3 };
@@ -79,6 +84,8 @@ int kno_cells_along_ray(const kno_scene* s, const double o[3], const double d[3]
                         int32_t* cells, double* t_enter);
 void kno_trace(const kno_scene* s, const double o[3], const double d[3], int max_steps,
                double eps, kno_trace_result* r);
+void kno_trace_mode(const kno_scene* s, const double o[3], const double d[3], int max_steps,
+                    double eps, int step_mode, kno_trace_result* r);
 void kno_shade(const kno_scene* s, const double o[3], const double d[3],
                const kno_trace_result* r, double* depth, double normal[3], double rgb[3],
                double z[15]);

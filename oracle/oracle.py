@@ -39,7 +39,10 @@ class _Scene(C.Structure):
 class _Camera(C.Structure):
     _fields_ = [("eye", C.c_double * 3), ("look_at", C.c_double * 3), ("up", C.c_double * 3),
                 ("tan_half_diag", C.c_double), ("width", C.c_int32), ("height", C.c_int32),
-                ("max_steps", C.c_int32), ("eps", C.c_double), ("background", C.c_double * 3)]
+                ("max_steps", C.c_int32), ("eps", C.c_double), ("background", C.c_double * 3),
+                ("step_mode", C.c_int32)]
+
+STEP_CLAMPED, STEP_UNCLAMPED = 0, 1
 
 
 class _Trace(C.Structure):
@@ -82,6 +85,8 @@ def lib():
         L.kno_cells_along_ray.restype = C.c_int
         L.kno_trace.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int, C.c_double,
                                 C.POINTER(_Trace)]
+        L.kno_trace_mode.argtypes = [C.POINTER(_Scene), dp, dp, C.c_int, C.c_double, C.c_int,
+                                     C.POINTER(_Trace)]
         L.kno_shade.argtypes = [C.POINTER(_Scene), dp, dp, C.POINTER(_Trace), dp, dp, dp, dp]
         L.kno_render.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.c_void_p, C.c_int64,
                                  dp, dp, dp, C.POINTER(C.c_uint8), C.POINTER(C.c_int32),
@@ -155,9 +160,10 @@ class OracleScene:
                                       cells.ctypes.data_as(C.POINTER(C.c_int32)), _dp(tin))
         return cells[:n], tin[:n]
 
-    def trace(self, o, d, max_steps: int, eps: float) -> dict:
+    def trace(self, o, d, max_steps: int, eps: float, unclamped: bool = False) -> dict:
         r = _Trace()
-        lib().kno_trace(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), max_steps, eps, C.byref(r))
+        lib().kno_trace_mode(C.byref(self.c), _dp(_vec(o)), _dp(_vec(d)), max_steps, eps,
+                             STEP_UNCLAMPED if unclamped else STEP_CLAMPED, C.byref(r))
         return dict(status=r.status, steps=r.steps, cell=tuple(r.cell), t=r.t,
                     t_entry=r.t_entry, fmin=r.fmin, _raw=r)
 
@@ -169,8 +175,8 @@ class OracleScene:
         return dict(depth=depth.value, normal=n, rgb=rgb, z=z)
 
     def render(self, view, width: int, height: int, max_steps: int, eps: float,
-               pixels=None, background=(0.0, 0.0, 0.0), nthreads: int = 0) -> dict:
-        cam = make_camera(view, width, height, max_steps, eps, background)
+               pixels=None, background=(0.0, 0.0, 0.0), nthreads: int = 0, unclamped: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, background, unclamped)
         if pixels is None:
             npix = width * height
             pix_ptr = None
@@ -240,10 +246,11 @@ class OracleScene:
         return dict(gnorm=gn, stencil=st, loss=loss.value)
 
     def path_trace(self, view, width: int, height: int, max_steps: int, eps: float, spp: int,
-                   bounces: int, seed: int, env=None, pixels=None, nthreads: int = 0) -> dict:
+                   bounces: int, seed: int, env=None, pixels=None, nthreads: int = 0,
+                   unclamped: bool = False) -> dict:
         """Path-traced pixels (mean radiance over spp) plus the primary
         segment's depth, normal and hit of sample 0."""
-        cam = make_camera(view, width, height, max_steps, eps)
+        cam = make_camera(view, width, height, max_steps, eps, unclamped=unclamped)
         envp = _make_env(env)
         pt = _PT(spp, bounces, seed, envp)
         if pixels is None:
@@ -304,10 +311,12 @@ def env_lookup(env, d) -> np.ndarray:
     return out
 
 
-def make_camera(view, width, height, max_steps, eps, background=(0.0, 0.0, 0.0)) -> _Camera:
+def make_camera(view, width, height, max_steps, eps, background=(0.0, 0.0, 0.0),
+                unclamped: bool = False) -> _Camera:
     return _Camera((C.c_double * 3)(*view.eye), (C.c_double * 3)(*view.look_at),
                    (C.c_double * 3)(*view.up), float(view.tan_half_diag), width, height,
-                   max_steps, eps, (C.c_double * 3)(*background))
+                   max_steps, eps, (C.c_double * 3)(*background),
+                   STEP_UNCLAMPED if unclamped else STEP_CLAMPED)
 
 
 def encode(p, L: int) -> np.ndarray:

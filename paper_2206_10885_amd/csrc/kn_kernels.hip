@@ -1065,7 +1065,12 @@ __device__ __forceinline__ float cell_exit(const SceneGeom& sg, const CellBox& c
 }
 
 // in-cell status of a staged ray
-enum : uint32_t { kStay = 0, kOutHit = 1, kOutNext = 2, kOutExit = 3, kOutBudget = 4 };
+// (kOutJump: an unclamped step left the cell; the ray goes on in the cell
+// that contains its new point)
+enum : uint32_t { kStay = 0, kOutHit = 1, kOutNext = 2, kOutExit = 3, kOutBudget = 4, kOutJump = 5 };
+// the staged ray word: steps (bits 0-9), exit axis (10-11), status (12-14),
+// the slot's step budget (16-25) and unclamped-step flag (26)
+constexpr uint32_t kStUnclamped = 1u << 26;
 
 // ---------------------------------------------------------------------------
 // the march: one workgroup (4 waves) per chunk of <= kChunk rays of one cell
@@ -1174,7 +1179,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   // that thread 0 can clear the next pass's one during a pass: a slot's last
   // reader is always behind an earlier barrier)
   __shared__ uint32_t s_nact[3];
-  __shared__ uint32_t s_face[7], s_foff[7];
+  __shared__ uint32_t s_face[7], s_foff[7], s_njump, s_jbase;
   __shared__ uint32_t s_nhit, s_evals, s_tiles;
   __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
   // the pool's scene table and each request slot's eps and step budget,
@@ -1194,7 +1199,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   if (tid < kMaxSlots) {
     s_miss[tid] = 0u;
     s_qeps[tid] = a.tabs.reqs[tid].eps;
-    s_qmst[tid] = a.tabs.reqs[tid].max_steps;
+    s_qmst[tid] = a.tabs.reqs[tid].max_steps | (a.tabs.reqs[tid].unclamped ? (kStUnclamped >> 16) : 0u);
   }
   {
     static_assert(sizeof(SceneEnt) % 4 == 0, "scene entries are copied as words");
@@ -1216,6 +1221,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     s_tiles = 0u;
     s_jn[4] = 0u;
     for (int f = 0; f < 7; ++f) s_face[f] = 0u;
+    s_njump = 0u;
   };
   if (tid == 0) {
     G = grab_init(a.grab, *a.n_chunks);
@@ -1349,13 +1355,19 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
               const float te = fmaxf(tt, s_ce[r_]);
               if (tt + f[u] < te) {
                 tt = tt + f[u];
+              } else if (stw & kStUnclamped) {
+                // Hart's full step: the ray goes on in the cell of its new point
+                tt = tt + f[u];
+                status = tt > s_tf[r_] ? kOutExit : kOutJump;
               } else {
                 tt = te;
                 const int sgn = d[u][eax] > 0.0f ? 1 : -1;
                 const int ni = (eax == 0 ? cb.ix : (eax == 1 ? cb.iy : cb.iz)) + sgn;
                 status = (ni < 0 || ni >= N || tt > s_tf[r_]) ? kOutExit : kOutNext;
               }
-              if ((status == kStay || status == kOutNext) && steps >= (stw >> 16)) status = kOutBudget;
+              if ((status == kStay || status == kOutNext || status == kOutJump) &&
+                  steps >= ((stw >> 16) & 1023u))
+                status = kOutBudget;
             }
             s_t[r_] = tt;
             s_st[r_] = steps | (eax << 10) | (status << 12) | (stw & 0xFFFF0000u);
@@ -1406,7 +1418,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
     // results: misses written out, hits appended to the hit list, rays for
     // the next round into this chunk's range of U, grouped by exit face
     // (face 6: still in this cell after max_passes)
-    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0, slot = 0;
+    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0, slot = 0, dest = 0;
     bool miss = false;
     float t = 0.0f, t_entry = 0.0f;
     if ((uint32_t)tid < count) {
@@ -1415,7 +1427,18 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       steps = stw & 1023u;
       t = s_t[tid];
       t_entry = s_te[tid];
-      if (status == kOutNext || status == kStay) {
+      if (status == kOutJump) {
+        // the cell containing the new point (cell map of Sec. 3.1, clamped)
+        int idx[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float x = fmaf(t, s_d[k * kChunk + tid], s_o[k * kChunk + tid]);
+          idx[k] = min(max((int)floorf((x - sg.bmin[k]) * sg.inv_side[k]), 0), N - 1);
+        }
+        dest = sg.cell_base + (uint32_t)(idx[0] + N * (idx[1] + N * idx[2]));
+        t_entry = t;
+        rank = atomicAdd(&s_njump, 1u);
+      } else if (status == kOutNext || status == kStay) {
         const uint32_t eax = (stw >> 10) & 3u;
         face = status == kStay ? 6u : 2u * eax + (s_d[eax * kChunk + tid] > 0.0f ? 1u : 0u);
         if (status == kOutNext) t_entry = t;
@@ -1453,8 +1476,11 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
     }
     if (miss) atomicAdd(&s_miss[slot], 1u);
+    // jumped rays are counted in their new cells for the next round
+    atomic_count_grouped(a.counts_next, a.cs, dest, status == kOutJump && (uint32_t)tid < count);
     __syncthreads();
     if (tid == 0) {
+      if (s_njump) s_jbase = atomicAdd(a.n_jump, s_njump);
       uint32_t off = 0;
       for (int f = 0; f < 7; ++f) {
         s_foff[f] = off;
@@ -1480,6 +1506,8 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       if (status == kOutNext || status == kStay)
         a.U[start + s_foff[face] + rank] =
             RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
+      else if (status == kOutJump)
+        a.jump[s_jbase + rank] = RayRec{t, t_entry, dest | (steps << kCellBits), s_rid[tid]};
     }
     if (tid == 0) {   // the next work item, and its counters cleared
       for (int i = 0; i < 6; ++i) s_job[i] = s_jn[i];
@@ -2024,6 +2052,190 @@ __global__ __launch_bounds__(256) void k_query_full(QueryArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// dense lattice sampling (mesh-extraction input, Sec. 4.1): the R^3 lattice
+// spanning the box is already grouped by cell, so it needs no binning.  A
+// work item is (cell, a 256-point part of the cell's lattice points); each
+// persistent workgroup takes a contiguous range of items, so it stages a
+// cell's weights once for all of that cell's items in its range.
+// ---------------------------------------------------------------------------
+// first lattice index along an axis whose cell floor(i N / (R - 1)) is c
+__device__ __forceinline__ uint32_t grid_lo(uint32_t c, uint32_t N, uint32_t R) {
+  return (c * (R - 1u) + N - 1u) / N;
+}
+// one past the last (the last cell also takes the lattice plane on the box face)
+__device__ __forceinline__ uint32_t grid_hi(uint32_t c, uint32_t N, uint32_t R) {
+  return c + 1u >= N ? R : grid_lo(c + 1u, N, R);
+}
+
+struct GridItem {
+  uint32_t lc, q0, cnt, nx, nxy;
+  uint32_t lo[3];
+};
+
+__device__ __forceinline__ GridItem grid_item(const GridArgs& a, uint64_t it, const CellBox& cb, uint32_t lc) {
+  GridItem gi;
+  const uint32_t N = (uint32_t)a.sg.N;
+  const uint32_t idx[3] = {(uint32_t)cb.ix, (uint32_t)cb.iy, (uint32_t)cb.iz};
+  uint32_t n[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    gi.lo[k] = grid_lo(idx[k], N, a.R);
+    n[k] = grid_hi(idx[k], N, a.R) - gi.lo[k];
+  }
+  gi.lc = lc;
+  gi.q0 = (uint32_t)(it % a.K) * 256u;
+  gi.nx = n[0];
+  gi.nxy = n[0] * n[1];
+  gi.cnt = gi.nxy * n[2];
+  return gi;
+}
+
+// lattice point q of the item's cell: its flat output index and local
+// coordinates x_l = (2 N i - (2 c + 1)(R - 1)) / (R - 1) per axis (the box
+// cancels); the numerator is an exact integer, so x_l is rounded once
+__device__ __forceinline__ uint64_t grid_point(const GridArgs& a, const GridItem& gi, const CellBox& cb, uint32_t q,
+                                               float xl[3]) {
+  const uint32_t c = q / gi.nxy, r = q - c * gi.nxy, b = r / gi.nx, i = r - b * gi.nx;
+  const uint32_t ijk[3] = {gi.lo[0] + i, gi.lo[1] + b, gi.lo[2] + c};
+  const int idx[3] = {cb.ix, cb.iy, cb.iz};
+  const int N = a.sg.N, rm1 = (int)a.R - 1;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) xl[k] = (float)(2 * N * (int)ijk[k] - (2 * idx[k] + 1) * rm1) / a.rm1;
+  return (uint64_t)ijk[0] + (uint64_t)a.R * ((uint64_t)ijk[1] + (uint64_t)a.R * (uint64_t)ijk[2]);
+}
+
+template <int H, int P>
+__global__ __launch_bounds__(256) void k_grid_d(GridArgs a) {
+  extern __shared__ __align__(16) float s_block[];
+  const int lane = lane_id(), g = lane >> 4, p = lane & 15, wave = threadIdx.x >> 6;
+  const PeLane pl = make_pe_lane(g);
+  const uint32_t N = (uint32_t)a.sg.N;
+  const uint64_t T = (uint64_t)N * N * N * a.K;
+  const uint64_t it0 = T * blockIdx.x / gridDim.x, it1 = T * (blockIdx.x + 1u) / gridDim.x;
+  uint32_t loaded = 0xFFFFFFFFu;
+  for (uint64_t it = it0; it < it1; ++it) {
+    const uint32_t lc = (uint32_t)(it / a.K);
+    const CellBox cb = cell_box(a.sg, lc);
+    const GridItem gi = grid_item(a, it, cb, lc);
+    if (gi.q0 >= gi.cnt) continue;   // the cell has fewer parts (uniform)
+    if (lc != loaded) {
+      __syncthreads();   // every wave is done with the previous cell's block
+      stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_wait();
+      __syncthreads();
+      loaded = lc;
+    }
+    for (uint32_t t = (uint32_t)wave; t < 16u; t += 4u) {
+      const uint32_t q = gi.q0 + 16u * t + (uint32_t)p;
+      const bool valid = q < gi.cnt;
+      float xl[3] = {0.0f, 0.0f, 0.0f};
+      uint64_t o = 0;
+      if (valid) o = grid_point(a, gi, cb, q, xl);
+      float v[kPeSlots];
+      pe_values(pl, xl[0], xl[1], xl[2], v);
+      const float f = march_eval<H, P>(s_block, lane, g, v, a.spk);
+      if (valid && g == 0) a.d_out[o] = f;
+    }
+  }
+}
+
+// value and world gradient (float32 shading block, forward mode: 4 points x
+// 4 columns per tile)
+template <int H>
+__global__ __launch_bounds__(256) void k_grid_full(GridArgs a) {
+  extern __shared__ __align__(16) float s_block[];
+  const int lane = lane_id(), g = lane >> 4, col = lane & 15, h = col >> 2, s = col & 3;
+  const int wave = threadIdx.x >> 6;
+  const PeLane pl = make_pe_lane(g);
+  const uint32_t N = (uint32_t)a.sg.N;
+  const uint64_t T = (uint64_t)N * N * N * a.K;
+  const uint64_t it0 = T * blockIdx.x / gridDim.x, it1 = T * (blockIdx.x + 1u) / gridDim.x;
+  uint32_t loaded = 0xFFFFFFFFu;
+  for (uint64_t it = it0; it < it1; ++it) {
+    const uint32_t lc = (uint32_t)(it / a.K);
+    const CellBox cb = cell_box(a.sg, lc);
+    const GridItem gi = grid_item(a, it, cb, lc);
+    if (gi.q0 >= gi.cnt) continue;
+    if (lc != loaded) {
+      __syncthreads();
+      stage_block(s_block, a.blocks + (size_t)lc * a.block_words, a.block_words);
+      stage_wait();
+      __syncthreads();
+      loaded = lc;
+    }
+    for (uint32_t t = (uint32_t)wave; t < 64u; t += 4u) {
+      const uint32_t q = gi.q0 + 4u * t + (uint32_t)h;
+      const bool valid = q < gi.cnt;
+      float xl[3] = {0.0f, 0.0f, 0.0f};
+      uint64_t o = 0;
+      if (valid) o = grid_point(a, gi, cb, q, xl);
+      float v[kPeSlots];
+      pe_values_tangent(pl, s, s ? a.sg.inv_half[s - 1] : 0.0f, xl[0], xl[1], xl[2], v);
+      const f32x4 y = sdf_full<H>(s_block, lane, g, s == 0, v, a.spk);
+      if (valid && g == 0) {
+        if (s == 0) a.d_out[o] = y[0];
+        else if (a.grad_out) a.grad_out[3u * o + (uint32_t)(s - 1)] = y[0];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// eikonal term by central differences (Sec. 3.2, Sec. 3.3): the six stencil
+// points of each point, then (after a point query of the stencil) the
+// gradient norms and the mean squared residual
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_eik_points(EikArgs a) {
+  const uint64_t i = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  if (i >= 6u * a.n) return;
+  const uint64_t q = i / 6u;
+  const uint32_t s = (uint32_t)(i - 6u * q), ax = s >> 1;
+  float x[3] = {a.pts[3u * q], a.pts[3u * q + 1u], a.pts[3u * q + 2u]};
+  x[ax] = (s & 1u) ? x[ax] - a.delta : x[ax] + a.delta;   // order +x, -x, +y, -y, +z, -z
+#pragma unroll
+  for (int k = 0; k < 3; ++k) a.stencil_pts[3u * i + k] = x[k];
+}
+
+__global__ __launch_bounds__(256) void k_eik_combine(EikArgs a) {
+  __shared__ double s_sum[256];
+  const uint64_t q = (uint64_t)blockIdx.x * 256u + threadIdx.x;
+  double r = 0.0;
+  if (q < a.n) {
+    float g2 = 0.0f;
+#pragma unroll
+    for (int ax = 0; ax < 3; ++ax) {
+      const float ga = (a.stencil[6u * q + 2u * ax] - a.stencil[6u * q + 2u * ax + 1u]) / (2.0f * a.delta);
+      g2 = fmaf(ga, ga, g2);
+    }
+    const float gn = sqrtf(g2);
+    a.gnorm[q] = gn;
+    r = (double)(gn - 1.0f) * (double)(gn - 1.0f);
+  }
+  s_sum[threadIdx.x] = r;
+  __syncthreads();
+  for (uint32_t w = 128u; w; w >>= 1) {
+    if (threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = s_sum[0];
+}
+
+// one workgroup: the partial sums in a fixed order, so the loss is the same
+// on every run
+__global__ __launch_bounds__(256) void k_eik_loss(EikArgs a, uint32_t nparts) {
+  __shared__ double s_sum[256];
+  double acc = 0.0;
+  for (uint32_t i = threadIdx.x; i < nparts; i += 256u) acc += a.partial[i];
+  s_sum[threadIdx.x] = acc;
+  __syncthreads();
+  for (uint32_t w = 128u; w; w >>= 1) {
+    if (threadIdx.x < w) s_sum[threadIdx.x] += s_sum[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && a.loss) a.loss[0] = s_sum[0] / (double)a.n;
+}
+
+// ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st) {
@@ -2166,6 +2378,44 @@ hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream
   if (H == 32) hipLaunchKernelGGL(k_query_full<32>, dim3(grid), dim3(256), lds, st, a);
   else if (H == 64) hipLaunchKernelGGL(k_query_full<64>, dim3(grid), dim3(256), lds, st, a);
   else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <int H>
+static hipError_t grid_d_h(const GridArgs& a, int prec, size_t lds, uint32_t grid, hipStream_t st) {
+  if (prec == kPrecF32) hipLaunchKernelGGL((k_grid_d<H, kPrecF32>), dim3(grid), dim3(256), lds, st, a);
+  else if (prec == kPrecBf16) hipLaunchKernelGGL((k_grid_d<H, kPrecBf16>), dim3(grid), dim3(256), lds, st, a);
+  else if (prec == kPrecFp8) hipLaunchKernelGGL((k_grid_d<H, kPrecFp8>), dim3(grid), dim3(256), lds, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_grid_d(const GridArgs& a, int H, int prec, uint32_t grid, hipStream_t st) {
+  if (a.R < 2 || a.K == 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)a.block_words * 4u;
+  if (H == 32) return grid_d_h<32>(a, prec, lds, grid, st);
+  if (H == 64) return grid_d_h<64>(a, prec, lds, grid, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_grid_full(const GridArgs& a, int H, uint32_t grid, hipStream_t st) {
+  if (a.R < 2 || a.K == 0) return hipErrorInvalidValue;
+  const size_t lds = (size_t)a.block_words * 4u;
+  if (H == 32) hipLaunchKernelGGL(k_grid_full<32>, dim3(grid), dim3(256), lds, st, a);
+  else if (H == 64) hipLaunchKernelGGL(k_grid_full<64>, dim3(grid), dim3(256), lds, st, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_eik_points(const EikArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_eik_points, dim3((uint32_t)((6u * a.n + 255u) / 256u)), dim3(256), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_eik_combine(const EikArgs& a, hipStream_t st) {
+  const uint32_t nb = (uint32_t)((a.n + 255u) / 256u);
+  hipLaunchKernelGGL(k_eik_combine, dim3(nb), dim3(256), 0, st, a);
+  hipLaunchKernelGGL(k_eik_loss, dim3(1), dim3(256), 0, st, a, nb);
   return hipGetLastError();
 }
 

@@ -39,6 +39,7 @@ struct ReqEnt {
   uint32_t seed_lo, seed_hi;
   const float* env;        // [env_h][env_w][3] or null (black)
   uint32_t env_w, env_h;
+  uint32_t unclamped;      // 1: Hart's unclamped steps (the next cell is the one containing the new point)
 };
 
 // Tables shared by the kernels of a pool.
@@ -148,6 +149,11 @@ struct MarchArgs {
   unsigned long long* evals;     // Ctrl::tally: [kTallyLines][16], per line evaluations, tiles, chunks
   int max_passes;            // in-cell passes per chunk before the rest wait a round
   uint32_t cs;               // words between per-cell counters
+  // requests with unclamped steps: rays whose step leaves the cell go on in
+  // the cell that contains the new point, appended here for the next round
+  RayRec* jump;              // next round's jumped rays
+  uint32_t* n_jump;          // their count
+  uint32_t* counts_next;     // arrivals per cell for the next round (cell c at c * cs)
 };
 
 struct ShadeArgs {
@@ -187,6 +193,31 @@ struct QueryArgs {
   float* z_out;
 };
 
+// dense lattice sampling: R points per axis, K work items of 256 points per
+// cell (K >= the largest cell's point count / 256)
+struct GridArgs {
+  SceneGeom sg;
+  const float* blocks;
+  uint32_t block_words;
+  SoftplusK spk;
+  uint32_t R, K;
+  float rm1;             // R - 1
+  float* d_out;          // [R^3], index i + R (j + R k)
+  float* grad_out;       // [R^3][3] or null (k_grid_full only)
+};
+
+// finite-difference eikonal term over n points
+struct EikArgs {
+  const float* pts;      // [n][3]
+  uint64_t n;
+  float delta;
+  float* stencil_pts;    // [6n][3]: x +- delta e_a, order +x, -x, +y, -y, +z, -z
+  const float* stencil;  // [6n]: the SDF at the stencil points
+  float* gnorm;          // [n]
+  double* partial;       // [ceil(n / 256)]
+  double* loss;          // [1] or null
+};
+
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st);
 hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st);
@@ -211,5 +242,10 @@ hipError_t launch_fill_u32(uint32_t* p, size_t n, uint32_t v, hipStream_t st);
 hipError_t launch_copy_u32(uint32_t* dst, const uint32_t* src, size_t n, hipStream_t st);
 hipError_t launch_query_d(const QueryArgs& a, int H, int prec, uint32_t grid, hipStream_t st);
 hipError_t launch_query_full(const QueryArgs& a, int H, uint32_t grid, hipStream_t st);
+hipError_t launch_grid_d(const GridArgs& a, int H, int prec, uint32_t grid, hipStream_t st);
+hipError_t launch_grid_full(const GridArgs& a, int H, uint32_t grid, hipStream_t st);
+hipError_t launch_eik_points(const EikArgs& a, hipStream_t st);
+// gradient norms, per-workgroup partial sums, then the loss (one workgroup)
+hipError_t launch_eik_combine(const EikArgs& a, hipStream_t st);
 
 }  // namespace kn

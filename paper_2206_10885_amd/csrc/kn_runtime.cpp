@@ -65,6 +65,8 @@ std::vector<std::string> hip_runtimes_loaded() {
 
 constexpr uint32_t kShadeChunk = 64;    // hits per shading work item
 constexpr uint32_t kQueryChunk = 256;   // points per query work item
+constexpr uint32_t kGridMaxR = 4096;    // lattice points per axis of kn_grid_sample
+constexpr uint64_t kEikMaxPoints = (1ull << 28) / 6u;   // stencil points fit one point query
 
 }  // namespace
 
@@ -345,6 +347,8 @@ struct Pool {
   RayRec* Uin = nullptr;           // records of newly generated rays
   RayRec* HL = nullptr;            // hit list since the last shading pass
   PathRec* path = nullptr;         // path tracing state (allocated on first use)
+  RayRec* J = nullptr;             // [2][cap]: rays of unclamped steps that jumped cells, per
+                                   // round parity (allocated on first use)
   // per-cell counters, cell c at word c * cs: on grids of up to
   // kPadCells cells each counter has a 128-byte line of its own
   uint32_t cs = 1;
@@ -422,6 +426,8 @@ struct kn_ctx {
   kn_scene_id next_id = 1;
   std::atomic<bool> poisoned{false};
   Pool ws;                     // the workspace of kn_render and kn_query
+  void* aux = nullptr;         // grow-only work buffer of kn_eikonal_fd
+  size_t aux_bytes = 0;
   uint32_t* pinned = nullptr;  // round counters read back by the host
   SceneEnt* h_scene = nullptr; // pinned staging of kn_render's tables
   ReqEnt* h_req = nullptr;
@@ -464,7 +470,7 @@ constexpr int kPinnedScanErr = 16;
 constexpr int kPinnedScanErrNoAlloc = 17;
 
 void free_pool(Pool& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.counts, w.runs, w.hit_count, w.cursor, w.base,
+  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.J, w.counts, w.runs, w.hit_count, w.cursor, w.base,
                   w.chunk, w.chunk_out, w.ctrl, w.scenes, w.reqs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -500,12 +506,15 @@ size_t pool_bytes(size_t R, size_t C, size_t K) {
 
 // grow-only pool for `rays` records over `cells` cells (with path state if
 // `paths`)
-kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool paths = false) {
+kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool paths = false,
+                      bool jumps = false) {
   const size_t chunks = rays / kShadeChunk + cells + 2;
-  if (w.ctrl && w.cap >= rays && w.cells >= cells && w.chunks >= chunks && (!paths || w.path)) return KN_OK;
+  if (w.ctrl && w.cap >= rays && w.cells >= cells && w.chunks >= chunks && (!paths || w.path) &&
+      (!jumps || w.J))
+    return KN_OK;
   const size_t R = std::max(w.cap, rays), C = std::max(w.cells, cells), K = std::max(w.chunks, chunks);
-  const bool P = paths || w.path;
-  const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0);
+  const bool P = paths || w.path, J = jumps || w.J;
+  const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0) + (J ? 2 * R * sizeof(RayRec) : 0);
   const uint64_t other = ctx->used.load() - w.bytes;
   if (other + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "ray workspace of %zu bytes exceeds the HBM budget", bytes);
@@ -527,6 +536,7 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.Uin, uin_entries(R) * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
   if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
+  if (J) KN_HIP(ctx, hipMalloc(&n.J, 2 * R * sizeof(RayRec)));
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * n.cs * 4));
@@ -539,6 +549,25 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.scenes, kMaxScenes * sizeof(SceneEnt)));
   KN_HIP(ctx, hipMalloc(&n.reqs, kMaxSlots * sizeof(ReqEnt)));
   w = n;
+  ctx->used += bytes;
+  return KN_OK;
+}
+
+// grow-only device buffer of at least `bytes` (kn_eikonal_fd's stencil)
+kn_status ensure_aux(kn_ctx* ctx, size_t bytes) {
+  if (ctx->aux_bytes >= bytes) return KN_OK;
+  const uint64_t other = ctx->used.load() - ctx->aux_bytes;
+  if (other + bytes > ctx->budget)
+    return fail(KN_E_NOMEM, "work buffer of %zu bytes exceeds the HBM budget", bytes);
+  if (ctx->aux) {
+    KN_HIP(ctx, hipDeviceSynchronize());
+    (void)hipFree(ctx->aux);
+    ctx->used -= ctx->aux_bytes;
+    ctx->aux = nullptr;
+    ctx->aux_bytes = 0;
+  }
+  KN_HIP(ctx, hipMalloc(&ctx->aux, bytes));
+  ctx->aux_bytes = bytes;
   ctx->used += bytes;
   return KN_OK;
 }
@@ -588,6 +617,7 @@ struct RoundCfg {
   uint32_t march_words;   // largest march block of the scenes
   uint32_t shade_words;   // largest shading block
   bool split;             // bf16 / fp8 pools: split-bfloat16 shading (else float32)
+  bool jumps;             // unclamped steps: rays that jump cells go through Pool::J
   uint32_t cells;         // global cells in use
   int max_passes;
 };
@@ -615,7 +645,8 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   sa.ticket = &w.ctrl->scan_ticket;
   sa.flags = w.ctrl->scan_flags;
   sa.err = &w.ctrl->scan_err;
-  sa.zero_word = nullptr;
+  // the march of this round appends the rays that jump cells to J[par ^ 1]
+  sa.zero_word = c.jumps ? &w.ctrl->n_jump[par ^ 1] : nullptr;
   sa.total = nullptr;
   KN_HIP(ctx, launch_scan(sa, st));
   if (r > 0) {
@@ -636,6 +667,10 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
     ScatterArgs sc{w.Uin, w.S, 0u, n_new_dev, w.cursor, 0, w.cs};
     KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
   }
+  if (c.jumps && r > 0) {
+    ScatterArgs sc{w.J + (size_t)par * w.cap, w.S, 0u, &w.ctrl->n_jump[par], w.cursor, 0, w.cs};
+    KN_HIP(ctx, launch_scatter(sc, persistent_grid(ctx, 4), st));
+  }
   MarchArgs ma{};
   ma.tabs = tabs;
   ma.S = w.S;
@@ -651,6 +686,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.cs = w.cs;
   ma.evals = &w.ctrl->tally[0][0];
   ma.max_passes = c.max_passes;
+  if (c.jumps) {
+    ma.jump = w.J + (size_t)(par ^ 1) * w.cap;
+    ma.n_jump = &w.ctrl->n_jump[par ^ 1];
+    ma.counts_next = w.counts + (par ^ 1) * w.cells * w.cs;
+  }
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
   // the grid is what the CUs hold at once: bf16 and fp8 march kernels 3
   // workgroups per CU (3 waves per SIMD, about 33 KB of LDS each), the
@@ -769,6 +809,8 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
     delete s;
   }
   free_pool(ctx->ws);
+  if (ctx->aux) (void)hipFree(ctx->aux);
+  ctx->used -= ctx->aux_bytes;
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->h_scene) (void)hipHostFree(ctx->h_scene);
   if (ctx->h_req) (void)hipHostFree(ctx->h_req);
@@ -945,7 +987,7 @@ kn_status validate_camera(const kn_camera* c, const KnScene* s) {
     return fail(KN_E_INVALID, "environment map of size %ux%u", c->env_w, c->env_h);
   if (c->precision != KN_FP32 && c->precision != KN_BF16 && c->precision != KN_FP8_E4M3)
     return fail(KN_E_INVALID, "unknown precision %d", (int)c->precision);
-  if (c->flags & ~(uint32_t)KN_CAMERA_SPLIT_BF16_SHADING)
+  if (c->flags & ~(uint32_t)(KN_CAMERA_SPLIT_BF16_SHADING | KN_CAMERA_UNCLAMPED_STEPS))
     return fail(KN_E_INVALID, "unknown camera flags 0x%x", c->flags);
   if (!s->march(c->precision))
     return fail(KN_E_INVALID, "scene has no copy in precision %d (set its bit in precisions)",
@@ -1093,7 +1135,8 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   const size_t npix = (size_t)c->width * c->height;
   const size_t rays = npix * spp;
   const size_t cells = (size_t)s->N * s->N * s->N;
-  kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt);
+  const bool jumps = (c->flags & KN_CAMERA_UNCLAMPED_STEPS) != 0;
+  kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt, jumps);
   if (st != KN_OK) return st;
   Pool& w = ctx->ws;
   const bool split = (c->flags & KN_CAMERA_SPLIT_BF16_SHADING) && c->precision != KN_FP32;
@@ -1112,9 +1155,10 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   q.env = c->env_rgb;
   q.env_w = c->env_w;
   q.env_h = c->env_h;
+  q.unclamped = jumps ? 1u : 0u;
   *ctx->h_req = q;
   const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, split,
-                     (uint32_t)cells, ctx->max_passes};
+                     jumps, (uint32_t)cells, ctx->max_passes};
 
   const bool timed = stats && stats->kernel_times;
   std::vector<std::pair<int, int>> march_ev, shade_ev;   // event index pairs
@@ -1376,6 +1420,115 @@ kn_status kn_query_noalloc(kn_ctx* ctx, kn_scene_id scene, kn_precision precisio
   }
   s->refs--;
   return st;
+}
+
+kn_status kn_grid_sample(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, uint32_t R, float* d_out,
+                         float* grad_out, void* hip_stream) {
+  kn_status st = check_ctx(ctx);
+  if (st != KN_OK) return st;
+  KnScene* s = find_scene(ctx, scene);
+  if (!s) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
+  if (!d_out) return fail(KN_E_INVALID, "d_out is NULL");
+  if (R < 2 || R > kGridMaxR) return fail(KN_E_INVALID, "lattice size R = %u outside [2, %u]", R, kGridMaxR);
+  if (precision != KN_FP32 && precision != KN_BF16 && precision != KN_FP8_E4M3)
+    return fail(KN_E_INVALID, "unknown precision %d", (int)precision);
+  if (grad_out && precision != KN_FP32)
+    return fail(KN_E_INVALID, "gradients are computed with the float32 weights (precision KN_FP32)");
+  if (!s->march(precision)) return fail(KN_E_INVALID, "scene has no copy in precision %d", (int)precision);
+  // work items per cell: enough 256-point parts for the largest cell
+  const uint32_t N = s->N;
+  uint32_t nmax = 0;
+  for (uint32_t c = 0; c < N; ++c) {
+    const uint32_t lo = (uint32_t)(((uint64_t)c * (R - 1u) + N - 1u) / N);
+    const uint32_t hi = c + 1u >= N ? R : (uint32_t)(((uint64_t)(c + 1u) * (R - 1u) + N - 1u) / N);
+    nmax = std::max(nmax, hi - lo);
+  }
+  const uint64_t per_cell = (uint64_t)nmax * nmax * nmax;
+  if (per_cell >= (1ull << 31))
+    return fail(KN_E_INVALID, "%llu lattice points in one cell exceed the limit of 2^31",
+                (unsigned long long)per_cell);
+  const uint64_t K = (per_cell + 255u) / 256u;
+  std::lock_guard<std::mutex> lk(ctx->render_mu);
+  KN_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  GridArgs ga{};
+  ga.sg = s->geom;
+  ga.spk = softplus_consts(s->geom.beta);
+  ga.R = R;
+  ga.K = (uint32_t)K;
+  ga.rm1 = (float)(R - 1u);
+  ga.d_out = d_out;
+  s->refs++;
+  hipError_t e;
+  if (grad_out) {
+    ga.blocks = s->shade;
+    ga.block_words = s->shade_words;
+    ga.grad_out = grad_out;
+    e = launch_grid_full(ga, s->H, persistent_grid(ctx, 2), stream);
+  } else {
+    ga.blocks = s->march(precision);
+    ga.block_words = s->march_words(precision);
+    e = launch_grid_d(ga, s->H, (int)precision, persistent_grid(ctx, 2), stream);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  s->refs--;
+  if (e != hipSuccess) {
+    ctx->poisoned = true;
+    return fail(KN_E_DEVICE, "lattice sampling: %s", hipGetErrorString(e));
+  }
+  return KN_OK;
+}
+
+kn_status kn_eikonal_fd(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points, uint64_t n,
+                        float delta, float* gnorm_out, float* stencil_out, double* loss_out, void* hip_stream) {
+  kn_status st = check_ctx(ctx);
+  if (st != KN_OK) return st;
+  KnScene* s = find_scene(ctx, scene);
+  if (!s) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
+  if (!gnorm_out) return fail(KN_E_INVALID, "gnorm_out is NULL");
+  if (!(delta > 0.0f) || !std::isfinite(delta)) return fail(KN_E_INVALID, "delta must be positive and finite");
+  if (n == 0) return KN_OK;
+  if (n > kEikMaxPoints)
+    return fail(KN_E_INVALID, "%llu points exceed the limit of %llu", (unsigned long long)n,
+                (unsigned long long)kEikMaxPoints);
+  if ((st = validate_query(s, precision, points, 6u * n)) != KN_OK) return st;
+  std::lock_guard<std::mutex> lk(ctx->render_mu);
+  KN_HIP(ctx, hipSetDevice(ctx->device));
+  hipStream_t stream = hip_stream ? (hipStream_t)hip_stream : ctx->stream;
+  const size_t cells = (size_t)s->N * s->N * s->N;
+  const uint64_t ns = 6u * n, nparts = (n + 255u) / 256u;
+  // work buffer: stencil points, stencil values (unless the caller keeps
+  // them), per-workgroup partial sums
+  const size_t off_val = align256(ns * 3u * 4u), off_part = off_val + align256(ns * 4u);
+  if ((st = ensure_aux(ctx, off_part + nparts * 8u)) != KN_OK) return st;
+  if ((st = ensure_pool(ctx, ctx->ws, ns, cells)) != KN_OK) return st;
+  uint8_t* aux = static_cast<uint8_t*>(ctx->aux);
+  EikArgs ea{};
+  ea.pts = points;
+  ea.n = n;
+  ea.delta = delta;
+  ea.stencil_pts = reinterpret_cast<float*>(aux);
+  float* vals = stencil_out ? stencil_out : reinterpret_cast<float*>(aux + off_val);
+  ea.stencil = vals;
+  ea.gnorm = gnorm_out;
+  ea.partial = reinterpret_cast<double*>(aux + off_part);
+  ea.loss = loss_out;
+  s->refs++;
+  hipError_t e = launch_eik_points(ea, stream);
+  if (e != hipSuccess) {
+    s->refs--;
+    ctx->poisoned = true;
+    return fail(KN_E_DEVICE, "eikonal stencil: %s", hipGetErrorString(e));
+  }
+  Pool& w = ctx->ws;
+  const QueryBufs b{w.U, w.S, w.counts, w.cursor, w.chunk, w.ctrl, w.cs};
+  st = enqueue_query(ctx, s, precision, ea.stencil_pts, ns, vals, nullptr, nullptr, stream, b, false);
+  s->refs--;
+  if (st != KN_OK) return st;
+  KN_HIP(ctx, launch_eik_combine(ea, stream));
+  KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
+  KN_HIP(ctx, hipStreamSynchronize(stream));
+  return check_scan(ctx, ctx->pinned[kPinnedScanErr]);
 }
 
 }  // extern "C"
@@ -1838,6 +1991,8 @@ kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, 
     if (cam->bounces != 0) return fail(KN_E_UNSUPPORTED, "the serving loop renders primary rays (bounces 0)");
     if (cam->flags & KN_CAMERA_SPLIT_BF16_SHADING)
       return fail(KN_E_UNSUPPORTED, "the serving loop refines and shades with float32 weights");
+    if (cam->flags & KN_CAMERA_UNCLAMPED_STEPS)
+      return fail(KN_E_UNSUPPORTED, "the serving loop takes cell-clamped steps");
     if (cam->precision != ctx->serve->precision())
       return fail(KN_E_INVALID, "camera precision %d differs from the serving loop's %d", (int)cam->precision,
                   (int)ctx->serve->precision());

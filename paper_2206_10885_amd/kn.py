@@ -18,6 +18,7 @@ KN_OK, KN_PENDING = 0, 1
 KN_FP32, KN_BF16, KN_FP8_E4M3 = 0, 1, 2
 KN_ABI_VERSION = 2
 KN_CAMERA_SPLIT_BF16_SHADING = 1
+KN_CAMERA_UNCLAMPED_STEPS = 2
 _STATUS = {0: "KN_OK", 1: "KN_PENDING", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_NOT_FOUND",
            -4: "KN_E_BUSY", -5: "KN_E_DEVICE", -6: "KN_E_TIMEOUT", -7: "KN_E_UNSUPPORTED",
            -8: "KN_E_SHUTDOWN"}
@@ -84,7 +85,8 @@ class Stats(C.Structure):
 
 
 EXPORTS = ["kn_ctx_create", "kn_ctx_destroy", "kn_last_error", "kn_scene_create",
-           "kn_scene_destroy", "kn_render", "kn_query", "kn_query_noalloc", "kn_serve_start",
+           "kn_scene_destroy", "kn_render", "kn_query", "kn_query_noalloc", "kn_grid_sample",
+           "kn_eikonal_fd", "kn_serve_start",
            "kn_serve_submit", "kn_serve_poll", "kn_serve_stop"]
 
 _lib = None
@@ -114,6 +116,8 @@ def lib():
         L.kn_render.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame), C.POINTER(Stats)]
         L.kn_query.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
         L.kn_query_noalloc.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
+        L.kn_grid_sample.argtypes = [vp, C.c_uint32, C.c_int, C.c_uint32, vp, vp, vp]
+        L.kn_eikonal_fd.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, C.c_float, vp, vp, vp, vp]
         L.kn_serve_start.argtypes = [vp, C.c_uint32, C.c_int]
         L.kn_serve_submit.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame),
                                       C.POINTER(C.c_uint64)]
@@ -138,16 +142,18 @@ def _ptr(t):
 
 def make_camera(view, width: int, height: int, max_steps: int, eps: float,
                 precision: str = "fp32", spp: int = 1, bounces: int = 0, seed: int = 0,
-                env=None, split_shading: bool = False) -> Camera:
+                env=None, split_shading: bool = False, unclamped: bool = False) -> Camera:
     """A kn_camera; split_shading selects the split-bfloat16 refinement and
-    shading of bf16 / fp8 marches (float32 otherwise)."""
+    shading of bf16 / fp8 marches (float32 otherwise); unclamped selects
+    Hart's unclamped steps across cells."""
     env_ptr, ew, eh = None, 0, 0
     if env is not None:
         env_ptr, eh, ew = env.data_ptr(), env.shape[0], env.shape[1]
     return Camera((C.c_float * 3)(*view.eye), (C.c_float * 3)(*view.look_at),
                   (C.c_float * 3)(*view.up), float(view.tan_half_diag), width, height, spp,
                   bounces, max_steps, eps, PRECISIONS[precision], seed, env_ptr, ew, eh,
-                  KN_CAMERA_SPLIT_BF16_SHADING if split_shading else 0)
+                  (KN_CAMERA_SPLIT_BF16_SHADING if split_shading else 0) |
+                  (KN_CAMERA_UNCLAMPED_STEPS if unclamped else 0))
 
 
 class Context:
@@ -221,8 +227,10 @@ class Context:
         return st.as_dict()
 
     def render(self, sid: int, view, width: int, height: int, max_steps: int, eps: float,
-               precision: str = "fp32", with_trace: bool = False, split_shading: bool = False) -> dict:
-        cam = make_camera(view, width, height, max_steps, eps, precision, split_shading=split_shading)
+               precision: str = "fp32", with_trace: bool = False, split_shading: bool = False,
+               unclamped: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, precision, split_shading=split_shading,
+                          unclamped=unclamped)
         out = self.alloc_frame(width, height, with_trace)
         out["stats"] = self.render_into(sid, cam, out)
         return out
@@ -269,3 +277,38 @@ class Context:
         check(fn(self.h, sid, PRECISIONS[precision], _ptr(pts), n, _ptr(d), _ptr(g), _ptr(z),
                  C.c_void_p(stream.cuda_stream)))
         return dict(d=d, grad=g, z=z)
+
+    def grid_sample(self, sid: int, R: int, precision: str = "fp32", grad: bool = False, stream=None,
+                    out=None) -> dict:
+        """kn_grid_sample: the SDF on the R^3 lattice spanning the box, as
+        [R, R, R] tensors indexed [k, j, i] (z, y, x); `out` (d, grad) receives
+        the results if given."""
+        import torch
+        dev = torch.device("cuda", self.device)
+        if out is not None:
+            d, g = out.get("d"), out.get("grad")
+        else:
+            d = torch.empty((R, R, R), dtype=torch.float32, device=dev)
+            g = torch.empty((R, R, R, 3), dtype=torch.float32, device=dev) if grad else None
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        check(lib().kn_grid_sample(self.h, sid, PRECISIONS[precision], R, _ptr(d), _ptr(g),
+                                   C.c_void_p(stream.cuda_stream)))
+        return dict(d=d, grad=g)
+
+    def eikonal_fd(self, sid: int, points, delta: float, precision: str = "fp32", stencil: bool = False,
+                   stream=None) -> dict:
+        """kn_eikonal_fd on a [n, 3] float32 device tensor: gradient norms,
+        optionally the six stencil values per point, and the loss (a device
+        float64 scalar)."""
+        import torch
+        pts = points.contiguous()
+        n = pts.shape[0]
+        gn = torch.empty(n, dtype=torch.float32, device=pts.device)
+        st = torch.empty((n, 6), dtype=torch.float32, device=pts.device) if stencil else None
+        loss = torch.empty(1, dtype=torch.float64, device=pts.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(pts.device)
+        check(lib().kn_eikonal_fd(self.h, sid, PRECISIONS[precision], _ptr(pts), n, float(delta), _ptr(gn),
+                                  _ptr(st), _ptr(loss), C.c_void_p(stream.cuda_stream)))
+        return dict(gnorm=gn, stencil=st, loss=loss)

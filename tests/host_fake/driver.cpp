@@ -175,6 +175,13 @@ void case_render_query(bool scan_err) {
     c.bounces = 3;
     c.spp = 4;
     expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_OK, "path-traced render");
+    c.flags = KN_CAMERA_UNCLAMPED_STEPS;
+    expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_OK, "path-traced render, unclamped steps");
+    kn_camera cu = camera(64, 48, KN_FP32);
+    cu.flags = KN_CAMERA_UNCLAMPED_STEPS;
+    expect(kn_render(ctx, id, &cu, &fr.f, nullptr) == KN_OK, "render, unclamped steps");
+    cu.flags = 4u;
+    expect(kn_render(ctx, id, &cu, &fr.f, nullptr) == KN_E_INVALID, "unknown camera flag refused");
     float* pts = nullptr;
     float *dd = nullptr, *gg = nullptr, *zz = nullptr;
     const uint64_t n = 5000;
@@ -216,6 +223,50 @@ void case_noalloc() {
   (void)hipFree(dd);
   (void)hipFree(gg);
   (void)hipFree(zz);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
+void case_grid_eikonal() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(4, 32, 14);
+  kn_scene_desc d = desc_of(s, kAll);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  const uint32_t R = 37;
+  float *dd = nullptr, *gg = nullptr;
+  (void)hipMalloc((void**)&dd, (size_t)R * R * R * 4);
+  (void)hipMalloc((void**)&gg, (size_t)R * R * R * 12);
+  for (kn_precision p : {KN_FP32, KN_BF16, KN_FP8_E4M3})
+    expect(kn_grid_sample(ctx, id, p, R, dd, nullptr, nullptr) == KN_OK, "lattice values");
+  expect(kn_grid_sample(ctx, id, KN_FP32, R, dd, gg, nullptr) == KN_OK, "lattice gradients");
+  expect(kn_grid_sample(ctx, id, KN_BF16, R, dd, gg, nullptr) == KN_E_INVALID, "bf16 gradients refused");
+  expect(kn_grid_sample(ctx, id, KN_FP32, 1, dd, nullptr, nullptr) == KN_E_INVALID, "R = 1 refused");
+  expect(kn_grid_sample(ctx, id, KN_FP32, R, nullptr, nullptr, nullptr) == KN_E_INVALID, "NULL d_out refused");
+  const uint64_t n = 3000;
+  float *pts = nullptr, *gn = nullptr, *st = nullptr;
+  double* loss = nullptr;
+  (void)hipMalloc((void**)&pts, 2 * n * 12);
+  (void)hipMalloc((void**)&gn, 2 * n * 4);
+  (void)hipMalloc((void**)&st, n * 24);
+  (void)hipMalloc((void**)&loss, 8);
+  for (kn_precision p : {KN_FP32, KN_BF16, KN_FP8_E4M3})
+    expect(kn_eikonal_fd(ctx, id, p, pts, n, 1e-3f, gn, st, loss, nullptr) == KN_OK, "eikonal");
+  expect(kn_eikonal_fd(ctx, id, KN_FP32, pts, n, 1e-3f, gn, nullptr, nullptr, nullptr) == KN_OK,
+         "eikonal without stencil or loss");
+  expect(kn_eikonal_fd(ctx, id, KN_FP32, pts, 2 * n, 1e-3f, gn, nullptr, nullptr, nullptr) == KN_OK,
+         "eikonal, work buffer grown");
+  expect(kn_eikonal_fd(ctx, id, KN_FP32, pts, n, 0.0f, gn, nullptr, nullptr, nullptr) == KN_E_INVALID,
+         "delta 0 refused");
+  expect(kn_eikonal_fd(ctx, id, KN_FP32, pts, n, 1e-3f, nullptr, nullptr, nullptr, nullptr) == KN_E_INVALID,
+         "NULL gnorm refused");
+  (void)hipFree(dd);
+  (void)hipFree(gg);
+  (void)hipFree(pts);
+  (void)hipFree(gn);
+  (void)hipFree(st);
+  (void)hipFree(loss);
+  kn_scene_destroy(ctx, id);
   expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
 }
 
@@ -288,6 +339,7 @@ int main(int argc, char** argv) {
   else if (c == "render") case_render_query(false);
   else if (c == "render_scan_err") case_render_query(true);
   else if (c == "query_scan_err") case_query_scan_err();
+  else if (c == "grid_eikonal") case_grid_eikonal();
   else if (c == "noalloc") case_noalloc();
   else if (c == "serve") case_serve(false);
   else if (c == "serve_scan_err") case_serve(true);

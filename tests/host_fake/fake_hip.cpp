@@ -219,4 +219,28 @@ hipError_t launch_query_full(const QueryArgs& a, int, uint32_t, hipStream_t) {
   return hipSuccess;
 }
 
+hipError_t launch_grid_d(const GridArgs& a, int, int, uint32_t, hipStream_t) {
+  need(a.blocks, 4, "weight blocks");
+  need(a.d_out, (size_t)a.R * a.R * a.R * 4, "lattice values");
+  return hipSuccess;
+}
+hipError_t launch_grid_full(const GridArgs& a, int, uint32_t, hipStream_t) {
+  need(a.blocks, 4, "weight blocks");
+  need(a.d_out, (size_t)a.R * a.R * a.R * 4, "lattice values");
+  if (a.grad_out) need(a.grad_out, (size_t)a.R * a.R * a.R * 12, "lattice gradients");
+  return hipSuccess;
+}
+hipError_t launch_eik_points(const EikArgs& a, hipStream_t) {
+  need(a.pts, a.n * 12, "eikonal points");
+  need(a.stencil_pts, a.n * 72, "stencil points");
+  return hipSuccess;
+}
+hipError_t launch_eik_combine(const EikArgs& a, hipStream_t) {
+  need(a.stencil, a.n * 24, "stencil values");
+  need(a.gnorm, a.n * 4, "gradient norms");
+  need(a.partial, (a.n + 255) / 256 * 8, "partial sums");
+  if (a.loss) need(a.loss, 8, "loss");
+  return hipSuccess;
+}
+
 }  // namespace kn

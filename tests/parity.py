@@ -53,11 +53,11 @@ def jittered(view: synth.View, amount: float, seed: int) -> synth.View:
     return synth.View(eye=tuple(e), look_at=view.look_at, up=view.up, tan_half_diag=view.tan_half_diag)
 
 
-def oracle_render(scene, view, W, H, S, eps, pixels=None) -> dict:
-    return O.OracleScene.from_scene(scene).render(view, W, H, S, eps, pixels=pixels)
+def oracle_render(scene, view, W, H, S, eps, pixels=None, unclamped: bool = False) -> dict:
+    return O.OracleScene.from_scene(scene).render(view, W, H, S, eps, pixels=pixels, unclamped=unclamped)
 
 
-def stable_mask(scene, view, W, H, S, eps, ref: dict, pixels=None, trials: int = 6):
+def stable_mask(scene, view, W, H, S, eps, ref: dict, pixels=None, trials: int = 6, unclamped: bool = False):
     """Pixels whose oracle result stays within half the tolerance under
     float32-sized perturbations of the inputs (weights x (1 + 1e-6 xi), eye
     + 1e-6 xi), and the oracle's own worst hit-mask agreement across them."""
@@ -65,7 +65,7 @@ def stable_mask(scene, view, W, H, S, eps, ref: dict, pixels=None, trials: int =
     self_agree = 1.0
     for k in range(trials):
         r = oracle_render(perturbed(scene, 1e-6, 100 + k), jittered(view, 1e-6, 200 + k), W, H, S, eps,
-                          pixels)
+                          pixels, unclamped)
         same_hit = r["hit"] == ref["hit"]
         self_agree = min(self_agree, float(np.mean(same_hit)))
         both = (r["hit"] == 1) & (ref["hit"] == 1)
@@ -158,13 +158,15 @@ def _trace_struct(cell_idx, t, t_entry):
     return dict(_raw=tr)
 
 
-def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None) -> Report:
+def compare(scene, view, W, H, S, eps, gpu: dict, pixels=None, unclamped: bool = False,
+            trials: int = 6) -> Report:
     """Full comparison of a GPU frame (numpy dict from gpu_arrays, restricted
-    to `pixels` if given) against the oracle."""
-    ref = oracle_render(scene, view, W, H, S, eps, pixels)
+    to `pixels` if given) against the oracle (in the same step rule);
+    `trials` perturbed oracle runs decide which pixels are well conditioned."""
+    ref = oracle_render(scene, view, W, H, S, eps, pixels, unclamped)
     n = len(ref["hit"])
     hit_agree = float(np.mean(ref["hit"] == gpu["hit"]))
-    stable, self_agree = stable_mask(scene, view, W, H, S, eps, ref, pixels)
+    stable, self_agree = stable_mask(scene, view, W, H, S, eps, ref, pixels, trials=trials, unclamped=unclamped)
     both = (ref["hit"] == 1) & (gpu["hit"] == 1)
     dd = np.abs(ref["depth"] - gpu["depth"])
     an = angle_deg(ref["normal"], gpu["normal"])

@@ -1,0 +1,146 @@
+"""GPU parity of Hart's unclamped sphere-tracing steps (KN_CAMERA_UNCLAMPED_STEPS)
+against the FP64 oracle in the same step rule.
+
+All calls go through the C ABI (libkn.so via the ctypes binding)."""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2206_10885_amd import synth
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.fail("no HIP device visible: GPU tests need an MI355X")
+    from paper_2206_10885_amd import kn
+    c = kn.Context(0)
+    yield c
+    c.close()
+
+
+def _render(ctx, sid, view, W, H, S, precision="fp32", unclamped=True, eps=1e-4):
+    return ctx.render(sid, view, W, H, S, eps, precision, with_trace=True, unclamped=unclamped)
+
+
+def test_unclamped_plane_closed_form(ctx):
+    """A plane folded into a 4^3 grid: unclamped steps hit at the plane's
+    exact crossing with the evaluation count of one global plane (the
+    oracle's, which a CPU test pins to the closed form), and never use more
+    evaluations than the clamped rule on the same pixels."""
+    n = np.array([0.3, 0.5, 0.81]); n /= np.linalg.norm(n)
+    sc = synth.plane_scene(4, 32, n, 0.1, seed=4)
+    view = synth.View(eye=tuple(2.5 * n + np.array([0.2, -0.1, 0.05])))
+    W = H = 48
+    sid = ctx.scene_create(sc)
+    out = _render(ctx, sid, view, W, H, 256)
+    g = P.gpu_arrays(out)
+    rep = P.compare(sc, view, W, H, 256, 1e-4, g, unclamped=True)
+    log("unclamped plane", rep.as_dict(), out["stats"])
+    assert rep.hit_agree >= P.TOL_HIT_MASK
+    assert rep.stable_bad == 0 and rep.replay_bad == 0 and rep.point_bad == 0
+    ref = P.oracle_render(sc, view, W, H, 256, 1e-4, unclamped=True)
+    same = (ref["hit"] == 1) & (g["hit"] == 1)
+    # float32 against FP64 steps: the count may differ by one where a value
+    # lands within rounding of eps
+    assert np.mean(np.abs(g["steps"][same] - ref["steps"][same]) <= 1) == 1.0
+    assert np.mean(g["steps"][same] == ref["steps"][same]) > 0.99
+    clamped = P.gpu_arrays(_render(ctx, sid, view, W, H, 256, unclamped=False))
+    both = same & (clamped["hit"] == 1)
+    assert (g["steps"][both] <= clamped["steps"][both] + 1).all()
+    assert g["steps"][both].sum() < clamped["steps"][both].sum()
+    ctx.scene_destroy(sid)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_unclamped_c1_full_frame(ctx, precision):
+    """C1 (4^3, H=32, 64x64, S=64) with unclamped steps, every pixel against
+    the oracle in the same rule (float32: the parity bar; bf16: every hit
+    valid at its own point and replay within the bar, the march's stops
+    within its stated bound)."""
+    c = synth.CONFIGS["c1"]
+    sc = synth.config_scene("c1")
+    view = synth.config_views("c1")[0]
+    sid = ctx.scene_create(sc)
+    out = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"], precision)
+    g = P.gpu_arrays(out)
+    rep = P.compare(sc, view, c["width"], c["height"], c["max_steps"], c["eps"], g, unclamped=True)
+    log("C1 unclamped", precision, rep.as_dict(), out["stats"])
+    if precision == "fp32":
+        assert rep.ok(), rep.as_dict()
+    else:
+        assert rep.point_bad <= 1e-3 * max(1, rep.point_n)
+        assert rep.replay_bad <= 1e-3 * max(1, rep.replay_n)
+    ctx.scene_destroy(sid)
+
+
+def test_unclamped_lipschitz_safe_ragged(ctx):
+    """The Lipschitz-safe sphere on an 8^3 grid at 97x61 (ragged tiles):
+    every pixel within the tolerance, and fewer evaluations than with
+    clamped steps."""
+    base = synth.sphere_scene(8, 32, 0.55, 0.0, seed=31)
+    sc = synth.lipschitz_safe(base, 0.6)
+    view = synth.View(eye=(0.8, 0.9, 2.2))
+    W, H = 97, 61
+    sid = ctx.scene_create(sc)
+    out = _render(ctx, sid, view, W, H, 512)
+    g = P.gpu_arrays(out)
+    rep = P.compare(sc, view, W, H, 512, 1e-4, g, unclamped=True)
+    log("lipschitz-safe unclamped", rep.as_dict(), out["stats"])
+    assert rep.hit_agree >= P.TOL_HIT_MASK
+    assert rep.stable_bad <= 1e-3 * rep.stable_checked and rep.replay_bad == 0 and rep.point_bad == 0
+    cl = _render(ctx, sid, view, W, H, 512, unclamped=False)
+    log(f"evaluations: unclamped {out['stats']['evals']}, clamped {cl['stats']['evals']}")
+    assert out["stats"]["evals"] < cl["stats"]["evals"]
+    ctx.scene_destroy(sid)
+
+
+def test_unclamped_c3_sampled_and_deterministic(ctx):
+    """C3 (16^3, H=64, 1920x1080) float32 with unclamped steps at full size,
+    sampled pixels against the oracle; two renders are identical.  Full
+    steps across the noisy scene's seams are far more chaotic than clamped
+    ones (the oracle's own hit mask moves on about 8% of the pixels under
+    1e-6 perturbations), so the well-conditioned pixels are those stable
+    over 12 perturbed oracle runs instead of 6."""
+    c = synth.CONFIGS["c3"]
+    sc = synth.config_scene("c3")
+    sid = ctx.scene_create(sc)
+    view = synth.config_views("c3")[3]
+    out = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"])
+    pix = synth.sample_pixels(c["width"], c["height"], 1500, seed=33)
+    g = P.gpu_arrays(out, pix)
+    rep = P.compare(sc, view, c["width"], c["height"], c["max_steps"], c["eps"], g, pixels=pix, unclamped=True,
+                    trials=12)
+    log("C3 unclamped", rep.as_dict(), out["stats"])
+    assert rep.ok(), rep.as_dict()
+    out2 = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"])
+    for k in ("rgb", "depth", "hit", "steps"):
+        assert torch.equal(out[k], out2[k]), k
+    ctx.scene_destroy(sid)
+
+
+def test_unclamped_refused_by_serving(ctx):
+    from paper_2206_10885_amd import kn
+    sc = synth.sphere_scene(4, 32, 0.5, 0.0, seed=3)
+    sid = ctx.scene_create(sc)
+    ctx.serve_start(4, "bf16")
+    try:
+        cam = kn.make_camera(synth.View(eye=(0.0, 0.0, 2.5)), 8, 8, 64, 1e-4, "bf16", unclamped=True)
+        with pytest.raises(kn.KnError) as e:
+            ctx.serve_submit(sid, cam, ctx.alloc_frame(8, 8))
+        assert e.value.status == -7
+    finally:
+        ctx.serve_stop()
+    ctx.scene_destroy(sid)

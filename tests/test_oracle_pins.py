@@ -581,3 +581,67 @@ def test_step_budget_exact_evaluation_count():
             assert r["status"] == O.HIT and r["steps"] == want
             checked += 1
     assert checked >= 40
+
+
+def test_unclamped_steps_closed_form_on_a_plane():
+    """Hart's unclamped stepping (the step rule without the cell-boundary
+    clamp) on a plane folded into a 4^3 grid: every step moves by the full
+    SDF value, across cells, so the evaluations follow the geometric
+    sequence f_k = f_0 (1 - cos) ^ k of the one global plane and their count
+    has the closed form; the hit cell is the cell that contains the march's
+    stop point, and the depth is the plane's exact crossing.  The clamped
+    rule on the same rays needs at least as many evaluations, and more only
+    on rays that cross a cell face before the hit (the clamped steps stop on
+    each face)."""
+    rng = np.random.default_rng(78)
+    checked = more = 0
+    N = 4
+    for case in range(10):
+        n = rng.standard_normal(3)
+        n /= np.linalg.norm(n)
+        sc = synth.plane_scene(N, 32, n, rng.uniform(-0.3, 0.3), seed=950 + case)
+        os_ = O.OracleScene.from_scene(sc)
+        g, c0 = synth.plane_affine_map(sc, 0)
+        gn = g / np.linalg.norm(g)
+        for _ in range(8):
+            cos_t = rng.uniform(0.1, 0.6)
+            tang = np.cross(gn, rng.standard_normal(3))
+            tang /= np.linalg.norm(tang)
+            d = -cos_t * gn + math.sqrt(1.0 - cos_t ** 2) * tang
+            o = -(c0 / (g @ g)) * g + rng.uniform(0.1, 0.6) * gn + rng.uniform(-0.3, 0.3) * tang
+            if np.abs(o).max() >= 0.98:
+                continue
+            ok, tn, tf = os_.slab(o, d)
+            t0 = max(tn, 0.0)
+            t_star = -(g @ o + c0) / (g @ d)
+            if not ok or t_star >= tf - 1e-2:
+                continue
+            # the cells' affine maps differ from cell 0's by float32 rounding
+            # of the stored parameters (~1e-7): keep rays whose decisive
+            # values are 1% away from the threshold
+            want, margin = _budget_count(g, c0, o, d, t0, 1e-4)
+            if margin < 0.01:
+                continue
+            r = os_.trace(o, d, 200, 1e-4, unclamped=True)
+            assert r["status"] == O.HIT and r["steps"] == want, (case, want, r)
+            x = o + r["t"] * d
+            idx = np.clip(np.floor((x + 1) * N / 2).astype(int), 0, N - 1)
+            assert tuple(idx) == tuple(r["cell"]), (x, r["cell"])
+            rc = os_.trace(o, d, 200, 1e-4)
+            assert rc["status"] == O.HIT and rc["steps"] >= want
+            cells, _ = os_.cells_along_ray(o, d)
+            hit_cell = idx[0] + N * (idx[1] + N * idx[2])
+            if rc["steps"] > want:
+                assert cells[0] != hit_cell   # only a face crossing costs extra evaluations
+                more += 1
+            checked += 1
+    assert checked >= 30 and more >= 10, (checked, more)
+    # the render path takes the same rule: depth at the closed-form crossing
+    view = synth.View(eye=tuple(2.5 * gn + 0.1 * tang))
+    out = os_.render(view, 24, 24, 200, 1e-4, unclamped=True)
+    hits = np.nonzero(out["hit"])[0]
+    assert hits.size > 100
+    for p in hits[::7]:
+        oo, dd = O.camera_ray(view, 24, 24, p // 24, p % 24)
+        ts = -(g @ oo + c0) / (g @ dd)
+        assert abs(out["depth"][p] - ts) < 1e-6
