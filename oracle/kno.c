@@ -305,16 +305,30 @@ void kno_trace(const kno_scene* s, const double o[3], const double d[3], int max
  * need not be a neighbour, so cells inside a step are never evaluated.  The
  * cell's entry parameter (the refinement's lower bound) is the t of its
  * first evaluation. */
+static void trace_interval(const kno_scene* s, const double o[3], const double d[3], double t0, double tf,
+                           int max_steps, double eps, int step_mode, kno_trace_result* r);
+
 void kno_trace_mode(const kno_scene* s, const double o[3], const double d[3], int max_steps,
                     double eps, int step_mode, kno_trace_result* r) {
-  memset(r, 0, sizeof(*r));
-  r->fmin = INFINITY;
   double tn, tf;
   if (!kno_slab(s, o, d, &tn, &tf)) {
+    memset(r, 0, sizeof(*r));
+    r->fmin = INFINITY;
     r->status = KNO_BOX_MISS;
     return;
   }
-  double t = fmax(tn, 0.0);
+  trace_interval(s, o, d, fmax(tn, 0.0), tf, max_steps, eps, step_mode, r);
+}
+
+/* The march over the parameter interval [t0, tf] inside the box: the entry
+ * cell is the one containing o + t0 d, and a step past tf ends the march as
+ * a miss wherever it lands (for the whole box interval, tf is the box exit,
+ * which no in-cell step can pass). */
+static void trace_interval(const kno_scene* s, const double o[3], const double d[3], double t0, double tf,
+                           int max_steps, double eps, int step_mode, kno_trace_result* r) {
+  memset(r, 0, sizeof(*r));
+  r->fmin = INFINITY;
+  double t = t0;
   int idx[3];
   cell_at(s, o, d, t, idx);
   double t_entry = t;
@@ -337,6 +351,11 @@ void kno_trace_mode(const kno_scene* s, const double o[3], const double d[3], in
     double t_exit = fmax(t, cell_exit(s, o, d, idx, &ax));
     if (t + f < t_exit) {
       t = t + f;
+      if (t > tf) {   /* past the end of the interval inside a cell (an interval cut short) */
+        r->status = KNO_EXIT_MISS;
+        r->t = t;
+        return;
+      }
     } else if (step_mode == KNO_STEP_UNCLAMPED) {
       t = t + f;
       t_entry = t;
@@ -551,7 +570,7 @@ static void trace_path(const kno_scene* s, const kno_camera* c, const kno_pt* pt
                        double L[3], kno_trace_result* first, double* first_depth, double first_n[3]) {
   const int row = (int)(p / c->width), colm = (int)(p % c->width);
   double xi1 = 0.5, xi2 = 0.5;
-  if (pt->spp > 1) path_uniforms(pt->seed, p, sample, 0, &xi1, &xi2);
+  if (pt->spp > 1 || pt->jitter) path_uniforms(pt->seed, p, sample, 0, &xi1, &xi2);
   double o[3], d[3];
   kno_camera_ray(c, row, colm, xi1, xi2, o, d);
   double T[3] = {1.0, 1.0, 1.0};
@@ -608,6 +627,294 @@ void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, c
     }
     if (depth) depth[q] = h ? dep : 0.0;
     if (hit) hit[q] = (uint8_t)h;
+  }
+}
+
+/* ------------------------------------------------------------------------
+ * Shared scenes (Sec. 3.4: the path tracer renders KiloNeuS objects next to
+ * classic primitives; for each ray it finds the closest intersection with an
+ * object's bounding volume, and inside a KiloNeuS object's box it
+ * sphere-traces the neural surface).  Readings:
+ *   - primitives are Lambertian spheres, axis-aligned boxes and triangles,
+ *     two-sided: the shading normal faces the incoming ray;
+ *   - a KiloNeuS instance is its scene placed by a uniform scale s > 0 and a
+ *     translation T (world x = T + s x_local); its MLPs see local
+ *     coordinates, so the local ray is ((o - T) / s, d) and a local
+ *     parameter t' is the world distance s t'; instance boxes are disjoint;
+ *   - a ray's next object is the nearest of: the closest primitive hit past
+ *     t_prim_min, and the entry of each instance box that starts at or past
+ *     t_inst_min (ties go to the primitive, then the lower index);
+ *   - an instance is sphere-traced from its entry to min(box exit, the
+ *     closest primitive hit); a march that leaves this interval continues
+ *     the ray from the box exit (t_inst_min = the exit); running out of
+ *     steps ends the ray as a miss, as for a single object.
+ * ------------------------------------------------------------------------ */
+
+static void face_ray(double n[3], const double d[3]) {
+  if (n[0] * d[0] + n[1] * d[1] + n[2] * d[2] > 0.0)
+    for (int a = 0; a < 3; ++a) n[a] = -n[a];
+}
+
+int kno_prim_hit(const kno_prim* p, const double o[3], const double d[3], double t_min, double* t,
+                 double n[3]) {
+  if (p->kind == KNO_PRIM_SPHERE) {
+    const double oc[3] = {o[0] - p->p[0], o[1] - p->p[1], o[2] - p->p[2]};
+    const double r = p->p[3];
+    const double b = oc[0] * d[0] + oc[1] * d[1] + oc[2] * d[2];
+    const double c = oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2] - r * r;
+    const double disc = b * b - c;
+    if (disc < 0.0) return 0;
+    const double sq = sqrt(disc);
+    double th = -b - sq;
+    if (!(th > t_min)) th = -b + sq;
+    if (!(th > t_min)) return 0;
+    *t = th;
+    for (int a = 0; a < 3; ++a) n[a] = (o[a] + th * d[a] - p->p[a]) / r;
+    face_ray(n, d);
+    return 1;
+  }
+  if (p->kind == KNO_PRIM_BOX) {
+    double tn = -INFINITY, tf = INFINITY;
+    int an = -1, af = -1;
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] == 0.0) {
+        if (o[a] < p->p[a] || o[a] > p->p[3 + a]) return 0;
+        continue;
+      }
+      double t1 = (p->p[a] - o[a]) / d[a], t2 = (p->p[3 + a] - o[a]) / d[a];
+      if (t1 > t2) {
+        const double x = t1;
+        t1 = t2;
+        t2 = x;
+      }
+      if (t1 > tn) {
+        tn = t1;
+        an = a;
+      }
+      if (t2 < tf) {
+        tf = t2;
+        af = a;
+      }
+    }
+    if (tn > tf) return 0;
+    int ax;
+    if (tn > t_min) {
+      *t = tn;
+      ax = an;
+    } else if (tf > t_min) {
+      *t = tf;
+      ax = af;
+    } else {
+      return 0;
+    }
+    if (ax < 0) return 0;
+    n[0] = n[1] = n[2] = 0.0;
+    n[ax] = d[ax] > 0.0 ? -1.0 : 1.0;
+    return 1;
+  }
+  if (p->kind == KNO_PRIM_TRIANGLE) {
+    /* Moller-Trumbore */
+    const double* A = p->p;
+    const double e1[3] = {p->p[3] - A[0], p->p[4] - A[1], p->p[5] - A[2]};
+    const double e2[3] = {p->p[6] - A[0], p->p[7] - A[1], p->p[8] - A[2]};
+    double pv[3], qv[3], tv[3] = {o[0] - A[0], o[1] - A[1], o[2] - A[2]};
+    cross3(d, e2, pv);
+    const double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    if (fabs(det) < 1e-300) return 0;
+    const double inv = 1.0 / det;
+    const double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+    if (u < 0.0 || u > 1.0) return 0;
+    cross3(tv, e1, qv);
+    const double v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+    if (v < 0.0 || u + v > 1.0) return 0;
+    const double th = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+    if (!(th > t_min)) return 0;
+    *t = th;
+    cross3(e1, e2, n);
+    normalize3(n);
+    face_ray(n, d);
+    return 1;
+  }
+  return 0;
+}
+
+typedef struct {
+  int32_t kind;     /* KNO_OBJ_* */
+  int32_t index;
+  double t;         /* primitive hit, or instance entry (world) */
+  double t_exit;    /* instance box exit (world) */
+  double t_prim;    /* closest primitive hit (INFINITY if none) */
+  double n[3];      /* primitive: facing normal */
+} world_next;
+
+static void instance_ray(const kno_instance* in, const double o[3], double ol[3]) {
+  for (int a = 0; a < 3; ++a) ol[a] = (o[a] - in->translate[a]) / in->scale;
+}
+
+/* the ray's next object past t_prim_min (primitives) and t_inst_min
+ * (instance entries) */
+static void world_step(const kno_world* w, const double o[3], const double d[3], double t_prim_min,
+                       double t_inst_min, world_next* r) {
+  r->kind = KNO_OBJ_NONE;
+  r->index = -1;
+  r->t = INFINITY;
+  r->t_prim = INFINITY;
+  int pi = -1;
+  double pn[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < w->n_prim; ++i) {
+    double t, n[3];
+    if (kno_prim_hit(&w->prim[i], o, d, t_prim_min, &t, n) && t < r->t_prim) {
+      r->t_prim = t;
+      pi = i;
+      memcpy(pn, n, sizeof(pn));
+    }
+  }
+  int ii = -1;
+  double te = INFINITY, tx = 0.0;
+  for (int k = 0; k < w->n_inst; ++k) {
+    const kno_instance* in = &w->inst[k];
+    double ol[3], tn, tf;
+    instance_ray(in, o, ol);
+    if (!kno_slab(in->scene, ol, d, &tn, &tf)) continue;
+    const double entry = in->scale * fmax(tn, 0.0);
+    if (entry < t_inst_min) continue;
+    if (entry < te) {
+      te = entry;
+      tx = in->scale * tf;
+      ii = k;
+    }
+  }
+  if (pi >= 0 && r->t_prim <= te) {
+    r->kind = KNO_OBJ_PRIM;
+    r->index = pi;
+    r->t = r->t_prim;
+    memcpy(r->n, pn, sizeof(pn));
+  } else if (ii >= 0) {
+    r->kind = KNO_OBJ_INST;
+    r->index = ii;
+    r->t = te;
+    r->t_exit = tx;
+  }
+}
+
+/* the surface a world ray meets: kind, world t, normal, albedo (KiloNeuS:
+ * the color MLP); first_* of the KiloNeuS march for diagnostics */
+typedef struct {
+  int32_t kind;     /* KNO_OBJ_NONE: escaped (or ran out of steps) */
+  int32_t index;
+  double t, n[3], albedo[3];
+} world_hit;
+
+static void world_trace(const kno_world* w, const kno_camera* c, const double o[3], const double d[3],
+                        world_hit* h) {
+  double t_prim_min = 0.0, t_inst_min = 0.0;
+  h->kind = KNO_OBJ_NONE;
+  h->index = -1;
+  for (int guard = 0; guard <= w->n_inst; ++guard) {
+    world_next nx;
+    world_step(w, o, d, t_prim_min, t_inst_min, &nx);
+    if (nx.kind == KNO_OBJ_NONE) return;
+    if (nx.kind == KNO_OBJ_PRIM) {
+      h->kind = KNO_OBJ_PRIM;
+      h->index = nx.index;
+      h->t = nx.t;
+      memcpy(h->n, nx.n, sizeof(h->n));
+      memcpy(h->albedo, w->prim[nx.index].albedo, sizeof(h->albedo));
+      return;
+    }
+    const kno_instance* in = &w->inst[nx.index];
+    double ol[3];
+    instance_ray(in, o, ol);
+    const double tfar = fmin(nx.t_exit, nx.t_prim) / in->scale;
+    kno_trace_result r;
+    trace_interval(in->scene, ol, d, nx.t / in->scale, tfar, c->max_steps, c->eps, c->step_mode, &r);
+    if (r.status == KNO_HIT) {
+      double dep, z[15];
+      kno_shade(in->scene, ol, d, &r, &dep, h->n, h->albedo, z);
+      h->kind = KNO_OBJ_INST;
+      h->index = nx.index;
+      h->t = in->scale * dep;
+      return;
+    }
+    if (r.status != KNO_EXIT_MISS) return;   /* out of steps: a miss */
+    t_inst_min = nx.t_exit;                  /* on past this instance's box */
+  }
+}
+
+void kno_world_render(const kno_world* w, const kno_camera* c, const int64_t* pixels, int64_t npix,
+                      double* rgb, double* depth, double* normal, uint8_t* hit, int32_t* object,
+                      int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+  for (int64_t q = 0; q < npix; ++q) {
+    const int64_t p = pixels ? pixels[q] : q;
+    double o[3], d[3];
+    kno_camera_ray(c, (int)(p / c->width), (int)(p % c->width), 0.5, 0.5, o, d);
+    world_hit h;
+    world_trace(w, c, o, d, &h);
+    const int on = h.kind != KNO_OBJ_NONE;
+    for (int a = 0; a < 3; ++a) {
+      if (rgb) rgb[q * 3 + a] = on ? h.albedo[a] : c->background[a];
+      if (normal) normal[q * 3 + a] = on ? h.n[a] : 0.0;
+    }
+    if (depth) depth[q] = on ? h.t : 0.0;
+    if (hit) hit[q] = (uint8_t)on;
+    /* object id: -1 none, instance k as k, primitive i as -(2 + i) */
+    if (object) object[q] = h.kind == KNO_OBJ_INST ? h.index : (h.kind == KNO_OBJ_PRIM ? -(2 + h.index) : -1);
+  }
+}
+
+void kno_world_path_trace(const kno_world* w, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
+                          int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit,
+                          int nthreads) {
+#ifdef _OPENMP
+  if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+  for (int64_t q = 0; q < npix; ++q) {
+    const int64_t p = pixels ? pixels[q] : q;
+    const int row = (int)(p / c->width), colm = (int)(p % c->width);
+    double acc[3] = {0.0, 0.0, 0.0}, dep0 = 0.0, n0[3] = {0.0, 0.0, 0.0};
+    int h0 = 0;
+    for (int smp = 0; smp < pt->spp; ++smp) {
+      double xi1 = 0.5, xi2 = 0.5;
+      if (pt->spp > 1 || pt->jitter) path_uniforms(pt->seed, p, smp, 0, &xi1, &xi2);
+      double o[3], d[3], T[3] = {1.0, 1.0, 1.0}, L[3] = {0.0, 0.0, 0.0};
+      kno_camera_ray(c, row, colm, xi1, xi2, o, d);
+      for (int k = 0;; ++k) {
+        world_hit h;
+        world_trace(w, c, o, d, &h);
+        if (k == 0 && smp == 0) {
+          h0 = h.kind != KNO_OBJ_NONE;
+          dep0 = h0 ? h.t : 0.0;
+          for (int a = 0; a < 3; ++a) n0[a] = h0 ? h.n[a] : 0.0;
+        }
+        if (h.kind == KNO_OBJ_NONE) {
+          double env[3];
+          kno_env_lookup(&pt->env, d, env);
+          for (int a = 0; a < 3; ++a) L[a] += T[a] * env[a];
+          break;
+        }
+        if (k >= pt->bounces) break;
+        for (int a = 0; a < 3; ++a) T[a] *= h.albedo[a];
+        double u1, u2, nd[3];
+        path_uniforms(pt->seed, p, smp, k + 1, &u1, &u2);
+        kno_cosine_dir(h.n, u1, u2, nd);
+        for (int a = 0; a < 3; ++a) {
+          o[a] = o[a] + h.t * d[a] + 1e-3 * h.n[a];
+          d[a] = nd[a];
+        }
+      }
+      for (int a = 0; a < 3; ++a) acc[a] += L[a];
+    }
+    for (int a = 0; a < 3; ++a) {
+      if (rgb) rgb[q * 3 + a] = acc[a] / pt->spp;
+      if (normal) normal[q * 3 + a] = n0[a];
+    }
+    if (depth) depth[q] = dep0;
+    if (hit) hit[q] = (uint8_t)h0;
   }
 }
 

@@ -104,6 +104,7 @@ typedef struct {
   int32_t bounces;        /* scatters per path */
   uint64_t seed;          /* Philox key */
   kno_env env;
+  int32_t jitter;         /* pixel jitter even at spp = 1 (progressive accumulation) */
 } kno_pt;
 
 void kno_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -112,6 +113,41 @@ void kno_cosine_dir(const double n[3], double u1, double u2, double out[3]);
 void kno_env_lookup(const kno_env* e, const double d[3], double rgb[3]);
 void kno_path_trace(const kno_scene* s, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
                     int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit, int nthreads);
+
+/* shared scenes (Sec. 3.4: KiloNeuS objects with classic primitives):
+ * Lambertian spheres, axis-aligned boxes and triangles, and KiloNeuS
+ * instances placed by a uniform scale and a translation */
+enum { KNO_PRIM_SPHERE = 1, KNO_PRIM_BOX = 2, KNO_PRIM_TRIANGLE = 3 };
+typedef struct {
+  int32_t kind;           /* KNO_PRIM_* */
+  double p[9];            /* sphere: centre, radius; box: min, max; triangle: 3 vertices */
+  double albedo[3];
+} kno_prim;
+
+typedef struct {
+  const kno_scene* scene; /* its box [bmin, bmax] in the instance's own frame */
+  double translate[3];    /* world = translate + scale * local */
+  double scale;
+} kno_instance;
+
+typedef struct {
+  int32_t n_inst;
+  const kno_instance* inst;
+  int32_t n_prim;
+  const kno_prim* prim;
+} kno_world;
+
+/* outcome of a world ray */
+enum { KNO_OBJ_NONE = 0, KNO_OBJ_PRIM = 1, KNO_OBJ_INST = 2 };
+
+int kno_prim_hit(const kno_prim* p, const double o[3], const double d[3], double t_min, double* t,
+                 double n[3]);
+void kno_world_render(const kno_world* w, const kno_camera* c, const int64_t* pixels, int64_t npix,
+                      double* rgb, double* depth, double* normal, uint8_t* hit, int32_t* object,
+                      int nthreads);
+void kno_world_path_trace(const kno_world* w, const kno_camera* c, const kno_pt* pt, const int64_t* pixels,
+                          int64_t npix, double* rgb, double* depth, double* normal, uint8_t* hit,
+                          int nthreads);
 
 /* point-query workloads (Sec. 3.3): the global piecewise SDF at world
  * points, on a dense lattice (mesh extraction, Sec. 4.1) and the eikonal

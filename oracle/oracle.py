@@ -55,7 +55,24 @@ class _Env(C.Structure):
 
 
 class _PT(C.Structure):
-    _fields_ = [("spp", C.c_int32), ("bounces", C.c_int32), ("seed", C.c_uint64), ("env", _Env)]
+    _fields_ = [("spp", C.c_int32), ("bounces", C.c_int32), ("seed", C.c_uint64), ("env", _Env),
+                ("jitter", C.c_int32)]
+
+
+class _Prim(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("p", C.c_double * 9), ("albedo", C.c_double * 3)]
+
+
+class _Instance(C.Structure):
+    _fields_ = [("scene", C.POINTER(_Scene)), ("translate", C.c_double * 3), ("scale", C.c_double)]
+
+
+class _World(C.Structure):
+    _fields_ = [("n_inst", C.c_int32), ("inst", C.POINTER(_Instance)), ("n_prim", C.c_int32),
+                ("prim", C.POINTER(_Prim))]
+
+
+PRIM_SPHERE, PRIM_BOX, PRIM_TRIANGLE = 1, 2, 3
 
 
 _lib = None
@@ -99,6 +116,12 @@ def lib():
         L.kno_path_trace.argtypes = [C.POINTER(_Scene), C.POINTER(_Camera), C.POINTER(_PT), C.c_void_p,
                                      C.c_int64, dp, dp, dp, C.POINTER(C.c_uint8), C.c_int]
         L.kno_query.argtypes = [C.POINTER(_Scene), dp, C.c_int64, dp, dp, dp, C.c_int]
+        L.kno_prim_hit.argtypes = [C.POINTER(_Prim), dp, dp, C.c_double, dp, dp]
+        L.kno_prim_hit.restype = C.c_int
+        L.kno_world_render.argtypes = [C.POINTER(_World), C.POINTER(_Camera), C.c_void_p, C.c_int64, dp, dp, dp,
+                                       C.POINTER(C.c_uint8), C.POINTER(C.c_int32), C.c_int]
+        L.kno_world_path_trace.argtypes = [C.POINTER(_World), C.POINTER(_Camera), C.POINTER(_PT), C.c_void_p,
+                                           C.c_int64, dp, dp, dp, C.POINTER(C.c_uint8), C.c_int]
         L.kno_grid_sample.argtypes = [C.POINTER(_Scene), C.c_int, C.POINTER(C.c_int64), C.c_int64,
                                       dp, dp, dp, C.c_int]
         L.kno_eikonal_fd.argtypes = [C.POINTER(_Scene), dp, C.c_int64, C.c_double, dp, dp, dp, C.c_int]
@@ -247,12 +270,13 @@ class OracleScene:
 
     def path_trace(self, view, width: int, height: int, max_steps: int, eps: float, spp: int,
                    bounces: int, seed: int, env=None, pixels=None, nthreads: int = 0,
-                   unclamped: bool = False) -> dict:
+                   unclamped: bool = False, jitter: bool = False) -> dict:
         """Path-traced pixels (mean radiance over spp) plus the primary
-        segment's depth, normal and hit of sample 0."""
+        segment's depth, normal and hit of sample 0; jitter: jittered
+        pixel samples at spp = 1 too."""
         cam = make_camera(view, width, height, max_steps, eps, unclamped=unclamped)
         envp = _make_env(env)
-        pt = _PT(spp, bounces, seed, envp)
+        pt = _PT(spp, bounces, seed, envp, 1 if jitter else 0)
         if pixels is None:
             npix, pix_ptr = width * height, None
         else:
@@ -335,3 +359,59 @@ def camera_ray(view, width, height, row, col, xi1=0.5, xi2=0.5):
     o, d = np.zeros(3), np.zeros(3)
     lib().kno_camera_ray(C.byref(cam), row, col, xi1, xi2, _dp(o), _dp(d))
     return o, d
+
+
+def prim_hit(kind: int, params, o, d, t_min: float = 0.0):
+    """Closest hit of one primitive past t_min: (hit, t, facing normal)."""
+    pr = _Prim(kind, (C.c_double * 9)(*(list(params) + [0.0] * (9 - len(params)))), (C.c_double * 3)(0, 0, 0))
+    t = C.c_double()
+    n = np.zeros(3)
+    ok = lib().kno_prim_hit(C.byref(pr), _dp(_vec(o)), _dp(_vec(d)), float(t_min), C.byref(t), _dp(n))
+    return bool(ok), t.value, n
+
+
+class OracleWorld:
+    """A shared scene: KiloNeuS instances (OracleScene, translation, uniform
+    scale) and Lambertian primitives (kind, params, albedo)."""
+
+    def __init__(self, instances=(), prims=()):
+        self._scenes = [sc for sc, _, _ in instances]   # keep the scenes alive
+        n_i, n_p = len(instances), len(prims)
+        self._inst = (_Instance * max(1, n_i))()
+        for k, (sc, t, s_) in enumerate(instances):
+            self._inst[k] = _Instance(C.pointer(sc.c), (C.c_double * 3)(*t), float(s_))
+        self._prim = (_Prim * max(1, n_p))()
+        for k, (kind, params, alb) in enumerate(prims):
+            ps = list(params) + [0.0] * (9 - len(params))
+            self._prim[k] = _Prim(kind, (C.c_double * 9)(*ps), (C.c_double * 3)(*alb))
+        self.w = _World(n_i, self._inst, n_p, self._prim)
+
+    def render(self, view, width: int, height: int, max_steps: int, eps: float, pixels=None,
+               background=(0.0, 0.0, 0.0), nthreads: int = 0, unclamped: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, background, unclamped)
+        if pixels is None:
+            npix, pix_ptr = width * height, None
+        else:
+            pixels = np.ascontiguousarray(pixels, np.int64)
+            npix, pix_ptr = pixels.size, pixels.ctypes.data
+        rgb, depth, normal = np.zeros((npix, 3)), np.zeros(npix), np.zeros((npix, 3))
+        hit, obj = np.zeros(npix, np.uint8), np.zeros(npix, np.int32)
+        lib().kno_world_render(C.byref(self.w), C.byref(cam), pix_ptr, npix, _dp(rgb), _dp(depth), _dp(normal),
+                               hit.ctypes.data_as(C.POINTER(C.c_uint8)), obj.ctypes.data_as(C.POINTER(C.c_int32)),
+                               nthreads)
+        return dict(rgb=rgb, depth=depth, normal=normal, hit=hit, object=obj)
+
+    def path_trace(self, view, width: int, height: int, max_steps: int, eps: float, spp: int, bounces: int,
+                   seed: int, env=None, pixels=None, nthreads: int = 0, jitter: bool = False,
+                   unclamped: bool = False) -> dict:
+        cam = make_camera(view, width, height, max_steps, eps, unclamped=unclamped)
+        pt = _PT(spp, bounces, seed, _make_env(env), 1 if jitter else 0)
+        if pixels is None:
+            npix, pix_ptr = width * height, None
+        else:
+            pixels = np.ascontiguousarray(pixels, np.int64)
+            npix, pix_ptr = pixels.size, pixels.ctypes.data
+        rgb, depth, normal, hit = np.zeros((npix, 3)), np.zeros(npix), np.zeros((npix, 3)), np.zeros(npix, np.uint8)
+        lib().kno_world_path_trace(C.byref(self.w), C.byref(cam), C.byref(pt), pix_ptr, npix, _dp(rgb), _dp(depth),
+                                   _dp(normal), hit.ctypes.data_as(C.POINTER(C.c_uint8)), nthreads)
+        return dict(rgb=rgb, depth=depth, normal=normal, hit=hit)
