@@ -29,7 +29,8 @@
 extern "C" {
 #endif
 
-#define KN_ABI_VERSION 2u   /* 2: kn_camera gained `flags`, kn_frame `segments` */
+#define KN_ABI_VERSION 3u   /* 2: kn_camera gained `flags`, kn_frame `segments`;
+                               3: kn_camera `sample_offset`, kn_frame `accum`, shared scenes */
 
 typedef enum {
   KN_OK = 0,
@@ -143,6 +144,9 @@ typedef struct {
   const float* env_rgb;            /* DEVICE [env_h][env_w][3] or NULL (black); path tracing */
   uint32_t env_w, env_h;
   uint32_t flags;                  /* KN_CAMERA_* bits, 0 by default */
+  uint32_t sample_offset;          /* path tracing: the index of this call's first sample (its
+                                      samples are sample_offset .. sample_offset + spp - 1 of
+                                      each pixel's stream); 0 for a single call */
 } kn_camera;
 
 /* kn_camera.flags: refinement and shading of a bf16 or fp8 march with the SDF
@@ -226,6 +230,12 @@ typedef struct {
   kn_trace_record* trace;          /* optional diagnostics */
   kn_segment_record* segments;     /* optional, path tracing: [W*H*spp][bounces + 1] */
   void* hip_stream;                /* hipStream_t to run on; NULL = ctx stream */
+  float* accum;                    /* optional, path tracing: progressive accumulation,
+                                      [height][width][3] running sum of the samples'
+                                      radiance.  A call with sample_offset 0 restarts it;
+                                      every call adds its spp samples and sets
+                                      rgb = accum / (sample_offset + spp).  With accum the
+                                      pixel samples are jittered even at spp = 1. */
 } kn_frame;
 
 typedef struct {
@@ -312,6 +322,65 @@ kn_status kn_grid_sample(kn_ctx* ctx, kn_scene_id scene, kn_precision precision,
  * KN_E_DEVICE. */
 kn_status kn_eikonal_fd(kn_ctx* ctx, kn_scene_id scene, kn_precision precision, const float* points, uint64_t n,
                         float delta, float* gnorm_out, float* stencil_out, double* loss_out, void* hip_stream);
+
+/* ---------------------------------------------------------------------
+ * Shared scenes (Sec. 3.4: the path tracer renders KiloNeuS objects
+ * together with classic primitives).  A world holds up to 16 KiloNeuS
+ * instances and up to 256 primitives.
+ *   - An instance places a resident scene by a uniform scale s > 0 and a
+ *     translation T: world x = T + s x_local.  Its MLPs see local
+ *     coordinates (ray ((o - T) / s, d); a local parameter t' is the world
+ *     distance s t').  The world boxes T + s [bbox_min, bbox_max] of the
+ *     instances must be disjoint.
+ *   - Primitives are Lambertian (albedo in [0, 1]^3) and two-sided (the
+ *     shading normal faces the incoming ray): spheres (p[0..2] centre,
+ *     p[3] radius > 0), axis-aligned boxes (p[0..2] min < p[3..5] max) and
+ *     triangles (p[0..8]: three vertices, nonzero area).
+ *   - A ray's next object is the nearest of its closest primitive hit and
+ *     the instance boxes it enters (ties go to the primitive, then to the
+ *     lower index).  An instance is sphere-traced, as kn_render does, from
+ *     its box entry to the nearer of its box exit and the closest primitive
+ *     hit; a march that reaches that end goes on past the box, one that
+ *     runs out of steps ends the ray as a miss.
+ *   - Primary renders (bounces 0): rgb is the primitive's albedo or the
+ *     KiloNeuS color; depth is the world distance; hit = 1 on either.  Path
+ *     tracing treats every surface as Lambertian with its albedo, as
+ *     kn_render does.  kn_trace_record.cell of a primitive hit is
+ *     -(2 + primitive index); segments are not recorded.
+ * --------------------------------------------------------------------- */
+typedef uint32_t kn_world_id;
+enum { KN_PRIM_SPHERE = 1, KN_PRIM_BOX = 2, KN_PRIM_TRIANGLE = 3 };
+typedef struct {
+  uint32_t kind;                   /* KN_PRIM_* */
+  float p[9];
+  float albedo[3];
+} kn_primitive;
+typedef struct {
+  kn_scene_id scene;
+  float translate[3];
+  float scale;
+} kn_instance;
+typedef struct {
+  uint32_t n_instances;            /* 0..16 */
+  const kn_instance* instances;    /* HOST */
+  uint32_t n_primitives;           /* 0..256 */
+  const kn_primitive* primitives;  /* HOST, copied by the call */
+} kn_world_desc;
+
+/* Creates a world over resident scenes (which it references until it is
+ * destroyed: kn_scene_destroy of such a scene returns KN_E_BUSY).
+ * Errors: KN_E_INVALID (overlapping instance boxes, bad primitive),
+ * KN_E_NOT_FOUND, KN_E_NOMEM, KN_E_DEVICE. */
+kn_status kn_world_create(kn_ctx* ctx, const kn_world_desc* desc, kn_world_id* out);
+kn_status kn_world_destroy(kn_ctx* ctx, kn_world_id world);
+
+/* Renders one frame of a world, as kn_render does a single scene (same
+ * camera, frame and flags; every instance's scene needs a copy in the
+ * camera's precision).  Returns when the frame is complete.  Errors as
+ * kn_render, and KN_E_UNSUPPORTED for unclamped steps in a world whose
+ * instances mix MLP widths. */
+kn_status kn_render_world(kn_ctx* ctx, kn_world_id world, const kn_camera* cam, const kn_frame* frame,
+                          kn_stats* stats_opt);
 
 /* ---------------------------------------------------------------------
  * Serving: a loop that keeps scenes resident and renders queued requests

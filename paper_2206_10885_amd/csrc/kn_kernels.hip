@@ -94,7 +94,13 @@ __device__ __forceinline__ void write_miss(const OutPtrs& o, uint32_t pix, int s
   }
   if (o.hit) gmem(o.hit)[pix] = 0;
   if (o.steps) gmem(o.steps)[pix] = (uint16_t)steps;
-  if (o.trace) o.trace[pix] = TraceRec{t, t_entry, cell, status};
+  if (o.trace) {
+    auto tr = gmem(o.trace + pix);
+    tr->t_march = t;
+    tr->t_entry = t_entry;
+    tr->cell = cell;
+    tr->status = status;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
     const uint32_t pix = id / a.spp, smp = id % a.spp;
     const int row = (int)(pix / (uint32_t)a.W), col = (int)(pix % (uint32_t)a.W);
     float xi1 = 0.5f, xi2 = 0.5f;
-    if (a.spp > 1) path_uniforms(a.seed_lo, a.seed_hi, pix, smp, 0u, &xi1, &xi2);
+    if (a.spp > 1 || a.jitter) path_uniforms(a.seed_lo, a.seed_hi, pix, a.sample_offset + smp, 0u, &xi1, &xi2);
     const float u = (2.0f * ((float)col + xi1) / (float)a.W - 1.0f) * a.tx;
     const float v = (1.0f - 2.0f * ((float)row + xi2) / (float)a.Hh) * a.ty;
     float d[3], n2 = 0.0f;
@@ -254,16 +260,285 @@ __global__ __launch_bounds__(256) void k_raygen_pt(RaygenPtArgs a) {
   wg_count(&a.miss_done[a.slot], valid && !inbox, &s_cnt);
 }
 
+// ---------------------------------------------------------------------------
+// Shared scenes (Sec. 3.4): Lambertian primitives and KiloNeuS instances.
+// A world ray goes to its nearest object: the closest primitive hit past
+// tpm, or the nearest instance box entered at or past tim (ties to the
+// primitive, then the lower index).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void face_ray(float n[3], const float d[3]) {
+  if (n[0] * d[0] + n[1] * d[1] + n[2] * d[2] > 0.0f)
+    for (int k = 0; k < 3; ++k) n[k] = -n[k];
+}
+
+// closest hit of primitive p past t_min: t and the normal facing the ray
+__device__ bool prim_hit(const PrimDev& p, const float o[3], const float d[3], float t_min, float* t,
+                         float n[3]) {
+  if (p.kind == 1u) {   // sphere
+    // roots of t^2 + 2 b t + c (unit d).  In float32, b^2 - c cancels near
+    // the silhouette; r^2 - |oc - b d|^2 is the same discriminant without
+    // that cancellation.  The root of larger magnitude is q = -(b + sign(b)
+    // sqrt(disc)), the other c / q (their product is c).
+    const float oc[3] = {o[0] - p.p[0], o[1] - p.p[1], o[2] - p.p[2]};
+    const float r = p.p[3];
+    const float b = oc[0] * d[0] + oc[1] * d[1] + oc[2] * d[2];
+    const float l[3] = {oc[0] - b * d[0], oc[1] - b * d[1], oc[2] - b * d[2]};
+    const float disc = r * r - (l[0] * l[0] + l[1] * l[1] + l[2] * l[2]);
+    if (disc < 0.0f) return false;
+    const float c = oc[0] * oc[0] + oc[1] * oc[1] + oc[2] * oc[2] - r * r;
+    const float q = -(b + copysignf(sqrtf(disc), b));
+    const float t2 = q != 0.0f ? c / q : q;
+    float th = fminf(q, t2);
+    if (!(th > t_min)) th = fmaxf(q, t2);
+    if (!(th > t_min)) return false;
+    *t = th;
+    for (int k = 0; k < 3; ++k) n[k] = (o[k] + th * d[k] - p.p[k]) / r;
+    face_ray(n, d);
+    return true;
+  }
+  if (p.kind == 2u) {   // axis-aligned box
+    float tn = -INFINITY, tf = INFINITY;
+    int an = -1, af = -1;
+    for (int k = 0; k < 3; ++k) {
+      if (d[k] == 0.0f) {
+        if (o[k] < p.p[k] || o[k] > p.p[3 + k]) return false;
+        continue;
+      }
+      float t1 = (p.p[k] - o[k]) / d[k], t2 = (p.p[3 + k] - o[k]) / d[k];
+      if (t1 > t2) {
+        const float x = t1;
+        t1 = t2;
+        t2 = x;
+      }
+      if (t1 > tn) {
+        tn = t1;
+        an = k;
+      }
+      if (t2 < tf) {
+        tf = t2;
+        af = k;
+      }
+    }
+    if (tn > tf) return false;
+    int ax;
+    if (tn > t_min) {
+      *t = tn;
+      ax = an;
+    } else if (tf > t_min) {
+      *t = tf;
+      ax = af;
+    } else {
+      return false;
+    }
+    if (ax < 0) return false;
+    n[0] = n[1] = n[2] = 0.0f;
+    n[ax] = d[ax] > 0.0f ? -1.0f : 1.0f;
+    return true;
+  }
+  if (p.kind == 3u) {   // triangle (Moller-Trumbore)
+    const float e1[3] = {p.p[3] - p.p[0], p.p[4] - p.p[1], p.p[5] - p.p[2]};
+    const float e2[3] = {p.p[6] - p.p[0], p.p[7] - p.p[1], p.p[8] - p.p[2]};
+    const float tv[3] = {o[0] - p.p[0], o[1] - p.p[1], o[2] - p.p[2]};
+    const float pv[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+    const float det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    if (det == 0.0f) return false;
+    const float inv = 1.0f / det;
+    const float u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+    if (u < 0.0f || u > 1.0f) return false;
+    const float qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+    const float v = (d[0] * qv[0] + d[1] * qv[1] + d[2] * qv[2]) * inv;
+    if (v < 0.0f || u + v > 1.0f) return false;
+    const float th = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+    if (!(th > t_min)) return false;
+    *t = th;
+    n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    const float nl = 1.0f / sqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int k = 0; k < 3; ++k) n[k] *= nl;
+    face_ray(n, d);
+    return true;
+  }
+  return false;
+}
+
+// camera rays of a world render (one per path) into the first world list
+__global__ __launch_bounds__(256) void k_world_raygen(WorldRaygenArgs a, uint32_t npath) {
+  const uint32_t id = blockIdx.x * 256u + threadIdx.x;
+  if (id >= npath) return;
+  const uint32_t pix = id / a.spp, smp = id % a.spp;
+  const int row = (int)(pix / (uint32_t)a.W), col = (int)(pix % (uint32_t)a.W);
+  float xi1 = 0.5f, xi2 = 0.5f;
+  if (a.pt && (a.spp > 1 || a.jitter)) path_uniforms(a.seed_lo, a.seed_hi, pix, a.sample_offset + smp, 0u, &xi1, &xi2);
+  const float u = (2.0f * ((float)col + xi1) / (float)a.W - 1.0f) * a.tx;
+  const float v = (1.0f - 2.0f * ((float)row + xi2) / (float)a.Hh) * a.ty;
+  float d[3], n2 = 0.0f;
+  for (int k = 0; k < 3; ++k) {
+    d[k] = a.fwd[k] + u * a.right[k] + v * a.up[k];
+    n2 += d[k] * d[k];
+  }
+  const float inv = 1.0f / sqrtf(n2);
+  WorldRec w;
+  for (int k = 0; k < 3; ++k) {
+    w.o[k] = a.eye[k];
+    w.d[k] = d[k] * inv;
+  }
+  w.tpm = 0.0f;
+  w.tim = 0.0f;
+  w.rid = id;
+  w.pad[0] = w.pad[1] = w.pad[2] = 0u;
+  a.out[id] = w;
+  if (a.pt) a.path[id] = PathRec{{1.0f, 1.0f, 1.0f}, {0.0f, 0.0f, 0.0f}, 0u, 0u};
+}
+
+// Each record: its next object.  A primitive hit is shaded here (primary:
+// the outputs; path tracing: albedo, scatter, and the loop goes on in this
+// thread); an escape ends the path (environment); an instance entry becomes
+// a march record of the next round, in the instance's local frame, marched
+// from the box entry to the nearer of the box exit and the primitive hit.
+__global__ __launch_bounds__(256) void k_world_step(WorldStepArgs a) {
+  __shared__ uint32_t s_cnt;
+  const uint32_t n = a.n_dev ? *a.n_dev : a.n;
+  const int lane = lane_id();
+  const ReqEnt& qr = a.tabs.reqs[0];   // world renders are one request (slot 0)
+  for (uint32_t base = blockIdx.x * 256u; base < n; base += gridDim.x * 256u) {
+    const uint32_t i = base + threadIdx.x;
+    bool spawn = false, finished = false;
+    uint32_t ncell = 0;
+    RayRec nrec{0, 0, 0, 0};
+    if (i < n) {
+      const ReqEnt q = qr;
+      WorldRec w = a.in[i];
+      const uint32_t rid = w.rid, pix = q.pt ? rid / q.spp : rid, smp = q.pt ? rid % q.spp : 0u;
+      PathRec pr;
+      if (q.pt) pr = a.tabs.path[rid];
+      for (;;) {
+        // the nearest primitive hit and instance entry
+        float tp = INFINITY, pn[3] = {0.0f, 0.0f, 0.0f};
+        int pi = -1;
+        for (uint32_t k = 0; k < a.n_prims; ++k) {
+          float th, nn[3];
+          if (prim_hit(a.prims[k], w.o, w.d, w.tpm, &th, nn) && th < tp) {
+            tp = th;
+            pi = (int)k;
+            pn[0] = nn[0];
+            pn[1] = nn[1];
+            pn[2] = nn[2];
+          }
+        }
+        float te = INFINITY, tx = 0.0f, ol[3] = {0.0f, 0.0f, 0.0f};
+        int ii = -1;
+        for (uint32_t k = 0; k < a.tabs.n_scenes; ++k) {
+          const SceneEnt& se = a.tabs.scenes[k];
+          float l[3], tn, tf;
+          for (int c = 0; c < 3; ++c) l[c] = (w.o[c] - se.wt[c]) / se.ws;
+          if (!slab(se.sg, l, w.d, &tn, &tf)) continue;
+          const float entry = se.ws * fmaxf(tn, 0.0f);
+          if (entry < w.tim || !(entry < te)) continue;
+          te = entry;
+          tx = se.ws * tf;
+          ii = (int)k;
+          ol[0] = l[0];
+          ol[1] = l[1];
+          ol[2] = l[2];
+        }
+        const bool first = !q.pt || (pr.bounce == 0 && smp == 0);
+        if (ii >= 0 && !(pi >= 0 && tp <= te)) {
+          // into instance ii: a march record for the next round
+          const SceneEnt& se = a.tabs.scenes[ii];
+          const float t0 = te / se.ws, tfar = fminf(tx, tp) / se.ws;
+          ncell = entry_cell(se.sg, ol, w.d, t0);
+          a.rs[rid] = RayStatic{ol[0], ol[1], ol[2], tfar, w.d[0], w.d[1], w.d[2], pix};
+          a.ws[rid] = WState{{w.o[0], w.o[1], w.o[2]}, w.tpm};
+          nrec = RayRec{t0, t0, ncell, rid};
+          spawn = true;
+          break;
+        }
+        if (pi < 0) {
+          // the ray escapes
+          if (q.pt) {
+            float e[3];
+            env_lookup(q.env, q.env_w, q.env_h, w.d, e);
+            for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
+          }
+          if (first) write_miss(q.out, pix, 0, 0.0f, 0.0f, -1, kBoxMiss, !q.pt);
+          finished = true;
+          break;
+        }
+        // a primitive hit
+        const PrimDev& pm = a.prims[pi];
+        if (first) {
+          const OutPtrs& out = q.out;
+          if (!q.pt) {
+            gmem(out.rgb)[3 * pix + 0] = pm.albedo[0];
+            gmem(out.rgb)[3 * pix + 1] = pm.albedo[1];
+            gmem(out.rgb)[3 * pix + 2] = pm.albedo[2];
+          }
+          if (out.depth) gmem(out.depth)[pix] = tp;
+          if (out.normal) {
+            gmem(out.normal)[3 * pix + 0] = pn[0];
+            gmem(out.normal)[3 * pix + 1] = pn[1];
+            gmem(out.normal)[3 * pix + 2] = pn[2];
+          }
+          if (out.hit) gmem(out.hit)[pix] = 1;
+          if (out.steps) gmem(out.steps)[pix] = 0;
+          if (out.trace) {
+            auto tr = gmem(out.trace + pix);
+            tr->t_march = tp;
+            tr->t_entry = tp;
+            tr->cell = -(2 + pi);
+            tr->status = kHit;
+          }
+        }
+        if (!q.pt || pr.bounce >= q.bounces) {
+          finished = true;
+          break;
+        }
+        // scatter off the primitive and go on from 1e-3 off its surface
+        for (int c = 0; c < 3; ++c) pr.T[c] *= pm.albedo[c];
+        float u1, u2, nd[3];
+        path_uniforms(q.seed_lo, q.seed_hi, pix, q.sample_offset + smp, pr.bounce + 1u, &u1, &u2);
+        cosine_dir(pn, u1, u2, nd);
+        for (int c = 0; c < 3; ++c) {
+          w.o[c] = w.o[c] + tp * w.d[c] + 1e-3f * pn[c];
+          w.d[c] = nd[c];
+        }
+        w.tpm = 0.0f;
+        w.tim = 0.0f;
+        ++pr.bounce;
+      }
+      if (q.pt) a.tabs.path[rid] = pr;
+    }
+    // one reservation per wave of exactly its spawns (the list holds at most
+    // one record per ray)
+    const uint64_t sm = __ballot(spawn);
+    const uint32_t ns = (uint32_t)__popcll(sm);
+    if (ns) {
+      uint32_t b = 0;
+      if (lane == 0) b = atomicAdd(a.n_spawn, ns);
+      b = __shfl(b, 0);
+      if (spawn) a.spawn[b + (uint32_t)__popcll(sm & lanemask_lt())] = nrec;
+    }
+    atomic_count_grouped(a.counts_next, a.cs, ncell, spawn);
+    wg_count(&a.tabs.miss_done[0], finished, &s_cnt);
+  }
+}
+
 // Path tracing: pixel = mean radiance of its samples, in sample order.
 __global__ __launch_bounds__(256) void k_resolve(ResolveArgs a) {
   const uint32_t pix = blockIdx.x * 256u + threadIdx.x;
   if (pix >= a.npix) return;
   float L[3] = {0.0f, 0.0f, 0.0f};
+  if (a.accum && a.sample_offset)
+    for (int c = 0; c < 3; ++c) L[c] = a.accum[3 * pix + c];
   for (uint32_t s = 0; s < a.spp; ++s) {
     const PathRec& pr = a.path[(size_t)pix * a.spp + s];
     for (int c = 0; c < 3; ++c) L[c] += pr.L[c];
   }
-  const float inv = 1.0f / (float)a.spp;
+  if (a.accum)
+    for (int c = 0; c < 3; ++c) a.accum[3 * pix + c] = L[c];
+  // progressive accumulation: the running sum over the calls so far
+  const float inv = 1.0f / (float)((a.accum ? a.sample_offset : 0u) + a.spp);
   for (int c = 0; c < 3; ++c) a.rgb[3 * pix + c] = L[c] * inv;
 }
 
@@ -385,6 +660,7 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
       if (lane == 0) {
         *a.n_chunks = nch;
         if (a.zero_word) *a.zero_word = 0u;
+        if (a.zero_word2) *a.zero_word2 = 0u;
         if (a.total) *a.total += br + tr;
       }
       if (lane < (uint32_t)kGroups) {
@@ -1020,6 +1296,20 @@ __device__ __forceinline__ void stage_block(float* lds, const float* src, uint32
 // tracking knows every vector memory operation before it is complete
 __device__ __forceinline__ void stage_wait() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Workgroup barrier for data in LDS only: waits for this wave's own LDS
+// operations, not for vector memory, so direct global-to-LDS loads (weight
+// staging for the next work item) stay in flight across it.  A
+// __syncthreads() here would wait for them (its release fence covers every
+// LDS write, the pending direct loads included).  The signal fences keep the
+// compiler from moving memory operations across the barrier.  Only for
+// exchanges through LDS whose writers are ordinary LDS stores.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0); vmcnt and expcnt left at their maxima
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_barrier();
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 struct CellBox {
   int ix, iy, iz;
   float c[3];
@@ -1159,7 +1449,9 @@ __device__ __forceinline__ float march_eval_h(int H, const float* blk, int lane,
 // s_st word of a staged ray: steps | exit axis << 10 | status << 12 | step budget << 16
 // PAIR: each wave evaluates two 16-ray tiles per step (shared weight reads,
 // two independent chains); otherwise one tile with more waves per SIMD (WPE).
-template <int HM, int P, bool PAIR, int WPE>
+// UNC: a variant for requests with unclamped steps (the default kernel has
+// no code for them)
+template <int HM, int P, bool PAIR, int WPE, bool UNC>
 __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   extern __shared__ __align__(16) float s_dyn[];
   float* s_t = s_dyn;
@@ -1179,9 +1471,17 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   // that thread 0 can clear the next pass's one during a pass: a slot's last
   // reader is always behind an earlier barrier)
   __shared__ uint32_t s_nact[3];
-  __shared__ uint32_t s_face[7], s_foff[7], s_njump, s_jbase;
-  __shared__ uint32_t s_nhit, s_evals, s_tiles;
-  __shared__ uint32_t s_miss[kMaxSlots];   // misses per request slot
+  // The output phase runs while the next item's weight block is being
+  // staged by direct global-to-LDS loads, and the compiler makes every LDS
+  // atomic wait for those loads to land (it cannot tell the block from the
+  // counters).  So the phase counts with wave ballots and plain LDS stores
+  // instead: per wave, the rays of each class (exit faces 0-5, staying 6,
+  // jumping 7, hits 8), and per wave and request slot the misses.
+  constexpr int kCls = 9;
+  __shared__ uint32_t s_wcnt[4][kCls];
+  __shared__ uint32_t s_foff[7], s_jbase;
+  __shared__ uint32_t s_wmiss[4][kMaxSlots];   // misses per wave and request slot
+  __shared__ unsigned long long s_wtot[4][2];  // evaluations and tiles per wave
   // the pool's scene table and each request slot's eps and step budget,
   // copied once: every work item reads them
   __shared__ SceneEnt s_scn[kMaxScenes];
@@ -1189,7 +1489,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   __shared__ uint32_t s_qmst[kMaxSlots];
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
-  unsigned long long wg_evals = 0, wg_tiles = 0, wg_chunks = 0;  // thread 0's tallies
+  unsigned long long wv_evals = 0, wv_tiles = 0, wg_chunks = 0;  // lane 0's / thread 0's tallies
   uint32_t loaded = 0xFFFFFFFFu;
   // this chunk's ray record and static data, loaded ahead during the
   // previous chunk when possible
@@ -1197,7 +1497,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   RayStatic pf_st = {0, 0, 0, 0, 0, 0, 1, 0};
   bool pf_rec_ok = false, pf_st_ok = false;
   if (tid < kMaxSlots) {
-    s_miss[tid] = 0u;
+    for (int w = 0; w < 4; ++w) s_wmiss[w][tid] = 0u;
     s_qeps[tid] = a.tabs.reqs[tid].eps;
     s_qmst[tid] = a.tabs.reqs[tid].max_steps | (a.tabs.reqs[tid].unclamped ? (kStUnclamped >> 16) : 0u);
   }
@@ -1216,12 +1516,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   // thread 0: a work item's counters start at zero
   auto clear_item = [&]() {
     s_nact[1] = 0u;
-    s_nhit = 0u;
-    s_evals = 0u;
-    s_tiles = 0u;
     s_jn[4] = 0u;
-    for (int f = 0; f < 7; ++f) s_face[f] = 0u;
-    s_njump = 0u;
   };
   if (tid == 0) {
     G = grab_init(a.grab, *a.n_chunks);
@@ -1354,8 +1649,11 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
             } else {
               const float te = fmaxf(tt, s_ce[r_]);
               if (tt + f[u] < te) {
+                // an in-cell step can pass t_far only when the interval ends
+                // inside the box (a world ray cut short by a primitive)
                 tt = tt + f[u];
-              } else if (stw & kStUnclamped) {
+                if (tt > s_tf[r_]) status = kOutExit;
+              } else if (UNC && (stw & kStUnclamped)) {
                 // Hart's full step: the ray goes on in the cell of its new point
                 tt = tt + f[u];
                 status = tt > s_tf[r_] ? kOutExit : kOutJump;
@@ -1365,8 +1663,10 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
                 const int ni = (eax == 0 ? cb.ix : (eax == 1 ? cb.iy : cb.iz)) + sgn;
                 status = (ni < 0 || ni >= N || tt > s_tf[r_]) ? kOutExit : kOutNext;
               }
-              if ((status == kStay || status == kOutNext || status == kOutJump) &&
-                  steps >= ((stw >> 16) & 1023u))
+              // (the unclamped flag above the budget is set only for the
+              // UNC kernel's requests)
+              if ((status == kStay || status == kOutNext || (UNC && status == kOutJump)) &&
+                  steps >= (UNC ? ((stw >> 16) & 1023u) : (stw >> 16)))
                 status = kOutBudget;
             }
             s_t[r_] = tt;
@@ -1410,15 +1710,13 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         loaded = nx.cell;
       }
     }
-    if (lane == 0) {
-      atomicAdd(&s_evals, wave_evals);
-      atomicAdd(&s_tiles, wave_tiles);
-    }
+    wv_evals += wave_evals;
+    wv_tiles += wave_tiles;
 
     // results: misses written out, hits appended to the hit list, rays for
     // the next round into this chunk's range of U, grouped by exit face
     // (face 6: still in this cell after max_passes)
-    uint32_t status = kOutHit, steps = 0, rank = 0, face = 0, slot = 0, dest = 0;
+    uint32_t status = kOutHit, steps = 0, face = 0, slot = 0, dest = 0, cls = kCls;
     bool miss = false;
     float t = 0.0f, t_entry = 0.0f;
     if ((uint32_t)tid < count) {
@@ -1427,7 +1725,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       steps = stw & 1023u;
       t = s_t[tid];
       t_entry = s_te[tid];
-      if (status == kOutJump) {
+      if (UNC && status == kOutJump) {
         // the cell containing the new point (cell map of Sec. 3.1, clamped)
         int idx[3];
 #pragma unroll
@@ -1437,22 +1735,42 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         }
         dest = sg.cell_base + (uint32_t)(idx[0] + N * (idx[1] + N * idx[2]));
         t_entry = t;
-        rank = atomicAdd(&s_njump, 1u);
+        cls = 7u;
       } else if (status == kOutNext || status == kStay) {
         const uint32_t eax = (stw >> 10) & 3u;
         face = status == kStay ? 6u : 2u * eax + (s_d[eax * kChunk + tid] > 0.0f ? 1u : 0u);
         if (status == kOutNext) t_entry = t;
-        rank = atomicAdd(&s_face[face], 1u);
+        cls = face;
       } else if (status == kOutHit) {
         a.hits[s_rid[tid]] = RayRec{t, t_entry, cell | (steps << kCellBits), s_rid[tid]};
-        atomicAdd(&s_nhit, 1u);
+        cls = 8u;
       } else {
         const uint32_t px = s_pix[tid];
         slot = px >> kPixBits;
         miss = true;
         const ReqEnt q = a.tabs.reqs[slot];   // copied before the first store
         const int32_t mst = status == kOutExit ? kExitMiss : kBudgetMiss;
-        if (q.pt) {
+        if (q.world && status == kOutExit) {
+          // a world ray that reached the end of its interval goes on past
+          // this instance's box
+          const uint32_t rid = s_rid[tid];
+          const float ol[3] = {s_o[tid], s_o[kChunk + tid], s_o[2 * kChunk + tid]};
+          const float d[3] = {s_d[tid], s_d[kChunk + tid], s_d[2 * kChunk + tid]};
+          float tn, tf;
+          (void)slab(sg, ol, d, &tn, &tf);
+          const WState w = a.ws[rid];
+          WorldRec wr;
+          for (int c = 0; c < 3; ++c) {
+            wr.o[c] = w.o[c];
+            wr.d[c] = d[c];
+          }
+          wr.tpm = w.tpm;
+          wr.tim = se->ws * tf;
+          wr.rid = rid;
+          wr.pad[0] = wr.pad[1] = wr.pad[2] = 0u;
+          a.wlist[atomicAdd(a.n_w, 1u)] = wr;   // world renders only
+          miss = false;
+        } else if (q.pt) {
           // the path escapes: radiance += throughput x environment
           const uint32_t rid = s_rid[tid];
           PathRec& pr = a.tabs.path[rid];
@@ -1463,7 +1781,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
           if (pr.bounce == 0 && rid % q.spp == 0)
             write_miss(q.out, px & kPixMask, (int)steps, t, t_entry, (int32_t)cell, mst, false);
           if (q.out.seg) {
-            SegRec& sr = q.out.seg[(size_t)rid * (q.bounces + 1u) + pr.bounce];
+            auto& sr = *gmem(q.out.seg + (size_t)rid * (q.bounces + 1u) + pr.bounce);
             sr.t_march = t;
             sr.t_entry = t_entry;
             sr.cell = (int32_t)cell;
@@ -1475,53 +1793,79 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
         }
       }
     }
-    if (miss) atomicAdd(&s_miss[slot], 1u);
+    // this wave's count of each class and each lane's rank in its class
+    uint32_t rank = 0;
+#pragma unroll
+    for (uint32_t c = 0; c < (uint32_t)kCls; ++c) {
+      const uint64_t m = __ballot(cls == c);
+      if (cls == c) rank = (uint32_t)__popcll(m & lanemask_lt());
+      if (lane == 0) s_wcnt[wave][c] = (uint32_t)__popcll(m);
+    }
+    // misses per request slot: one lane per slot group adds to the wave's row
+    for (uint64_t todo = __ballot(miss); todo;) {
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const uint32_t sl = (uint32_t)__builtin_amdgcn_readlane((int)slot, leader);
+      const uint64_t grp = __ballot(miss && slot == sl);
+      if (lane == leader) s_wmiss[wave][sl] += (uint32_t)__popcll(grp);
+      todo &= ~grp;
+    }
     // jumped rays are counted in their new cells for the next round
-    atomic_count_grouped(a.counts_next, a.cs, dest, status == kOutJump && (uint32_t)tid < count);
-    __syncthreads();
+    if constexpr (UNC) atomic_count_grouped(a.counts_next, a.cs, dest, status == kOutJump && (uint32_t)tid < count);
+    lds_barrier();
     if (tid == 0) {
-      if (s_njump) s_jbase = atomicAdd(a.n_jump, s_njump);
+      uint32_t tot[kCls];
+#pragma unroll
+      for (int c = 0; c < kCls; ++c) tot[c] = s_wcnt[0][c] + s_wcnt[1][c] + s_wcnt[2][c] + s_wcnt[3][c];
+      if (UNC && tot[7]) s_jbase = atomicAdd(a.n_jump, tot[7]);
       uint32_t off = 0;
       for (int f = 0; f < 7; ++f) {
         s_foff[f] = off;
-        off += s_face[f];
+        off += tot[f];
       }
-      a.chunk_out[4 * job] = make_uint4(s_face[0], s_face[1], s_face[2], s_face[3]);
-      a.chunk_out[4 * job + 1] = make_uint4(s_face[4], s_face[5], s_face[6], s_nhit);
-      if (s_nhit) atomicAdd(&a.hit_count[(size_t)cell * a.cs], s_nhit);
-      wg_evals += s_evals;
-      wg_tiles += s_tiles;
+      a.chunk_out[4 * job] = make_uint4(tot[0], tot[1], tot[2], tot[3]);
+      a.chunk_out[4 * job + 1] = make_uint4(tot[4], tot[5], tot[6], tot[8]);
+      if (tot[8]) atomicAdd(&a.hit_count[(size_t)cell * a.cs], tot[8]);
       ++wg_chunks;
     } else if (tid <= 7) {
       // run f = tid - 1 reserves its place in the destination cell's next bin
       // (an empty run adds 0 to this cell); the offset is stored during the
       // next work item, after a wait that staging makes anyway, so the
       // atomic's round trip is never waited for on its own
-      const uint32_t f = (uint32_t)tid - 1u, n = s_face[f];
+      const uint32_t f = (uint32_t)tid - 1u, n = s_wcnt[0][f] + s_wcnt[1][f] + s_wcnt[2][f] + s_wcnt[3][f];
       pend_off = atomicAdd(&a.runs_next[(size_t)(n ? neighbor_cell(sg, cell, (int)f) : cell) * a.cs], n);
       pend_job = job;
     }
-    __syncthreads();
-    if ((uint32_t)tid < count) {
-      if (status == kOutNext || status == kStay)
+    lds_barrier();
+    if (cls < 8u) {
+      // rank among the item's rays of this class: the waves before this one first
+      for (int w = 0; w < wave; ++w) rank += s_wcnt[w][cls];
+      if (cls < 7u)
         a.U[start + s_foff[face] + rank] =
             RayRec{t, t_entry, neighbor_cell(sg, cell, (int)face) | (steps << kCellBits), s_rid[tid]};
-      else if (status == kOutJump)
+      else if (UNC)
         a.jump[s_jbase + rank] = RayRec{t, t_entry, dest | (steps << kCellBits), s_rid[tid]};
     }
     if (tid == 0) {   // the next work item, and its counters cleared
       for (int i = 0; i < 6; ++i) s_job[i] = s_jn[i];
       clear_item();
     }
-    __syncthreads();
+    lds_barrier();
   }
   if (tid >= 1 && tid <= 7 && pend_job != kNoJob)
     reinterpret_cast<uint32_t*>(a.chunk_out)[16u * pend_job + 8u + (uint32_t)tid - 1u] = pend_off;
-  if (tid < kMaxSlots && s_miss[tid]) atomicAdd(&a.tabs.miss_done[tid], s_miss[tid]);
+  if (lane == 0) {
+    s_wtot[wave][0] = wv_evals;
+    s_wtot[wave][1] = wv_tiles;
+  }
+  __syncthreads();
+  if (tid < kMaxSlots) {
+    const uint32_t m = s_wmiss[0][tid] + s_wmiss[1][tid] + s_wmiss[2][tid] + s_wmiss[3][tid];
+    if (m) atomicAdd(&a.tabs.miss_done[tid], m);
+  }
   if (tid == 0 && wg_chunks) {   // this workgroup's line of the tallies
     unsigned long long* ev = a.evals + (size_t)(blockIdx.x % kTallyLines) * 16u;
-    atomicAdd(&ev[0], wg_evals);
-    atomicAdd(&ev[1], wg_tiles);
+    atomicAdd(&ev[0], s_wtot[0][0] + s_wtot[1][0] + s_wtot[2][0] + s_wtot[3][0]);
+    atomicAdd(&ev[1], s_wtot[0][1] + s_wtot[1][1] + s_wtot[2][1] + s_wtot[3][1]);
     atomicAdd(&ev[2], wg_chunks);
   }
 }
@@ -1837,13 +2181,13 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
         c2 = mfma_f32(cfr[(24 + q) * 64 + lane], fmaxf(c1[q / 4][q % 4], 0.0f), c2);
       const bool writer = valid && g == 0 && value_col;
       const uint32_t slot = st.pix >> kPixBits;
-      bool done = writer, spawn = false;
+      bool done = writer, spawn = false, wgo = false;
       uint32_t ncell = 0;
       RayRec nrec{0, 0, 0, 0};
       if (writer) {
         // copied before the first store, so all its fields load together
         // (a store through an output pointer could otherwise alias the table)
-        const ReqEnt q = a.tabs.reqs[slot];
+        ReqEnt q = a.tabs.reqs[slot];
         const OutPtrs& out = q.out;
         const uint32_t px = st.pix & kPixMask;
         const float rgb[3] = {sigmoid(c2[0]), sigmoid(c2[1]), sigmoid(c2[2])};
@@ -1854,13 +2198,14 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           pr = a.tabs.path[r.rid];
           smp = r.rid % q.spp;
           aux = pr.bounce == 0 && smp == 0;
+          if (q.world) q.out.seg = nullptr;   // no segment records in worlds
         } else {
           gmem(out.rgb)[3 * px + 0] = rgb[0];
           gmem(out.rgb)[3 * px + 1] = rgb[1];
           gmem(out.rgb)[3 * px + 2] = rgb[2];
         }
         if (aux) {
-          if (out.depth) gmem(out.depth)[px] = t;
+          if (out.depth) gmem(out.depth)[px] = se->ws * t;   // world distance (ws = 1 outside worlds)
           if (out.normal) {
             gmem(out.normal)[3 * px + 0] = n[0];
             gmem(out.normal)[3 * px + 1] = n[1];
@@ -1868,11 +2213,17 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
           }
           if (out.hit) gmem(out.hit)[px] = 1;
           if (out.steps) gmem(out.steps)[px] = (uint16_t)(r.key >> kCellBits);
-          if (out.trace) out.trace[px] = TraceRec{r.t, r.t_entry, (int32_t)cell, kHit};
+          if (out.trace) {
+            auto tr = gmem(out.trace + px);
+            tr->t_march = r.t;
+            tr->t_entry = r.t_entry;
+            tr->cell = (int32_t)cell;
+            tr->status = kHit;
+          }
         }
         if constexpr (PT) {
           if (out.seg) {
-            SegRec& sr = out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce];
+            auto& sr = *gmem(out.seg + (size_t)r.rid * (q.bounces + 1u) + pr.bounce);
             sr.t_march = r.t;
             sr.t_entry = r.t_entry;
             sr.t = t;
@@ -1889,19 +2240,35 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
             // segment starts 1e-3 off the surface
             for (int c = 0; c < 3; ++c) pr.T[c] *= rgb[c];
             float u1, u2, nd[3], no[3];
-            path_uniforms(q.seed_lo, q.seed_hi, px, smp, pr.bounce + 1u, &u1, &u2);
+            path_uniforms(q.seed_lo, q.seed_hi, px, q.sample_offset + smp, pr.bounce + 1u, &u1, &u2);
             cosine_dir(n, u1, u2, nd);
-            for (int c = 0; c < 3; ++c) no[c] = o[c] + t * d[c] + 1e-3f * n[c];
             ++pr.bounce;
+            if (q.world) {
+              // the path goes on in the world from 1e-3 (world units) off the surface
+              WorldRec wr;
+              for (int c = 0; c < 3; ++c) {
+                wr.o[c] = se->wt[c] + se->ws * (o[c] + t * d[c]) + 1e-3f * n[c];
+                wr.d[c] = nd[c];
+              }
+              wr.tpm = 0.0f;
+              wr.tim = 0.0f;
+              wr.rid = r.rid;
+              wr.pad[0] = wr.pad[1] = wr.pad[2] = 0u;
+              a.wlist[atomicAdd(a.n_w, 1u)] = wr;   // world renders only
+              wgo = true;
+              done = false;
+            }
+            for (int c = 0; c < 3; ++c) no[c] = o[c] + t * d[c] + 1e-3f * n[c];
             if (out.seg) {
-              SegRec& sn = out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce];
+              auto& sn = *gmem(out.seg + (size_t)r.rid * (q.bounces + 1u) + pr.bounce);
               for (int c = 0; c < 3; ++c) {
                 sn.o[c] = no[c];
                 sn.d[c] = nd[c];
               }
             }
             float t0, tf;
-            if (slab(sg, no, nd, &t0, &tf)) {
+            if (wgo) {
+            } else if (slab(sg, no, nd, &t0, &tf)) {
               ncell = entry_cell(sg, no, nd, t0);
               a.rs[r.rid] = RayStatic{no[0], no[1], no[2], tf, nd[0], nd[1], nd[2], st.pix};
               nrec = RayRec{t0, t0, ncell, r.rid};
@@ -1911,7 +2278,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
               float e[3];
               env_lookup(q.env, q.env_w, q.env_h, nd, e);
               for (int c = 0; c < 3; ++c) pr.L[c] += pr.T[c] * e[c];
-              if (out.seg) out.seg[(size_t)r.rid * (q.bounces + 1u) + pr.bounce].status = kBoxMiss;
+              if (out.seg) gmem(out.seg + (size_t)r.rid * (q.bounces + 1u) + pr.bounce)->status = kBoxMiss;
             }
           }
           a.tabs.path[r.rid] = pr;
@@ -2272,7 +2639,14 @@ size_t shade_lds_bytes(uint32_t block_words) { return ((size_t)block_words + 4u 
 
 template <int HM, int P, bool PAIR, int WPE>
 static hipError_t march_t(const MarchArgs& a, uint32_t block_words, uint32_t grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_march<HM, P, PAIR, WPE>), dim3(grid), dim3(256), march_lds_bytes(block_words), st, a);
+  const size_t lds = march_lds_bytes(block_words);
+  if (!a.jump) {
+    hipLaunchKernelGGL((k_march<HM, P, PAIR, WPE, false>), dim3(grid), dim3(256), lds, st, a);
+  } else {
+    // unclamped steps: kn_render only (one request, H 32 or 64)
+    if constexpr (HM == 0) return hipErrorInvalidValue;
+    else hipLaunchKernelGGL((k_march<HM, P, PAIR, WPE, true>), dim3(grid), dim3(256), lds, st, a);
+  }
   return hipGetLastError();
 }
 
@@ -2416,6 +2790,17 @@ hipError_t launch_eik_combine(const EikArgs& a, hipStream_t st) {
   const uint32_t nb = (uint32_t)((a.n + 255u) / 256u);
   hipLaunchKernelGGL(k_eik_combine, dim3(nb), dim3(256), 0, st, a);
   hipLaunchKernelGGL(k_eik_loss, dim3(1), dim3(256), 0, st, a, nb);
+  return hipGetLastError();
+}
+
+hipError_t launch_world_raygen(const WorldRaygenArgs& a, uint32_t npath, hipStream_t st) {
+  hipLaunchKernelGGL(k_world_raygen, dim3((npath + 255u) / 256u), dim3(256), 0, st, a, npath);
+  return hipGetLastError();
+}
+
+hipError_t launch_world_step(const WorldStepArgs& a, uint32_t grid, hipStream_t st) {
+  if (a.cs == 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_world_step, dim3(grid), dim3(256), 0, st, a);
   return hipGetLastError();
 }
 

@@ -26,6 +26,32 @@ struct SceneEnt {
   const float* march;      // march blocks in the pool's precision
   const float* shade;      // float32 shading blocks
   SoftplusK spk;
+  float wt[3], ws;         // instance placement in a world: x = wt + ws x_local (identity otherwise)
+};
+
+// A ray of a world render waiting for its next object (world coordinates).
+struct WorldRec {
+  float o[3];
+  float tpm;               // primitives count from t > tpm
+  float d[3];
+  float tim;               // instance boxes entered at t >= tim
+  uint32_t rid;
+  uint32_t pad[3];
+};
+static_assert(sizeof(WorldRec) == 48, "world records are 48 bytes");
+
+// Per pool ray of a world render: the world origin of its current segment
+// and that segment's primitive bound, for its continuation past the box.
+struct WState {
+  float o[3];
+  float tpm;
+};
+
+// A Lambertian primitive on the device (kn_primitive).
+struct PrimDev {
+  uint32_t kind;
+  float p[9];
+  float albedo[3];
 };
 
 // One request slot of a ray pool (a frame being rendered).
@@ -40,6 +66,8 @@ struct ReqEnt {
   const float* env;        // [env_h][env_w][3] or null (black)
   uint32_t env_w, env_h;
   uint32_t unclamped;      // 1: Hart's unclamped steps (the next cell is the one containing the new point)
+  uint32_t world;          // 1: a world render (misses past a box and scatters continue in the world)
+  uint32_t sample_offset;  // path tracing: index of the call's first sample in each pixel's stream
 };
 
 // Tables shared by the kernels of a pool.
@@ -77,6 +105,8 @@ struct RaygenPtArgs {
   uint32_t seed_lo, seed_hi;
   const float* env;
   uint32_t env_w, env_h;
+  uint32_t jitter;         // pixel jitter at spp = 1 too (progressive accumulation)
+  uint32_t sample_offset;
   uint32_t slot;
   RayStatic* rs;
   RayRec* U;               // one record per path (index = pool ray id)
@@ -91,6 +121,8 @@ struct ResolveArgs {
   const PathRec* path;
   uint32_t npix, spp;
   float* rgb;
+  float* accum;          // progressive accumulation (or null)
+  uint32_t sample_offset;
 };
 
 struct ScanArgs {
@@ -103,6 +135,7 @@ struct ScanArgs {
   uint32_t* grab;        // out: per-range work cursors (kGroups x kGroupStride words)
   uint32_t* grab0;       // out: a copy of the initial cursors (to restart a pass)
   uint32_t* zero_word;   // optional counter reset to 0
+  uint32_t* zero_word2;  // a second one
   uint32_t* total;       // optional: the sum of the counts is added to it
   uint32_t* runs;        // optional: per-cell rays handed on by the previous round's chunks,
                          // binned first (read; zeroed if zero_counts)
@@ -154,6 +187,10 @@ struct MarchArgs {
   RayRec* jump;              // next round's jumped rays
   uint32_t* n_jump;          // their count
   uint32_t* counts_next;     // arrivals per cell for the next round (cell c at c * cs)
+  // world renders: rays that leave an instance's box go on from here
+  WorldRec* wlist;
+  uint32_t* n_w;
+  const WState* ws;
 };
 
 struct ShadeArgs {
@@ -166,6 +203,37 @@ struct ShadeArgs {
   RayRec* spawn;         // path tracing: records of the next segments
   uint32_t* n_spawn;     // their count
   uint32_t* counts_next; // arrivals per cell for the next round (cell c at c * cs)
+  uint32_t cs;
+  WorldRec* wlist;       // world renders: scattered rays go on from here
+  uint32_t* n_w;
+};
+
+// world renders: camera rays (one per path) into a world list
+struct WorldRaygenArgs {
+  float eye[3], fwd[3], right[3], up[3];
+  float tx, ty;
+  int W, Hh;
+  uint32_t spp, jitter, sample_offset;
+  uint32_t seed_lo, seed_hi;
+  bool pt;
+  PathRec* path;
+  WorldRec* out;         // [paths], index = path id
+};
+
+// world renders: each record's next object; primitive hits are shaded (and
+// scattered, path tracing) here, instance entries become march records
+struct WorldStepArgs {
+  PoolTabs tabs;         // instances = the pool's scene entries
+  const PrimDev* prims;
+  uint32_t n_prims;
+  const WorldRec* in;
+  uint32_t n;            // records, or
+  const uint32_t* n_dev; // if not null: their count, read on the device
+  RayStatic* rs;
+  WState* ws;
+  RayRec* spawn;         // march records of the next round
+  uint32_t* n_spawn;
+  uint32_t* counts_next;
   uint32_t cs;
 };
 
@@ -221,6 +289,8 @@ struct EikArgs {
 hipError_t launch_raygen(const RaygenArgs& a, hipStream_t st);
 hipError_t launch_raygen_pt(const RaygenPtArgs& a, hipStream_t st);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t st);
+hipError_t launch_world_raygen(const WorldRaygenArgs& a, uint32_t npath, hipStream_t st);
+hipError_t launch_world_step(const WorldStepArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t st);
 hipError_t launch_scatter(const ScatterArgs& a, uint32_t grid, hipStream_t st);
 hipError_t launch_scatter_chunks(const ScatterChunksArgs& a, uint32_t grid, hipStream_t st);

@@ -4,6 +4,7 @@
 #include <link.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <chrono>
 #include <cmath>
@@ -335,6 +336,20 @@ struct KnScene {
   uint32_t shading_words(int prec) const { return prec == KN_FP32 ? shade_words : shade3_words; }
   size_t bytes = 0;
   std::atomic<int> refs{0};
+  int world_refs = 0;      // worlds that place this scene (under kn_ctx::mu)
+};
+
+// A world (shared scenes): instances of resident scenes and primitives on
+// the device.
+struct KnWorld {
+  kn_world_id id = 0;
+  std::vector<kn_instance> inst;
+  std::vector<KnScene*> scenes;    // per instance
+  PrimDev* prims = nullptr;        // [n_prims] on the device
+  uint32_t n_prims = 0;
+  uint32_t cells = 0;              // global cells of the instances
+  size_t bytes = 0;
+  std::atomic<int> refs{0};
 };
 
 // Device buffers of a ray pool: up to `cap` rays (ids 0..cap-1) over
@@ -349,6 +364,8 @@ struct Pool {
   PathRec* path = nullptr;         // path tracing state (allocated on first use)
   RayRec* J = nullptr;             // [2][cap]: rays of unclamped steps that jumped cells, per
                                    // round parity (allocated on first use)
+  WorldRec* W = nullptr;           // [2][cap]: world renders, rays waiting for their next object
+  WState* WS = nullptr;            // [cap]: world renders, each ray's segment origin
   // per-cell counters, cell c at word c * cs: on grids of up to
   // kPadCells cells each counter has a 128-byte line of its own
   uint32_t cs = 1;
@@ -424,12 +441,14 @@ struct kn_ctx {
   std::mutex serve_mu;        // serving loop start / stop
   std::map<kn_scene_id, KnScene*> scenes;
   kn_scene_id next_id = 1;
+  std::map<kn_world_id, KnWorld*> worlds;   // under mu
+  kn_world_id next_world = 1;
   std::atomic<bool> poisoned{false};
   Pool ws;                     // the workspace of kn_render and kn_query
   void* aux = nullptr;         // grow-only work buffer of kn_eikonal_fd
   size_t aux_bytes = 0;
   uint32_t* pinned = nullptr;  // round counters read back by the host
-  SceneEnt* h_scene = nullptr; // pinned staging of kn_render's tables
+  SceneEnt* h_scene = nullptr; // pinned staging of kn_render's tables ([kMaxScenes])
   ReqEnt* h_req = nullptr;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
   hipEvent_t ev_round[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -470,7 +489,7 @@ constexpr int kPinnedScanErr = 16;
 constexpr int kPinnedScanErrNoAlloc = 17;
 
 void free_pool(Pool& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.J, w.counts, w.runs, w.hit_count, w.cursor, w.base,
+  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.J, w.W, w.WS, w.counts, w.runs, w.hit_count, w.cursor, w.base,
                   w.chunk, w.chunk_out, w.ctrl, w.scenes, w.reqs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
@@ -507,14 +526,15 @@ size_t pool_bytes(size_t R, size_t C, size_t K) {
 // grow-only pool for `rays` records over `cells` cells (with path state if
 // `paths`)
 kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool paths = false,
-                      bool jumps = false) {
+                      bool jumps = false, bool world = false) {
   const size_t chunks = rays / kShadeChunk + cells + 2;
   if (w.ctrl && w.cap >= rays && w.cells >= cells && w.chunks >= chunks && (!paths || w.path) &&
-      (!jumps || w.J))
+      (!jumps || w.J) && (!world || w.W))
     return KN_OK;
   const size_t R = std::max(w.cap, rays), C = std::max(w.cells, cells), K = std::max(w.chunks, chunks);
-  const bool P = paths || w.path, J = jumps || w.J;
-  const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0) + (J ? 2 * R * sizeof(RayRec) : 0);
+  const bool P = paths || w.path || world, J = jumps || w.J, Wd = world || w.W;
+  const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0) + (J ? 2 * R * sizeof(RayRec) : 0) +
+                       (Wd ? R * (2 * sizeof(WorldRec) + sizeof(WState)) : 0);
   const uint64_t other = ctx->used.load() - w.bytes;
   if (other + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "ray workspace of %zu bytes exceeds the HBM budget", bytes);
@@ -537,6 +557,10 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
   KN_HIP(ctx, hipMalloc(&n.HL, R * sizeof(RayRec)));
   if (P) KN_HIP(ctx, hipMalloc(&n.path, R * sizeof(PathRec)));
   if (J) KN_HIP(ctx, hipMalloc(&n.J, 2 * R * sizeof(RayRec)));
+  if (Wd) {
+    KN_HIP(ctx, hipMalloc(&n.W, 2 * R * sizeof(WorldRec)));
+    KN_HIP(ctx, hipMalloc(&n.WS, R * sizeof(WState)));
+  }
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * n.cs * 4));
@@ -600,6 +624,8 @@ SceneEnt scene_entry(const KnScene* s, int prec, uint32_t cell_base, bool split)
   e.shade = s->shading(shade_prec);
   e.shade_words = s->shading_words(shade_prec);
   e.spk = softplus_consts(s->geom.beta);
+  e.wt[0] = e.wt[1] = e.wt[2] = 0.0f;
+  e.ws = 1.0f;
   return e;
 }
 
@@ -620,6 +646,9 @@ struct RoundCfg {
   bool jumps;             // unclamped steps: rays that jump cells go through Pool::J
   uint32_t cells;         // global cells in use
   int max_passes;
+  int wpar = -1;          // world renders: the world list (parity) that rays leaving a box
+                          // go to this round; -1 otherwise
+  bool wzero = false;     // ... and this round's scan clears that list's count first
 };
 
 // Round r: bins the records arriving for it (the previous round's leavers,
@@ -647,6 +676,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   sa.err = &w.ctrl->scan_err;
   // the march of this round appends the rays that jump cells to J[par ^ 1]
   sa.zero_word = c.jumps ? &w.ctrl->n_jump[par ^ 1] : nullptr;
+  sa.zero_word2 = c.wpar >= 0 && c.wzero ? &w.ctrl->n_w[c.wpar] : nullptr;
   sa.total = nullptr;
   KN_HIP(ctx, launch_scan(sa, st));
   if (r > 0) {
@@ -690,6 +720,11 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
     ma.jump = w.J + (size_t)(par ^ 1) * w.cap;
     ma.n_jump = &w.ctrl->n_jump[par ^ 1];
     ma.counts_next = w.counts + (par ^ 1) * w.cells * w.cs;
+  }
+  if (c.wpar >= 0) {
+    ma.wlist = w.W + (size_t)c.wpar * w.cap;
+    ma.n_w = &w.ctrl->n_w[c.wpar];
+    ma.ws = w.WS;
   }
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
   // the grid is what the CUs hold at once: bf16 and fp8 march kernels 3
@@ -740,6 +775,10 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
   sh.n_spawn = &w.ctrl->n_in;
   sh.counts_next = w.counts + (next_round & 1) * w.cells * w.cs;
   sh.cs = w.cs;
+  if (c.wpar >= 0) {
+    sh.wlist = w.W + (size_t)c.wpar * w.cap;
+    sh.n_w = &w.ctrl->n_w[c.wpar];
+  }
   if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
   KN_HIP(ctx, launch_shade(sh, c.hmode, c.split ? c.prec : (int)KN_FP32, pt, c.shade_words,
                            persistent_grid(ctx, 3), st));
@@ -785,7 +824,7 @@ kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out)
   ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)freeb);
   KN_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault));
-  KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_scene, sizeof(SceneEnt), hipHostMallocDefault));
+  KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_scene, kMaxScenes * sizeof(SceneEnt), hipHostMallocDefault));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_req, sizeof(ReqEnt), hipHostMallocDefault));
   KN_HIP(ctx, hipEventCreate(&ctx->ev_start));
   KN_HIP(ctx, hipEventCreate(&ctx->ev_end));
@@ -799,6 +838,10 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
   if (ctx->serve) kn_serve_stop(ctx);
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  for (auto& kv : ctx->worlds) {
+    if (kv.second->prims) (void)hipFree(kv.second->prims);
+    delete kv.second;
+  }
   for (auto& kv : ctx->scenes) {
     KnScene* s = kv.second;
     if (s->march_f32) (void)hipFree(s->march_f32);
@@ -939,6 +982,7 @@ kn_status kn_scene_destroy(kn_ctx* ctx, kn_scene_id id) {
   if (it == ctx->scenes.end()) return fail(KN_E_NOT_FOUND, "scene %u not found", id);
   KnScene* s = it->second;
   if (s->refs.load() > 0) return fail(KN_E_BUSY, "scene %u has requests in flight", id);
+  if (s->world_refs > 0) return fail(KN_E_BUSY, "scene %u is placed in %d world(s)", id, s->world_refs);
   std::lock_guard<std::mutex> rk(ctx->render_mu);
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
@@ -989,7 +1033,10 @@ kn_status validate_camera(const kn_camera* c, const KnScene* s) {
     return fail(KN_E_INVALID, "unknown precision %d", (int)c->precision);
   if (c->flags & ~(uint32_t)(KN_CAMERA_SPLIT_BF16_SHADING | KN_CAMERA_UNCLAMPED_STEPS))
     return fail(KN_E_INVALID, "unknown camera flags 0x%x", c->flags);
-  if (!s->march(c->precision))
+  if (c->sample_offset && c->bounces == 0)
+    return fail(KN_E_INVALID, "sample_offset needs path tracing (bounces >= 1)");
+  if (c->sample_offset > (1u << 30)) return fail(KN_E_INVALID, "sample_offset %u above 2^30", c->sample_offset);
+  if (s && !s->march(c->precision))
     return fail(KN_E_INVALID, "scene has no copy in precision %d (set its bit in precisions)",
                 (int)c->precision);
   if (c->tan_half_diag < 0.0f || !std::isfinite(c->tan_half_diag))
@@ -1006,6 +1053,13 @@ kn_status validate_camera(const kn_camera* c, const KnScene* s) {
                         f[0] * c->up[1] - f[1] * c->up[0]};
   if (!(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] > 1e-12 * dist2))
     return fail(KN_E_INVALID, "up is parallel to the view direction");
+  return KN_OK;
+}
+
+kn_status validate_frame(const kn_frame* fr, const kn_camera* c) {
+  if (!fr || !fr->rgb) return fail(KN_E_INVALID, "frame or frame->rgb is NULL");
+  if (fr->accum && c->bounces == 0)
+    return fail(KN_E_UNSUPPORTED, "progressive accumulation needs path tracing (bounces >= 1)");
   return KN_OK;
 }
 
@@ -1156,6 +1210,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   q.env_w = c->env_w;
   q.env_h = c->env_h;
   q.unclamped = jumps ? 1u : 0u;
+  q.sample_offset = pt ? c->sample_offset : 0u;
   *ctx->h_req = q;
   const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, split,
                      jumps, (uint32_t)cells, ctx->max_passes};
@@ -1252,6 +1307,8 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     rp.env = q.env;
     rp.env_w = q.env_w;
     rp.env_h = q.env_h;
+    rp.jitter = fr->accum ? 1u : 0u;
+    rp.sample_offset = q.sample_offset;
     rp.slot = 0;
     rp.rs = w.rs;
     rp.U = w.Uin;
@@ -1291,7 +1348,215 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
       if ((st = check_scan(ctx, ctx->pinned[2])) != KN_OK) return st;
       if (ctx->pinned[0] == 0 && ctx->pinned[1] == 0) break;
     }
-    ResolveArgs ra{w.path, (uint32_t)npix, spp, fr->rgb};
+    ResolveArgs ra{w.path, (uint32_t)npix, spp, fr->rgb, fr->accum, q.sample_offset};
+    KN_HIP(ctx, launch_resolve(ra, stream));
+  }
+  KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
+  KN_HIP(ctx, hipEventRecord(ctx->ev_end, stream));
+  KN_HIP(ctx, hipEventSynchronize(ctx->ev_end));
+  if ((st = check_scan(ctx, ctx->pinned[kPinnedScanErr])) != KN_OK) return st;
+  if (stats) {
+    Ctrl hc;
+    KN_HIP(ctx, hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    float ms = 0.0f;
+    KN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_end));
+    stats->gpu_ms = ms;
+    stats->wall_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - wall0).count();
+    stats->rays = rays;
+    stats->evals = stats->march_tiles = stats->march_chunks = 0;
+    for (uint32_t l = 0; l < kTallyLines; ++l) {
+      stats->evals += hc.tally[l][0];
+      stats->march_tiles += hc.tally[l][1];
+      stats->march_chunks += hc.tally[l][2];
+    }
+    stats->hits = hc.n_hits;
+    stats->rounds = (uint64_t)rounds;
+    stats->march_launches = 0;
+    stats->march_ms = stats->shade_ms = 0.0;
+    if (timed) {
+      for (auto& pr : march_ev) {
+        float kms = 0.0f;
+        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[pr.first], ctx->ev_kernel[pr.second]));
+        stats->march_ms += kms;
+      }
+      for (auto& pr : shade_ev) {
+        float kms = 0.0f;
+        KN_HIP(ctx, hipEventElapsedTime(&kms, ctx->ev_kernel[pr.first], ctx->ev_kernel[pr.second]));
+        stats->shade_ms += kms;
+      }
+      stats->march_launches = (uint32_t)march_ev.size();
+    }
+  }
+  return KN_OK;
+}
+
+
+// Enqueues and runs one frame of a world (Sec. 3.4, shared scenes) on
+// `stream`; the caller holds render_mu.  The instances are the pool's scene
+// table (one global cell range each).  Camera rays start in a world list;
+// k_world_step takes each ray to its next object: primitive hits are shaded
+// (and, path tracing, scattered) there, instance entries become march
+// records of the next round.  Groups of rounds follow, each closed by a
+// shading pass; rays that leave an instance's box, and paths scattered off
+// instance surfaces, go to the group's world list, which the next
+// k_world_step takes.
+kn_status render_world(kn_ctx* ctx, KnWorld* wd, const kn_camera* c, const kn_frame* fr, hipStream_t stream,
+                       kn_stats* stats) {
+  const auto wall0 = std::chrono::steady_clock::now();
+  const bool pt = c->bounces > 0;
+  const uint32_t spp = pt ? c->spp : 1u;
+  const size_t npix = (size_t)c->width * c->height;
+  const size_t rays = npix * spp;
+  const bool jumps = (c->flags & KN_CAMERA_UNCLAMPED_STEPS) != 0;
+  const bool split = (c->flags & KN_CAMERA_SPLIT_BF16_SHADING) && c->precision != KN_FP32;
+  const uint32_t n_inst = (uint32_t)wd->inst.size();
+  int hmode = -1;
+  uint32_t mw = 0, shw = 0, cells = 0;
+  for (uint32_t k = 0; k < n_inst; ++k) {
+    const KnScene* sc = wd->scenes[k];
+    SceneEnt e = scene_entry(sc, (int)c->precision, cells, split);
+    for (int a = 0; a < 3; ++a) e.wt[a] = wd->inst[k].translate[a];
+    e.ws = wd->inst[k].scale;
+    ctx->h_scene[k] = e;
+    cells = e.cell_end;
+    hmode = hmode < 0 ? sc->H : (hmode == sc->H ? hmode : 0);
+    mw = std::max(mw, e.march_words);
+    shw = std::max(shw, e.shade_words);
+  }
+  if (hmode < 0) hmode = 64;   // no instances: the rounds find no work
+  if (jumps && hmode == 0)
+    return fail(KN_E_UNSUPPORTED, "unclamped steps need instances of one MLP width");
+  const uint32_t gcells = std::max<uint32_t>(cells, 1u);
+  kn_status st = ensure_pool(ctx, ctx->ws, rays, gcells, pt, jumps, true);
+  if (st != KN_OK) return st;
+  Pool& w = ctx->ws;
+  ReqEnt q{};
+  q.out = out_ptrs(fr);
+  q.out.seg = nullptr;   // no segment records in worlds
+  q.eps = c->eps;
+  q.max_steps = c->max_steps;
+  q.npix = (uint32_t)npix;
+  q.pt = pt ? 1u : 0u;
+  q.spp = spp;
+  q.bounces = c->bounces;
+  q.seed_lo = (uint32_t)c->seed;
+  q.seed_hi = (uint32_t)(c->seed >> 32);
+  q.env = c->env_rgb;
+  q.env_w = c->env_w;
+  q.env_h = c->env_h;
+  q.unclamped = jumps ? 1u : 0u;
+  q.world = 1u;
+  q.sample_offset = pt ? c->sample_offset : 0u;
+  *ctx->h_req = q;
+  RoundCfg cfg{hmode, (int)c->precision, n_inst, mw, shw, split, jumps, gcells, ctx->max_passes};
+
+  const bool timed = stats && stats->kernel_times;
+  std::vector<std::pair<int, int>> march_ev, shade_ev;
+  size_t next_ev = 0;
+  auto ev = [&](hipEvent_t* e) -> kn_status {
+    if (!timed) {
+      *e = nullptr;
+      return KN_OK;
+    }
+    if (next_ev == ctx->ev_kernel.size()) {
+      hipEvent_t x;
+      KN_HIP(ctx, hipEventCreate(&x));
+      ctx->ev_kernel.push_back(x);
+    }
+    *e = ctx->ev_kernel[next_ev++];
+    return KN_OK;
+  };
+  hipEvent_t e0, e1;
+
+  KN_HIP(ctx, hipEventRecord(ctx->ev_start, stream));
+  if (n_inst)
+    KN_HIP(ctx, hipMemcpyAsync(w.scenes, ctx->h_scene, n_inst * sizeof(SceneEnt), hipMemcpyHostToDevice, stream));
+  KN_HIP(ctx, hipMemcpyAsync(w.reqs, ctx->h_req, sizeof(ReqEnt), hipMemcpyHostToDevice, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.ctrl, 0, sizeof(Ctrl), stream));
+  KN_HIP(ctx, hipMemsetAsync(w.counts, 0, 2 * w.cells * w.cs * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.runs, 0, 2 * w.cells * w.cs * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * w.cs * 4, stream));
+  KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
+
+  RaygenArgs rg{};
+  camera_basis(c, rg);
+  WorldRaygenArgs wr{};
+  for (int k = 0; k < 3; ++k) {
+    wr.eye[k] = rg.eye[k];
+    wr.fwd[k] = rg.fwd[k];
+    wr.right[k] = rg.right[k];
+    wr.up[k] = rg.up[k];
+  }
+  wr.tx = rg.tx;
+  wr.ty = rg.ty;
+  wr.W = (int)c->width;
+  wr.Hh = (int)c->height;
+  wr.spp = spp;
+  wr.jitter = fr->accum ? 1u : 0u;
+  wr.sample_offset = q.sample_offset;
+  wr.seed_lo = q.seed_lo;
+  wr.seed_hi = q.seed_hi;
+  wr.pt = pt;
+  wr.path = w.path;
+  wr.out = w.W + w.cap;   // list 1: group 0 appends to list 0
+  KN_HIP(ctx, launch_world_raygen(wr, (uint32_t)rays, stream));
+
+  WorldStepArgs ws{};
+  ws.tabs = pool_tabs(w, n_inst);
+  ws.prims = wd->prims;
+  ws.n_prims = wd->n_prims;
+  ws.rs = w.rs;
+  ws.ws = w.WS;
+  ws.spawn = w.Uin;
+  ws.n_spawn = &w.ctrl->n_in;
+  ws.cs = w.cs;
+  // k_world_step over `n` records of list `in` (or *n_dev of them), into the
+  // march records of round r
+  auto world_step = [&](int list, uint32_t n, const uint32_t* n_dev, int r) -> kn_status {
+    KN_HIP(ctx, launch_fill_u32(&w.ctrl->n_in, 1, 0u, stream));
+    ws.in = w.W + (size_t)list * w.cap;
+    ws.n = n;
+    ws.n_dev = n_dev;
+    ws.counts_next = w.counts + (size_t)(r & 1) * w.cells * w.cs;
+    KN_HIP(ctx, launch_world_step(ws, persistent_grid(ctx, 4), stream));
+    return KN_OK;
+  };
+  if ((st = world_step(1, (uint32_t)rays, nullptr, 0)) != KN_OK) return st;
+
+  // a ray segment enters at most every instance once, each for at most
+  // max_steps + 2 rounds, and waits at most a group at each box
+  constexpr int kGroup = 4;
+  const int max_groups =
+      (int)((c->bounces + 1) * ((n_inst + 1) * (c->max_steps + 2 + kGroup) / kGroup + 2)) + 4;
+  int r = 0, rounds = 0;
+  for (int gi = 0;; ++gi) {
+    if (gi >= max_groups) return fail(KN_E_DEVICE, "world render did not finish in %d round groups", gi);
+    cfg.wpar = gi & 1;
+    for (int k = 0; k < kGroup; ++k, ++r) {
+      if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+      if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+      cfg.wzero = k == 0;
+      st = enqueue_round(ctx, w, cfg, r, 0u, stream, e0, e1, k == 0 ? &w.ctrl->n_in : nullptr);
+      if (st != KN_OK) return st;
+      ++rounds;
+    }
+    if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
+    if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
+    st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, e0, e1, pt, r);
+    if (st != KN_OK) return st;
+    if ((st = world_step(cfg.wpar, 0u, &w.ctrl->n_w[cfg.wpar], r)) != KN_OK) return st;
+    KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[0], &w.ctrl->n_chunks[(r - 1) & 1], 4, hipMemcpyDeviceToHost,
+                               stream));
+    KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[1], &w.ctrl->n_in, 4, hipMemcpyDeviceToHost, stream));
+    KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[2], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
+    KN_HIP(ctx, hipEventRecord(ctx->ev_round[0], stream));
+    KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[0]));
+    if ((st = check_scan(ctx, ctx->pinned[2])) != KN_OK) return st;
+    if (ctx->pinned[0] == 0 && ctx->pinned[1] == 0) break;
+  }
+  if (pt) {
+    ResolveArgs ra{w.path, (uint32_t)npix, spp, fr->rgb, fr->accum, q.sample_offset};
     KN_HIP(ctx, launch_resolve(ra, stream));
   }
   KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
@@ -1346,13 +1611,174 @@ kn_status kn_render(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, const 
   if (!s) return fail(KN_E_NOT_FOUND, "scene %u not found", scene);
   st = validate_camera(cam, s);
   if (st != KN_OK) return st;
-  if (!frame || !frame->rgb) return fail(KN_E_INVALID, "frame or frame->rgb is NULL");
+  if ((st = validate_frame(frame, cam)) != KN_OK) return st;
   std::lock_guard<std::mutex> lk(ctx->render_mu);
   KN_HIP(ctx, hipSetDevice(ctx->device));
   hipStream_t stream = frame->hip_stream ? (hipStream_t)frame->hip_stream : ctx->stream;
   s->refs++;
   st = render_frame(ctx, s, cam, frame, stream, stats);
   s->refs--;
+  return st;
+}
+
+constexpr uint32_t kMaxWorldPrims = 256;
+
+static kn_status check_primitive(const kn_primitive& p, uint32_t i) {
+  for (float v : p.p)
+    if (!std::isfinite(v)) return fail(KN_E_INVALID, "primitive %u: non-finite parameter", i);
+  for (float v : p.albedo)
+    if (!(v >= 0.0f && v <= 1.0f)) return fail(KN_E_INVALID, "primitive %u: albedo outside [0, 1]", i);
+  if (p.kind == KN_PRIM_SPHERE) {
+    if (!(p.p[3] > 0.0f)) return fail(KN_E_INVALID, "primitive %u: sphere radius must be positive", i);
+  } else if (p.kind == KN_PRIM_BOX) {
+    for (int a = 0; a < 3; ++a)
+      if (!(p.p[a] < p.p[3 + a])) return fail(KN_E_INVALID, "primitive %u: box min not below max on axis %d", i, a);
+  } else if (p.kind == KN_PRIM_TRIANGLE) {
+    const double e1[3] = {(double)p.p[3] - p.p[0], (double)p.p[4] - p.p[1], (double)p.p[5] - p.p[2]};
+    const double e2[3] = {(double)p.p[6] - p.p[0], (double)p.p[7] - p.p[1], (double)p.p[8] - p.p[2]};
+    const double cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2],
+                 cz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (!(cx * cx + cy * cy + cz * cz > 0.0)) return fail(KN_E_INVALID, "primitive %u: degenerate triangle", i);
+  } else {
+    return fail(KN_E_INVALID, "primitive %u: unknown kind %u", i, p.kind);
+  }
+  return KN_OK;
+}
+
+kn_status kn_world_create(kn_ctx* ctx, const kn_world_desc* d, kn_world_id* out) {
+  kn_status st = check_ctx(ctx);
+  if (st != KN_OK) return st;
+  if (!d || !out) return fail(KN_E_INVALID, "desc or out is NULL");
+  if (d->n_instances > (uint32_t)kMaxScenes)
+    return fail(KN_E_INVALID, "%u instances, at most %d", d->n_instances, kMaxScenes);
+  if (d->n_primitives > kMaxWorldPrims)
+    return fail(KN_E_INVALID, "%u primitives, at most %u", d->n_primitives, kMaxWorldPrims);
+  if ((d->n_instances && !d->instances) || (d->n_primitives && !d->primitives))
+    return fail(KN_E_INVALID, "instances or primitives is NULL");
+  for (uint32_t i = 0; i < d->n_primitives; ++i)
+    if ((st = check_primitive(d->primitives[i], i)) != KN_OK) return st;
+  std::unique_ptr<KnWorld> w(new KnWorld());
+  std::vector<std::array<double, 6>> boxes;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    uint64_t cells = 0;
+    for (uint32_t k = 0; k < d->n_instances; ++k) {
+      const kn_instance& in = d->instances[k];
+      auto it = ctx->scenes.find(in.scene);
+      if (it == ctx->scenes.end()) return fail(KN_E_NOT_FOUND, "instance %u: scene %u not found", k, in.scene);
+      if (!(in.scale > 0.0f) || !std::isfinite(in.scale))
+        return fail(KN_E_INVALID, "instance %u: scale must be positive and finite", k);
+      for (float v : in.translate)
+        if (!std::isfinite(v)) return fail(KN_E_INVALID, "instance %u: non-finite translation", k);
+      const KnScene* sc = it->second;
+      std::array<double, 6> b;
+      for (int a = 0; a < 3; ++a) {
+        b[a] = (double)in.translate[a] + (double)in.scale * sc->geom.bmin[a];
+        b[3 + a] = (double)in.translate[a] + (double)in.scale * sc->geom.bmax[a];
+      }
+      for (uint32_t j = 0; j < k; ++j) {
+        bool overlap = true;
+        for (int a = 0; a < 3; ++a) overlap = overlap && b[a] < boxes[j][3 + a] && boxes[j][a] < b[3 + a];
+        if (overlap) return fail(KN_E_INVALID, "instances %u and %u have overlapping boxes", j, k);
+      }
+      boxes.push_back(b);
+      cells += (uint64_t)sc->N * sc->N * sc->N;
+      w->inst.push_back(in);
+      w->scenes.push_back(it->second);
+    }
+    if (cells > kCellMask)
+      return fail(KN_E_INVALID, "instances hold %llu cells, at most %u", (unsigned long long)cells, kCellMask);
+    w->cells = (uint32_t)cells;
+  }
+  w->n_prims = d->n_primitives;
+  w->bytes = (size_t)std::max<uint32_t>(d->n_primitives, 1u) * sizeof(PrimDev);
+  if (ctx->used.load() + w->bytes > ctx->budget) return fail(KN_E_NOMEM, "world exceeds the HBM budget");
+  std::vector<PrimDev> hp(std::max<uint32_t>(d->n_primitives, 1u), PrimDev{0u, {}, {}});
+  for (uint32_t i = 0; i < d->n_primitives; ++i) {
+    hp[i].kind = d->primitives[i].kind;
+    for (int k = 0; k < 9; ++k) hp[i].p[k] = d->primitives[i].p[k];
+    for (int k = 0; k < 3; ++k) hp[i].albedo[k] = d->primitives[i].albedo[k];
+  }
+  KN_HIP(ctx, hipSetDevice(ctx->device));
+  KN_HIP(ctx, hipMalloc(&w->prims, hp.size() * sizeof(PrimDev)));
+  {
+    const hipError_t e = hipMemcpy(w->prims, hp.data(), hp.size() * sizeof(PrimDev), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(w->prims);
+      ctx->poisoned = true;
+      return fail(KN_E_DEVICE, "hipMemcpy of the primitives failed: %s", hipGetErrorString(e));
+    }
+  }
+  ctx->used += w->bytes;
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  // the scenes may have gone between the two locks
+  for (uint32_t k = 0; k < d->n_instances; ++k) {
+    auto it = ctx->scenes.find(d->instances[k].scene);
+    if (it == ctx->scenes.end() || it->second != w->scenes[k]) {
+      (void)hipFree(w->prims);
+      ctx->used -= w->bytes;
+      return fail(KN_E_NOT_FOUND, "instance %u: scene %u was destroyed", k, d->instances[k].scene);
+    }
+  }
+  for (KnScene* sc : w->scenes) sc->world_refs++;
+  KnWorld* wp = w.release();
+  wp->id = ctx->next_world++;
+  ctx->worlds[wp->id] = wp;
+  *out = wp->id;
+  return KN_OK;
+}
+
+kn_status kn_world_destroy(kn_ctx* ctx, kn_world_id id) {
+  if (!ctx) return fail(KN_E_INVALID, "ctx is NULL");
+  std::lock_guard<std::mutex> lk(ctx->mu);
+  auto it = ctx->worlds.find(id);
+  if (it == ctx->worlds.end()) return fail(KN_E_NOT_FOUND, "world %u not found", id);
+  KnWorld* w = it->second;
+  if (w->refs.load() > 0) return fail(KN_E_BUSY, "world %u is being rendered", id);
+  std::lock_guard<std::mutex> rk(ctx->render_mu);
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (KnScene* sc : w->scenes) sc->world_refs--;
+  if (w->prims) (void)hipFree(w->prims);
+  ctx->used -= w->bytes;
+  delete w;
+  ctx->worlds.erase(it);
+  return KN_OK;
+}
+
+kn_status kn_render_world(kn_ctx* ctx, kn_world_id world, const kn_camera* cam, const kn_frame* frame,
+                          kn_stats* stats) {
+  kn_status st = check_ctx(ctx);
+  if (st != KN_OK) return st;
+  KnWorld* w;
+  {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->worlds.find(world);
+    if (it == ctx->worlds.end()) return fail(KN_E_NOT_FOUND, "world %u not found", world);
+    w = it->second;
+    st = validate_camera(cam, nullptr);
+    if (st != KN_OK) return st;
+    for (size_t k = 0; k < w->scenes.size(); ++k)
+      if (!w->scenes[k]->march(cam->precision))
+        return fail(KN_E_INVALID, "instance %zu: its scene has no copy in precision %d", k, (int)cam->precision);
+    w->refs++;
+  }
+  if ((st = validate_frame(frame, cam)) != KN_OK) {
+    w->refs--;
+    return st;
+  }
+  {
+    std::lock_guard<std::mutex> rk(ctx->render_mu);
+    const hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) {
+      w->refs--;
+      ctx->poisoned = true;
+      return fail(KN_E_DEVICE, "hipSetDevice failed: %s", hipGetErrorString(e));
+    }
+    hipStream_t stream = frame->hip_stream ? (hipStream_t)frame->hip_stream : ctx->stream;
+    st = render_world(ctx, w, cam, frame, stream, stats);
+  }
+  w->refs--;
   return st;
 }
 
@@ -1988,6 +2414,7 @@ kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam, 
     s = it->second;
     st = validate_camera(cam, s);
     if (st != KN_OK) return st;
+    if ((st = validate_frame(frame, cam)) != KN_OK) return st;
     if (cam->bounces != 0) return fail(KN_E_UNSUPPORTED, "the serving loop renders primary rays (bounces 0)");
     if (cam->flags & KN_CAMERA_SPLIT_BF16_SHADING)
       return fail(KN_E_UNSUPPORTED, "the serving loop refines and shades with float32 weights");

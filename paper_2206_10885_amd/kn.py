@@ -16,9 +16,10 @@ LIB_PATH = os.path.join(HERE, "libkn.so")
 
 KN_OK, KN_PENDING = 0, 1
 KN_FP32, KN_BF16, KN_FP8_E4M3 = 0, 1, 2
-KN_ABI_VERSION = 2
+KN_ABI_VERSION = 3
 KN_CAMERA_SPLIT_BF16_SHADING = 1
 KN_CAMERA_UNCLAMPED_STEPS = 2
+KN_PRIM_SPHERE, KN_PRIM_BOX, KN_PRIM_TRIANGLE = 1, 2, 3
 _STATUS = {0: "KN_OK", 1: "KN_PENDING", -1: "KN_E_INVALID", -2: "KN_E_NOMEM", -3: "KN_E_NOT_FOUND",
            -4: "KN_E_BUSY", -5: "KN_E_DEVICE", -6: "KN_E_TIMEOUT", -7: "KN_E_UNSUPPORTED",
            -8: "KN_E_SHUTDOWN"}
@@ -48,13 +49,26 @@ class Camera(C.Structure):
                 ("spp", C.c_uint32), ("bounces", C.c_uint32), ("max_steps", C.c_uint32),
                 ("eps", C.c_float), ("precision", C.c_int), ("seed", C.c_uint64),
                 ("env_rgb", C.c_void_p), ("env_w", C.c_uint32), ("env_h", C.c_uint32),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("sample_offset", C.c_uint32)]
 
 
 class Frame(C.Structure):
     _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("normal", C.c_void_p),
                 ("hit", C.c_void_p), ("steps", C.c_void_p), ("trace", C.c_void_p),
-                ("segments", C.c_void_p), ("hip_stream", C.c_void_p)]
+                ("segments", C.c_void_p), ("hip_stream", C.c_void_p), ("accum", C.c_void_p)]
+
+
+class Primitive(C.Structure):
+    _fields_ = [("kind", C.c_uint32), ("p", C.c_float * 9), ("albedo", C.c_float * 3)]
+
+
+class Instance(C.Structure):
+    _fields_ = [("scene", C.c_uint32), ("translate", C.c_float * 3), ("scale", C.c_float)]
+
+
+class WorldDesc(C.Structure):
+    _fields_ = [("n_instances", C.c_uint32), ("instances", C.POINTER(Instance)),
+                ("n_primitives", C.c_uint32), ("primitives", C.POINTER(Primitive))]
 
 
 SEGMENT_WORDS = 20   # kn_segment_record: 80 bytes
@@ -86,7 +100,7 @@ class Stats(C.Structure):
 
 EXPORTS = ["kn_ctx_create", "kn_ctx_destroy", "kn_last_error", "kn_scene_create",
            "kn_scene_destroy", "kn_render", "kn_query", "kn_query_noalloc", "kn_grid_sample",
-           "kn_eikonal_fd", "kn_serve_start",
+           "kn_eikonal_fd", "kn_world_create", "kn_world_destroy", "kn_render_world", "kn_serve_start",
            "kn_serve_submit", "kn_serve_poll", "kn_serve_stop"]
 
 _lib = None
@@ -118,6 +132,9 @@ def lib():
         L.kn_query_noalloc.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, vp, vp, vp, vp]
         L.kn_grid_sample.argtypes = [vp, C.c_uint32, C.c_int, C.c_uint32, vp, vp, vp]
         L.kn_eikonal_fd.argtypes = [vp, C.c_uint32, C.c_int, vp, C.c_uint64, C.c_float, vp, vp, vp, vp]
+        L.kn_world_create.argtypes = [vp, C.POINTER(WorldDesc), C.POINTER(C.c_uint32)]
+        L.kn_world_destroy.argtypes = [vp, C.c_uint32]
+        L.kn_render_world.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame), C.POINTER(Stats)]
         L.kn_serve_start.argtypes = [vp, C.c_uint32, C.c_int]
         L.kn_serve_submit.argtypes = [vp, C.c_uint32, C.POINTER(Camera), C.POINTER(Frame),
                                       C.POINTER(C.c_uint64)]
@@ -142,10 +159,12 @@ def _ptr(t):
 
 def make_camera(view, width: int, height: int, max_steps: int, eps: float,
                 precision: str = "fp32", spp: int = 1, bounces: int = 0, seed: int = 0,
-                env=None, split_shading: bool = False, unclamped: bool = False) -> Camera:
+                env=None, split_shading: bool = False, unclamped: bool = False,
+                sample_offset: int = 0) -> Camera:
     """A kn_camera; split_shading selects the split-bfloat16 refinement and
     shading of bf16 / fp8 marches (float32 otherwise); unclamped selects
-    Hart's unclamped steps across cells."""
+    Hart's unclamped steps across cells; sample_offset is the index of the
+    call's first sample (progressive path tracing)."""
     env_ptr, ew, eh = None, 0, 0
     if env is not None:
         env_ptr, eh, ew = env.data_ptr(), env.shape[0], env.shape[1]
@@ -153,7 +172,7 @@ def make_camera(view, width: int, height: int, max_steps: int, eps: float,
                   (C.c_float * 3)(*view.up), float(view.tan_half_diag), width, height, spp,
                   bounces, max_steps, eps, PRECISIONS[precision], seed, env_ptr, ew, eh,
                   (KN_CAMERA_SPLIT_BF16_SHADING if split_shading else 0) |
-                  (KN_CAMERA_UNCLAMPED_STEPS if unclamped else 0))
+                  (KN_CAMERA_UNCLAMPED_STEPS if unclamped else 0), sample_offset)
 
 
 class Context:
@@ -213,14 +232,21 @@ class Context:
             f["trace"] = torch.empty((height, width, 4), dtype=torch.int32, device=dev)
         return f
 
+    @staticmethod
+    def _frame(out: dict, stream) -> Frame:
+        return Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
+                     _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
+                     _ptr(out.get("segments")), None if stream is None else C.c_void_p(stream.cuda_stream),
+                     _ptr(out.get("accum")))
+
     def render_into(self, sid: int, cam: Camera, out: dict, stream=None,
                     kernel_times: bool = False) -> dict:
+        """kn_render into the tensors of `out` (rgb required; depth, normal,
+        hit, steps, trace, segments and accum optional)."""
         import torch
         if stream is None:
             stream = torch.cuda.current_stream(self.device)
-        fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
-                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
-                   _ptr(out.get("segments")), C.c_void_p(stream.cuda_stream))
+        fr = self._frame(out, stream)
         st = Stats()
         st.kernel_times = 1 if kernel_times else 0
         check(lib().kn_render(self.h, sid, C.byref(cam), C.byref(fr), C.byref(st)))
@@ -235,6 +261,36 @@ class Context:
         out["stats"] = self.render_into(sid, cam, out)
         return out
 
+    # -- shared scenes -------------------------------------------------------
+    def world_create(self, instances=(), primitives=()) -> int:
+        """kn_world_create: instances = [(scene id, translate xyz, scale)],
+        primitives = [(KN_PRIM_* kind, parameters (up to 9), albedo rgb)]."""
+        ins = (Instance * max(1, len(instances)))()
+        for k, (sid, T, s) in enumerate(instances):
+            ins[k] = Instance(sid, (C.c_float * 3)(*T), float(s))
+        prs = (Primitive * max(1, len(primitives)))()
+        for k, (kind, p, alb) in enumerate(primitives):
+            pp = list(p) + [0.0] * (9 - len(p))
+            prs[k] = Primitive(kind, (C.c_float * 9)(*pp), (C.c_float * 3)(*alb))
+        d = WorldDesc(len(instances), ins, len(primitives), prs)
+        wid = C.c_uint32()
+        check(lib().kn_world_create(self.h, C.byref(d), C.byref(wid)))
+        return wid.value
+
+    def world_destroy(self, wid: int):
+        check(lib().kn_world_destroy(self.h, wid))
+
+    def render_world_into(self, wid: int, cam: Camera, out: dict, stream=None,
+                          kernel_times: bool = False) -> dict:
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        fr = self._frame(out, stream)
+        st = Stats()
+        st.kernel_times = 1 if kernel_times else 0
+        check(lib().kn_render_world(self.h, wid, C.byref(cam), C.byref(fr), C.byref(st)))
+        return st.as_dict()
+
     # -- serving ------------------------------------------------------------
     def serve_start(self, max_inflight: int = 16, precision: str = "bf16"):
         check(lib().kn_serve_start(self.h, max_inflight, PRECISIONS[precision]))
@@ -242,9 +298,7 @@ class Context:
     def serve_submit(self, sid: int, cam: Camera, out: dict) -> int:
         """Queues a frame; `out` (from alloc_frame) must stay alive until
         serve_poll reports it finished."""
-        fr = Frame(_ptr(out["rgb"]), _ptr(out.get("depth")), _ptr(out.get("normal")),
-                   _ptr(out.get("hit")), _ptr(out.get("steps")), _ptr(out.get("trace")),
-                   _ptr(out.get("segments")), None)
+        fr = self._frame(out, None)
         rid = C.c_uint64()
         check(lib().kn_serve_submit(self.h, sid, C.byref(cam), C.byref(fr), C.byref(rid)))
         return rid.value

@@ -270,6 +270,90 @@ void case_grid_eikonal() {
   expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
 }
 
+void case_world() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, (uint64_t)1 << 30, &ctx) == KN_OK, "ctx create");
+  HostScene s1 = make_scene(4, 64, 31), s2 = make_scene(8, 32, 32);
+  kn_scene_desc d1 = desc_of(s1, kAll), d2 = desc_of(s2, 1u << KN_BF16);
+  kn_scene_id a = 0, b = 0;
+  expect(kn_scene_create(ctx, &d1, &a) == KN_OK && kn_scene_create(ctx, &d2, &b) == KN_OK, "scenes create");
+  kn_instance inst[3] = {{a, {0.0f, 0.0f, 0.0f}, 1.0f}, {b, {3.0f, 0.0f, 0.0f}, 0.5f}, {a, {0.0f, 0.0f, -4.0f}, 2.0f}};
+  kn_primitive prim[3] = {{KN_PRIM_SPHERE, {0.0f, -3.0f, 0.0f, 1.0f}, {0.5f, 0.5f, 0.5f}},
+                          {KN_PRIM_BOX, {-5.0f, -6.0f, -5.0f, 5.0f, -5.0f, 5.0f}, {0.8f, 0.7f, 0.6f}},
+                          {KN_PRIM_TRIANGLE, {0.0f, 3.0f, 0.0f, 1.0f, 3.0f, 0.0f, 0.0f, 4.0f, 0.0f}, {1.0f, 0.0f, 0.0f}}};
+  kn_world_desc wd{3, inst, 3, prim};
+  kn_world_id w = 0;
+  expect(kn_world_create(ctx, &wd, &w) == KN_OK, "world create (3 instances, 3 primitives)");
+  expect(kn_scene_destroy(ctx, a) == KN_E_BUSY, "scene placed in a world is busy");
+  DevFrame fr(97 * 61);
+  for (kn_precision p : {KN_FP32, KN_BF16}) {
+    kn_camera c = camera(97, 61, p);
+    c.eye[2] = 9.0f;
+    kn_stats st{};
+    expect(kn_render_world(ctx, w, &c, &fr.f, &st) == KN_OK, "world render");
+  }
+  kn_camera c8 = camera(97, 61, KN_FP8_E4M3);
+  expect(kn_render_world(ctx, w, &c8, &fr.f, nullptr) == KN_E_INVALID, "instance without an fp8 copy refused");
+  float* acc = nullptr;
+  (void)hipMalloc((void**)&acc, 97 * 61 * 12);
+  kn_camera cp = camera(97, 61, KN_BF16);
+  cp.bounces = 2;
+  cp.spp = 2;
+  fr.f.accum = acc;
+  expect(kn_render_world(ctx, w, &cp, &fr.f, nullptr) == KN_OK, "path-traced world render with accumulation");
+  cp.sample_offset = 2;
+  expect(kn_render_world(ctx, w, &cp, &fr.f, nullptr) == KN_OK, "accumulation, second call");
+  expect(kn_render(ctx, a, &cp, &fr.f, nullptr) == KN_OK, "single-scene render with accumulation");
+  kn_camera c0 = camera(97, 61, KN_BF16);
+  expect(kn_render(ctx, a, &c0, &fr.f, nullptr) == KN_E_UNSUPPORTED, "accumulation without path tracing refused");
+  fr.f.accum = nullptr;
+  c0.sample_offset = 3;
+  expect(kn_render(ctx, a, &c0, &fr.f, nullptr) == KN_E_INVALID, "sample_offset without path tracing refused");
+  (void)hipFree(acc);
+  kn_camera cu = camera(33, 17, KN_BF16);
+  cu.flags = KN_CAMERA_UNCLAMPED_STEPS;
+  expect(kn_render_world(ctx, w, &cu, &fr.f, nullptr) == KN_E_UNSUPPORTED,
+         "unclamped steps in a world of mixed widths refused");
+  expect(kn_render_world(ctx, w + 77, &cu, &fr.f, nullptr) == KN_E_NOT_FOUND, "unknown world");
+  // validation
+  kn_instance ov[2] = {{a, {0.0f, 0.0f, 0.0f}, 1.0f}, {b, {1.5f, 0.0f, 0.0f}, 1.0f}};
+  kn_world_desc bad{2, ov, 0, nullptr};
+  kn_world_id wx = 0;
+  expect(kn_world_create(ctx, &bad, &wx) == KN_E_INVALID, "overlapping instance boxes refused");
+  kn_instance sc0[1] = {{a, {0.0f, 0.0f, 0.0f}, 0.0f}};
+  bad = kn_world_desc{1, sc0, 0, nullptr};
+  expect(kn_world_create(ctx, &bad, &wx) == KN_E_INVALID, "zero scale refused");
+  kn_instance nf[1] = {{a + 99, {0.0f, 0.0f, 0.0f}, 1.0f}};
+  bad = kn_world_desc{1, nf, 0, nullptr};
+  expect(kn_world_create(ctx, &bad, &wx) == KN_E_NOT_FOUND, "unknown scene refused");
+  kn_primitive bp[4] = {{KN_PRIM_SPHERE, {0.0f, 0.0f, 0.0f, -1.0f}, {0.5f, 0.5f, 0.5f}},
+                        {KN_PRIM_BOX, {0.0f, 0.0f, 0.0f, 1.0f, 0.0f, 1.0f}, {0.5f, 0.5f, 0.5f}},
+                        {KN_PRIM_TRIANGLE, {0.0f, 0.0f, 0.0f, 1.0f, 1.0f, 1.0f, 2.0f, 2.0f, 2.0f}, {0.5f, 0.5f, 0.5f}},
+                        {KN_PRIM_SPHERE, {0.0f, 0.0f, 0.0f, 1.0f}, {1.5f, 0.5f, 0.5f}}};
+  for (int i = 0; i < 4; ++i) {
+    bad = kn_world_desc{0, nullptr, 1, bp + i};
+    expect(kn_world_create(ctx, &bad, &wx) == KN_E_INVALID, "bad primitive refused");
+  }
+  // primitives only, then no objects at all
+  kn_world_desc po{0, nullptr, 1, prim};
+  kn_world_id wp = 0;
+  expect(kn_world_create(ctx, &po, &wp) == KN_OK, "world of primitives only");
+  kn_camera c1 = camera(40, 30, KN_FP32);
+  c1.eye[1] = -0.5f;
+  c1.eye[2] = 6.0f;
+  expect(kn_render_world(ctx, wp, &c1, &fr.f, nullptr) == KN_OK, "render a world of primitives");
+  expect(kn_world_destroy(ctx, wp) == KN_OK, "world destroy");
+  kn_world_desc none{0, nullptr, 0, nullptr};
+  expect(kn_world_create(ctx, &none, &wp) == KN_OK, "empty world");
+  expect(kn_render_world(ctx, wp, &c1, &fr.f, nullptr) == KN_OK, "render an empty world");
+  expect(kn_world_destroy(ctx, w) == KN_OK, "world destroy releases its scenes");
+  expect(kn_scene_destroy(ctx, b) == KN_OK, "scene destroy after its world");
+  // a world and a scene left for kn_ctx_destroy
+  kn_world_desc keep{1, inst, 1, prim};
+  expect(kn_world_create(ctx, &keep, &wx) == KN_OK, "world kept until the context is destroyed");
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy frees the remaining worlds");
+}
+
 void case_query_scan_err() {
   kn_ctx* ctx = nullptr;
   expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
@@ -340,6 +424,7 @@ int main(int argc, char** argv) {
   else if (c == "render_scan_err") case_render_query(true);
   else if (c == "query_scan_err") case_query_scan_err();
   else if (c == "grid_eikonal") case_grid_eikonal();
+  else if (c == "world") case_world();
   else if (c == "noalloc") case_noalloc();
   else if (c == "serve") case_serve(false);
   else if (c == "serve_scan_err") case_serve(true);

@@ -165,6 +165,27 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t) {
   need(a.path, (size_t)a.npix * a.spp * sizeof(PathRec), "path records");
   return hipSuccess;
 }
+hipError_t launch_world_raygen(const WorldRaygenArgs& a, uint32_t npath, hipStream_t) {
+  need(a.out, (size_t)npath * sizeof(WorldRec), "world records");
+  if (a.pt) need(a.path, (size_t)npath * sizeof(PathRec), "path records");
+  return hipSuccess;
+}
+// every record ends (escapes) here: nothing is spawned
+hipError_t launch_world_step(const WorldStepArgs& a, uint32_t, hipStream_t) {
+  need_tabs(a.tabs);
+  need(a.prims, sizeof(PrimDev), "primitives");
+  uint32_t n = a.n;
+  if (a.n_dev) {
+    need(a.n_dev, 4, "world record count");
+    n = *a.n_dev;
+  }
+  if (n) need(a.in, (size_t)n * sizeof(WorldRec), "world records");
+  need(a.n_spawn, 4, "spawn count");
+  need(a.spawn, 16, "spawn list");
+  need(a.counts_next, 4, "next round's counts");
+  finish_as_misses(a.tabs.miss_done, 0, n);
+  return hipSuccess;
+}
 hipError_t launch_scan(const ScanArgs& a, hipStream_t) {
   need(a.counts, (size_t)a.C * a.cs * 4, "scan counts");
   need(a.cursor, (size_t)a.C * a.cs * 4, "scan cursor");

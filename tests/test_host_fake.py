@@ -6,7 +6,7 @@ It is built with g++ against a host-only stand-in for the HIP runtime
 allocations that every kernel-launcher stub checks its buffers against, and
 streams are synchronous.  The driver creates and packs scenes at several grid
 and MLP sizes in every precision, checks argument validation, renders frames,
-runs point queries and the serving loop, and checks that a look-back overrun
+runs point queries, shared-scene worlds and the serving loop, and checks that a look-back overrun
 of the cell scan (raised by the stub when KN_FAKE_SCAN_ERR is set) fails the
 call, every request in flight, and poisons the context.  LeakSanitizer runs at
 exit.  No GPU is used."""
@@ -38,7 +38,7 @@ def driver(tmp_path_factory):
 
 
 @pytest.mark.parametrize("case", ["scenes", "validation", "render", "render_scan_err", "query_scan_err", "noalloc",
-                                  "grid_eikonal",
+                                  "grid_eikonal", "world",
                                   "serve", "serve_scan_err"])
 def test_host_runtime_under_sanitizers(driver, case):
     env = dict(os.environ)

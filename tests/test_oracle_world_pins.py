@@ -207,3 +207,32 @@ def test_path_trace_furnace_with_primitives():
     assert np.abs(hits - np.round(hits)).max() < 1e-9
     assert (np.round(hits) >= 0).all() and (np.round(hits) <= spp).all()
     assert (np.round(hits) == spp).sum() > 100 and (np.round(hits) == 0).sum() > 100
+
+
+def test_interval_cut_inside_a_cell():
+    """A sphere primitive just above a plane instance, inside one cell of
+    it: rays that meet the sphere first show the sphere (the instance's
+    march ends where the sphere cuts its interval, also inside a cell, so it
+    does not go on to the plane below), the others the plane at its
+    closed-form distance."""
+    n = np.array([0.0, 1.0, 0.0])
+    sc = synth.constant_color_plane_scene(2, 32, n, -0.3, [0.6, 0.35, 0.8], seed=3)
+    sph = [0.5, -0.15, 0.5, 0.1]     # inside the cell [0, 1] x [-1, 0] x [0, 1]
+    w = O.OracleWorld([(O.OracleScene.from_scene(sc), (0, 0, 0), 1.0)], [(O.PRIM_SPHERE, sph, (0.5, 0.5, 0.5))])
+    view = synth.View(eye=(0.9, 1.6, 1.4), look_at=(0.5, -0.2, 0.5), tan_half_diag=0.25)
+    W, H = 40, 30
+    r = w.render(view, W, H, 128, 1e-4)
+    n_s = n_p = 0
+    for p in range(W * H):
+        o, d = O.camera_ray(view, W, H, p // W, p % W)
+        ok, ts, _ = O.prim_hit(O.PRIM_SPHERE, sph, o, d)
+        tp = (-0.3 - o[1]) / d[1] if d[1] < 0 else np.inf
+        xp = o + tp * d if np.isfinite(tp) else None
+        in_box = xp is not None and abs(xp[0]) <= 1 and abs(xp[2]) <= 1
+        if ok and (not in_box or ts < tp):
+            n_s += 1
+            assert r["object"][p] == -2 and abs(r["depth"][p] - ts) < 1e-12
+        elif in_box and not (abs(abs(xp[0]) - 1) < 1e-3 or abs(abs(xp[2]) - 1) < 1e-3):
+            n_p += 1
+            assert r["object"][p] == 0 and abs(r["depth"][p] - tp) < 1e-4
+    assert n_s > 50 and n_p > 50, (n_s, n_p)
