@@ -659,6 +659,10 @@ __global__ __launch_bounds__(256) void k_scan(ScanArgs a) {
       const uint32_t nch = bk + tk;
       if (lane == 0) {
         *a.n_chunks = nch;
+        if (a.host_ring)
+          __hip_atomic_store(a.host_ring + a.ring_tag % kRoundRing,
+                             ((unsigned long long)a.ring_tag << 32) | (unsigned long long)nch, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_SYSTEM);
         if (a.zero_word) *a.zero_word = 0u;
         if (a.zero_word2) *a.zero_word2 = 0u;
         if (a.total) *a.total += br + tr;
@@ -1487,6 +1491,9 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
   __shared__ SceneEnt s_scn[kMaxScenes];
   __shared__ float s_qeps[kMaxSlots];
   __shared__ uint32_t s_qmst[kMaxSlots];
+  // a round without work items (the last rounds a frame enqueues ahead of
+  // knowing that it is done) returns before staging anything
+  if (*a.n_chunks == 0u) return;
   const int tid = threadIdx.x, lane = lane_id(), g = lane >> 4, p = lane & 15, wave = tid >> 6;
   const PeLane pl = make_pe_lane(g);
   unsigned long long wv_evals = 0, wv_tiles = 0, wg_chunks = 0;  // lane 0's / thread 0's tallies

@@ -144,6 +144,11 @@ struct ScanArgs {
   unsigned long long* flags;  // Ctrl::scan_flags
   uint32_t* err;         // Ctrl::scan_err
   uint32_t cs;           // counts, runs and cursor hold cell c at c * cs (base: at c)
+  // optional: host-mapped ring that receives (tag << 32 | chunk count) in
+  // slot tag % kRoundRing, stored at system scope, so the host can follow
+  // the rounds without a copy command
+  unsigned long long* host_ring;
+  uint32_t ring_tag;
 };
 
 struct ScatterArgs {

@@ -366,6 +366,14 @@ struct Pool {
                                    // round parity (allocated on first use)
   WorldRec* W = nullptr;           // [2][cap]: world renders, rays waiting for their next object
   WState* WS = nullptr;            // [cap]: world renders, each ray's segment origin
+  // primary frames whose hits are shaded in two passes, the first one on a
+  // second stream while the last rounds run (allocated on first use): the
+  // later rounds' per-cell hit counts, and the first pass's cursors and
+  // control block (its bins are Uin, which a primary frame uses only to
+  // bring its camera rays into round 0)
+  uint32_t* hit_count2 = nullptr;  // [cells * cs]
+  uint32_t* cursor2 = nullptr;     // [cells * cs]
+  Ctrl* ctrl2 = nullptr;
   // per-cell counters, cell c at word c * cs: on grids of up to
   // kPadCells cells each counter has a 128-byte line of its own
   uint32_t cs = 1;
@@ -374,7 +382,7 @@ struct Pool {
   uint32_t* hit_count = nullptr;   // [cells * cs]
   uint32_t* cursor = nullptr;      // [cells * cs]
   uint32_t* base = nullptr;        // [cells]: bin starts of the current round
-  uint2* chunk = nullptr;          // [3][chunks]: rounds of parity 0 / 1, shading
+  uint2* chunk = nullptr;          // [4][chunks]: rounds of parity 0 / 1, shading, early shading
   uint4* chunk_out = nullptr;      // [2][chunks][4]
   Ctrl* ctrl = nullptr;
   SceneEnt* scenes = nullptr;      // [kMaxScenes]
@@ -434,6 +442,8 @@ struct kn_ctx {
   hipError_t scratch_err = hipSuccess;
   int num_cu = 256;
   hipStream_t stream = nullptr;
+  hipStream_t stream2 = nullptr;   // early shading of primary frames
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   uint64_t budget = 0;
   std::atomic<uint64_t> used{0};
   std::mutex mu;              // scenes map, scene reference counts
@@ -448,6 +458,11 @@ struct kn_ctx {
   void* aux = nullptr;         // grow-only work buffer of kn_eikonal_fd
   size_t aux_bytes = 0;
   uint32_t* pinned = nullptr;  // round counters read back by the host
+  // host-mapped ring of primary rounds' chunk counts, written by the scan
+  // (tag << 32 | count at slot tag % kRoundRing); tags are frame_seq << 11 | round
+  unsigned long long* ring = nullptr;
+  unsigned long long* ring_dev = nullptr;
+  uint32_t frame_seq = 0;
   SceneEnt* h_scene = nullptr; // pinned staging of kn_render's tables ([kMaxScenes])
   ReqEnt* h_req = nullptr;
   hipEvent_t ev_start = nullptr, ev_end = nullptr;
@@ -487,10 +502,24 @@ kn_status check_scan(kn_ctx* ctx, uint32_t scan_err) {
 // (render and query; the allocation-free query)
 constexpr int kPinnedScanErr = 16;
 constexpr int kPinnedScanErrNoAlloc = 17;
+constexpr int kPinnedScanErr2 = 18;
+
+// Early shading of primary frames: once a round's work items fall below
+// this fraction of the largest round's, the hits so far are shaded on a
+// second stream beside the remaining rounds (frames of at least
+// kEarlyShadeMinRays rays whose rounds reached kEarlyShadeMinChunks items).
+// KN_EARLY_SHADE overrides the fraction (0 turns it off).
+constexpr size_t kEarlyShadeMinRays = (size_t)1 << 18;
+constexpr uint32_t kEarlyShadeMinChunks = 512;
+double early_shade_fraction() {
+  if (const char* e = std::getenv("KN_EARLY_SHADE")) return std::atof(e);
+  return 0.4;   // 1080p C3 frames: 0.12 / 0.25 / 0.4 gave 5.999 / 5.962 / 5.875 ms (6.044 without)
+}
 
 void free_pool(Pool& w) {
-  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.J, w.W, w.WS, w.counts, w.runs, w.hit_count, w.cursor, w.base,
-                  w.chunk, w.chunk_out, w.ctrl, w.scenes, w.reqs};
+  void* ptrs[] = {w.rs, w.U, w.S, w.Uin, w.HL, w.path, w.J, w.W, w.WS, w.hit_count2, w.cursor2, w.ctrl2,
+                  w.counts, w.runs, w.hit_count, w.cursor, w.base, w.chunk, w.chunk_out, w.ctrl, w.scenes,
+                  w.reqs};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   w = Pool{};
@@ -519,22 +548,24 @@ uint32_t counter_stride(size_t C) {
 
 size_t pool_bytes(size_t R, size_t C, size_t K) {
   return R * kRayBytes + (uin_entries(R) - R) * sizeof(RayRec) + C * 4 * (6 * (size_t)counter_stride(C) + 1) +
-         K * (3 * 8 + 2 * 64) +
+         K * (4 * 8 + 2 * 64) +
          sizeof(Ctrl) + kMaxScenes * sizeof(SceneEnt) + kMaxSlots * sizeof(ReqEnt);
 }
 
 // grow-only pool for `rays` records over `cells` cells (with path state if
 // `paths`)
 kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool paths = false,
-                      bool jumps = false, bool world = false) {
+                      bool jumps = false, bool world = false, bool early = false) {
   const size_t chunks = rays / kShadeChunk + cells + 2;
   if (w.ctrl && w.cap >= rays && w.cells >= cells && w.chunks >= chunks && (!paths || w.path) &&
-      (!jumps || w.J) && (!world || w.W))
+      (!jumps || w.J) && (!world || w.W) && (!early || w.ctrl2))
     return KN_OK;
   const size_t R = std::max(w.cap, rays), C = std::max(w.cells, cells), K = std::max(w.chunks, chunks);
-  const bool P = paths || w.path || world, J = jumps || w.J, Wd = world || w.W;
+  const bool P = paths || w.path || world, J = jumps || w.J, Wd = world || w.W, E = early || w.ctrl2;
+  const size_t cs = counter_stride(C);
   const size_t bytes = pool_bytes(R, C, K) + (P ? R * sizeof(PathRec) : 0) + (J ? 2 * R * sizeof(RayRec) : 0) +
-                       (Wd ? R * (2 * sizeof(WorldRec) + sizeof(WState)) : 0);
+                       (Wd ? R * (2 * sizeof(WorldRec) + sizeof(WState)) : 0) +
+                       (E ? 2 * C * cs * 4 + sizeof(Ctrl) : 0);
   const uint64_t other = ctx->used.load() - w.bytes;
   if (other + bytes > ctx->budget)
     return fail(KN_E_NOMEM, "ray workspace of %zu bytes exceeds the HBM budget", bytes);
@@ -561,12 +592,17 @@ kn_status ensure_pool(kn_ctx* ctx, Pool& w, size_t rays, size_t cells, bool path
     KN_HIP(ctx, hipMalloc(&n.W, 2 * R * sizeof(WorldRec)));
     KN_HIP(ctx, hipMalloc(&n.WS, R * sizeof(WState)));
   }
+  if (E) {
+    KN_HIP(ctx, hipMalloc(&n.hit_count2, C * n.cs * 4));
+    KN_HIP(ctx, hipMalloc(&n.cursor2, C * n.cs * 4));
+    KN_HIP(ctx, hipMalloc(&n.ctrl2, sizeof(Ctrl)));
+  }
   KN_HIP(ctx, hipMalloc(&n.counts, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.runs, 2 * C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.hit_count, C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.cursor, C * n.cs * 4));
   KN_HIP(ctx, hipMalloc(&n.base, C * 4));
-  KN_HIP(ctx, hipMalloc(&n.chunk, 3 * K * 8));
+  KN_HIP(ctx, hipMalloc(&n.chunk, 4 * K * 8));
   KN_HIP(ctx, hipMalloc(&n.chunk_out, 2 * K * 64));
   KN_HIP(ctx, hipMalloc(&n.ctrl, sizeof(Ctrl)));
   KN_HIP(ctx, hipMemset(n.HL, 0xFF, R * sizeof(RayRec)));   // no hits
@@ -649,6 +685,9 @@ struct RoundCfg {
   int wpar = -1;          // world renders: the world list (parity) that rays leaving a box
                           // go to this round; -1 otherwise
   bool wzero = false;     // ... and this round's scan clears that list's count first
+  unsigned long long* ring = nullptr;   // device address of kn_ctx::ring, or null
+  uint32_t tag0 = 0;      // round r's count goes to the ring with tag tag0 + r
+  uint32_t* hit_count = nullptr;    // per-cell hit counts the march adds to (null: Pool::hit_count)
 };
 
 // Round r: bins the records arriving for it (the previous round's leavers,
@@ -678,6 +717,8 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   sa.zero_word = c.jumps ? &w.ctrl->n_jump[par ^ 1] : nullptr;
   sa.zero_word2 = c.wpar >= 0 && c.wzero ? &w.ctrl->n_w[c.wpar] : nullptr;
   sa.total = nullptr;
+  sa.host_ring = c.ring;
+  sa.ring_tag = c.tag0 + (uint32_t)r;
   KN_HIP(ctx, launch_scan(sa, st));
   if (r > 0) {
     ScatterChunksArgs sc{tabs,
@@ -712,7 +753,7 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
   ma.U = w.U;
   ma.runs_next = w.runs + (par ^ 1) * w.cells * w.cs;
   ma.hits = w.HL;
-  ma.hit_count = w.hit_count;
+  ma.hit_count = c.hit_count ? c.hit_count : w.hit_count;
   ma.cs = w.cs;
   ma.evals = &w.ctrl->tally[0][0];
   ma.max_passes = c.max_passes;
@@ -742,35 +783,55 @@ kn_status enqueue_round(kn_ctx* ctx, Pool& w, const RoundCfg& c, int r, uint32_t
 // scatter clears each hit it takes), refined, shaded.  With path tracing,
 // hits that scatter append their next segment to Uin (count in ctrl->n_in,
 // cleared first) for round `next_round`.
+// The buffers one shading pass works in: the hit list and per-cell hit
+// counts it takes, and its own bins, cursors, work items and control block.
+struct ShadeSet {
+  RayRec* hits;
+  uint32_t* hit_count;
+  RayRec* S;
+  uint32_t* cursor;
+  uint2* chunks;
+  Ctrl* ctrl;
+};
+
+ShadeSet main_shade_set(const Pool& w) {
+  return ShadeSet{w.HL, w.hit_count, w.S, w.cursor, w.chunk + 2 * w.chunks, w.ctrl};
+}
+
+// With kst, the binning (scan and scatter, which takes the hits out of the
+// list) stays on st and the shading kernel runs on kst after it (ev_fork),
+// with per_cu workgroups per CU; ev_join marks its end on kst.
 kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids, hipStream_t st, hipEvent_t e0,
-                        hipEvent_t e1, bool pt = false, int next_round = 0) {
-  uint2* chunks = w.chunk + 2 * w.chunks;
+                        hipEvent_t e1, bool pt = false, int next_round = 0, const ShadeSet* set = nullptr,
+                        hipStream_t kst = nullptr, uint32_t per_cu = 3) {
+  const ShadeSet ss = set ? *set : main_shade_set(w);
+  uint2* chunks = ss.chunks;
   ScanArgs sa{};
-  sa.counts = w.hit_count;
+  sa.counts = ss.hit_count;
   sa.cs = w.cs;
   sa.C = c.cells;
   sa.T = kShadeChunk;
   sa.zero_counts = 1;
-  sa.cursor = w.cursor;
+  sa.cursor = ss.cursor;
   sa.chunks = chunks;
-  sa.n_chunks = &w.ctrl->n_chunks[2];
-  sa.grab = w.ctrl->grab;
-  sa.grab0 = w.ctrl->grab0;
-  sa.ticket = &w.ctrl->scan_ticket;
-  sa.flags = w.ctrl->scan_flags;
-  sa.err = &w.ctrl->scan_err;
+  sa.n_chunks = &ss.ctrl->n_chunks[2];
+  sa.grab = ss.ctrl->grab;
+  sa.grab0 = ss.ctrl->grab0;
+  sa.ticket = &ss.ctrl->scan_ticket;
+  sa.flags = ss.ctrl->scan_flags;
+  sa.err = &ss.ctrl->scan_err;
   sa.zero_word = pt ? &w.ctrl->n_in : nullptr;
-  sa.total = &w.ctrl->n_hits;
+  sa.total = &ss.ctrl->n_hits;
   KN_HIP(ctx, launch_scan(sa, st));
-  ScatterArgs sc{w.HL, w.S, n_ids, nullptr, w.cursor, 1, w.cs};
+  ScatterArgs sc{ss.hits, ss.S, n_ids, nullptr, ss.cursor, 1, w.cs};
   KN_HIP(ctx, launch_scatter(sc, std::min<uint32_t>((n_ids + 255u) / 256u, 65536u), st));
   ShadeArgs sh{};
   sh.tabs = pool_tabs(w, c.n_scenes);
-  sh.S = w.S;
+  sh.S = ss.S;
   sh.rs = w.rs;
   sh.chunks = chunks;
-  sh.n_chunks = &w.ctrl->n_chunks[2];
-  sh.grab = w.ctrl->grab;
+  sh.n_chunks = &ss.ctrl->n_chunks[2];
+  sh.grab = ss.ctrl->grab;
   sh.spawn = w.Uin;
   sh.n_spawn = &w.ctrl->n_in;
   sh.counts_next = w.counts + (next_round & 1) * w.cells * w.cs;
@@ -779,10 +840,16 @@ kn_status enqueue_shade(kn_ctx* ctx, Pool& w, const RoundCfg& c, uint32_t n_ids,
     sh.wlist = w.W + (size_t)c.wpar * w.cap;
     sh.n_w = &w.ctrl->n_w[c.wpar];
   }
-  if (e0) KN_HIP(ctx, hipEventRecord(e0, st));
+  if (kst) {
+    KN_HIP(ctx, hipEventRecord(ctx->ev_fork, st));
+    KN_HIP(ctx, hipStreamWaitEvent(kst, ctx->ev_fork, 0));
+  }
+  hipStream_t ks = kst ? kst : st;
+  if (e0) KN_HIP(ctx, hipEventRecord(e0, ks));
   KN_HIP(ctx, launch_shade(sh, c.hmode, c.split ? c.prec : (int)KN_FP32, pt, c.shade_words,
-                           persistent_grid(ctx, 3), st));
-  if (e1) KN_HIP(ctx, hipEventRecord(e1, st));
+                           persistent_grid(ctx, per_cu), ks));
+  if (e1) KN_HIP(ctx, hipEventRecord(e1, ks));
+  if (kst) KN_HIP(ctx, hipEventRecord(ctx->ev_join, kst));
   return KN_OK;
 }
 
@@ -823,7 +890,14 @@ kn_status kn_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kn_ctx** out)
   KN_HIP(ctx, hipMemGetInfo(&freeb, &total));
   ctx->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)freeb);
   KN_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking));
+  KN_HIP(ctx, hipStreamCreateWithFlags(&ctx->stream2, hipStreamNonBlocking));
+  KN_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  KN_HIP(ctx, hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->pinned, 64 * sizeof(uint32_t), hipHostMallocDefault));
+  KN_HIP(ctx, hipHostMalloc((void**)&ctx->ring, kRoundRing * sizeof(unsigned long long),
+                            hipHostMallocCoherent | hipHostMallocMapped));
+  for (uint32_t i = 0; i < kRoundRing; ++i) ctx->ring[i] = ~0ull;
+  KN_HIP(ctx, hipHostGetDevicePointer((void**)&ctx->ring_dev, ctx->ring, 0));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_scene, kMaxScenes * sizeof(SceneEnt), hipHostMallocDefault));
   KN_HIP(ctx, hipHostMalloc((void**)&ctx->h_req, sizeof(ReqEnt), hipHostMallocDefault));
   KN_HIP(ctx, hipEventCreate(&ctx->ev_start));
@@ -855,6 +929,7 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
   if (ctx->aux) (void)hipFree(ctx->aux);
   ctx->used -= ctx->aux_bytes;
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+  if (ctx->ring) (void)hipHostFree(ctx->ring);
   if (ctx->h_scene) (void)hipHostFree(ctx->h_scene);
   if (ctx->h_req) (void)hipHostFree(ctx->h_req);
   if (ctx->ev_start) (void)hipEventDestroy(ctx->ev_start);
@@ -862,6 +937,12 @@ kn_status kn_ctx_destroy(kn_ctx* ctx) {
   for (auto& e : ctx->ev_round)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : ctx->ev_kernel) (void)hipEventDestroy(e);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->stream2) {
+    (void)hipStreamSynchronize(ctx->stream2);
+    (void)hipStreamDestroy(ctx->stream2);
+  }
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return KN_OK;
@@ -1177,6 +1258,47 @@ kn_status enqueue_query(kn_ctx* ctx, const KnScene* s, kn_precision precision, c
 
 }  // namespace
 
+namespace {
+
+// Waits until the scan of the round tagged `tag` has put its chunk count into
+// the host-mapped ring (the count is stored by the scan itself, so no copy
+// command sits between the rounds).  A stream that has failed, or finished
+// without the entry, is an error.
+kn_status wait_round(kn_ctx* ctx, hipStream_t stream, uint32_t tag, uint32_t* n) {
+  volatile unsigned long long* slot = ctx->ring + tag % kRoundRing;
+  const auto t0 = std::chrono::steady_clock::now();
+  for (uint64_t it = 1;; ++it) {
+    const unsigned long long v = *slot;
+    if ((uint32_t)(v >> 32) == tag) {
+      *n = (uint32_t)v;
+      return KN_OK;
+    }
+    if ((it & 255u) == 0) {
+      const hipError_t q = hipStreamQuery(stream);
+      if (q == hipSuccess) {
+        const unsigned long long v2 = *slot;
+        if ((uint32_t)(v2 >> 32) == tag) {
+          *n = (uint32_t)v2;
+          return KN_OK;
+        }
+        ctx->poisoned = true;
+        return fail(KN_E_DEVICE, "round %u: its chunk count never reached the host", tag & 2047u);
+      }
+      if (q != hipErrorNotReady) {
+        ctx->poisoned = true;
+        return fail(KN_E_DEVICE, "stream failed while rendering: %s", hipGetErrorString(q));
+      }
+      if (std::chrono::steady_clock::now() - t0 > std::chrono::seconds(60)) {
+        ctx->poisoned = true;
+        return fail(KN_E_DEVICE, "round %u did not finish within 60 s", tag & 2047u);
+      }
+      std::this_thread::yield();
+    }
+  }
+}
+
+}  // namespace
+
 namespace kn {
 
 // Enqueues and runs one frame on `stream` as a one-request pool; the caller
@@ -1190,7 +1312,11 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   const size_t rays = npix * spp;
   const size_t cells = (size_t)s->N * s->N * s->N;
   const bool jumps = (c->flags & KN_CAMERA_UNCLAMPED_STEPS) != 0;
-  kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt, jumps);
+  const double early_frac = early_shade_fraction();
+  // (frames timed kernel by kernel run their shading in one pass: their
+  // per-launch times are not to be shared with a concurrent kernel)
+  const bool early = !pt && rays >= kEarlyShadeMinRays && early_frac > 0.0 && !(stats && stats->kernel_times);
+  kn_status st = ensure_pool(ctx, ctx->ws, rays, cells, pt, jumps, false, early);
   if (st != KN_OK) return st;
   Pool& w = ctx->ws;
   const bool split = (c->flags & KN_CAMERA_SPLIT_BF16_SHADING) && c->precision != KN_FP32;
@@ -1212,8 +1338,12 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   q.unclamped = jumps ? 1u : 0u;
   q.sample_offset = pt ? c->sample_offset : 0u;
   *ctx->h_req = q;
-  const RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, split,
-                     jumps, (uint32_t)cells, ctx->max_passes};
+  RoundCfg cfg{s->H, (int)c->precision, 1u, ctx->h_scene->march_words, ctx->h_scene->shade_words, split,
+               jumps, (uint32_t)cells, ctx->max_passes};
+  if (!pt) {   // primary frames follow their rounds through the ring
+    cfg.ring = ctx->ring_dev;
+    cfg.tag0 = (ctx->frame_seq++ & 0x1FFFFFu) << 11;
+  }
 
   const bool timed = stats && stats->kernel_times;
   std::vector<std::pair<int, int>> march_ev, shade_ev;   // event index pairs
@@ -1242,6 +1372,11 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   KN_HIP(ctx, hipMemsetAsync(w.runs, 0, 2 * w.cells * w.cs * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.hit_count, 0, w.cells * w.cs * 4, stream));
   KN_HIP(ctx, hipMemsetAsync(w.HL, 0xFF, rays * sizeof(RayRec), stream));
+  if (early) {
+    KN_HIP(ctx, hipMemsetAsync(w.ctrl2, 0, sizeof(Ctrl), stream));
+    KN_HIP(ctx, hipMemsetAsync(w.hit_count2, 0, w.cells * w.cs * 4, stream));
+  }
+  bool forked = false;
 
   RaygenArgs rg{};
   rg.sg = ctx->h_scene->sg;
@@ -1261,32 +1396,43 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     KN_HIP(ctx, launch_raygen(rg, stream));
     // every round takes at least one SDF evaluation of every live ray
     const int max_rounds = (int)c->max_steps + 2;
+    uint32_t peak = 0;
     for (int r = 0; r < max_rounds; ++r) {
       if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
       if (timed) march_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
       st = enqueue_round(ctx, w, cfg, r, r == 0 ? (uint32_t)rays : 0u, stream, e0, e1);
       if (st != KN_OK) return st;
       ++rounds;
-      // every kReadback rounds, read back how many chunks the round had; stop
-      // once an earlier readback shows an empty round (rounds enqueued after
-      // it find no work and return at once)
-      constexpr int kReadback = 4;
-      if (r % kReadback == kReadback - 1) {
-        const int slot = (r / kReadback) & 3;
-        KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[slot], &w.ctrl->n_chunks[r & 1], 4, hipMemcpyDeviceToHost,
-                                   stream));
-        KN_HIP(ctx, hipEventRecord(ctx->ev_round[slot], stream));
-        if (r >= 2 * kReadback - 1) {
-          const int prev = ((r / kReadback) - 1) & 3;
-          KN_HIP(ctx, hipEventSynchronize(ctx->ev_round[prev]));
-          if (ctx->pinned[prev] == 0) break;
+      // stop once the round kLag rounds back had no work (the rounds enqueued
+      // after it find none and return at once); its count arrives through
+      // the host-mapped ring while this round's work is queued behind it
+      constexpr int kLag = 2;
+      if (r >= kLag) {
+        uint32_t n = 0;
+        if ((st = wait_round(ctx, stream, cfg.tag0 + (uint32_t)(r - kLag), &n)) != KN_OK) return st;
+        if (n == 0) break;
+        peak = std::max(peak, n);
+        // the rounds have thinned out: the hits so far (rounds 0..r) are
+        // taken out of the hit list and binned here, then shaded on the
+        // second stream, with two workgroups per CU, beside the remaining
+        // rounds (whose hits are counted per cell in hit_count2)
+        if (early && !forked && peak >= kEarlyShadeMinChunks && (double)n < early_frac * (double)peak) {
+          const ShadeSet first{w.HL, w.hit_count, w.Uin, w.cursor2, w.chunk + 3 * w.chunks, w.ctrl2};
+          st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, nullptr, nullptr, false, 0, &first, ctx->stream2,
+                             2);
+          if (st != KN_OK) return st;
+          cfg.hit_count = w.hit_count2;
+          forked = true;
         }
       }
     }
     if ((st = ev(&e0)) != KN_OK || (st = ev(&e1)) != KN_OK) return st;
     if (timed) shade_ev.push_back({(int)next_ev - 2, (int)next_ev - 1});
-    st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, e0, e1);
+    const ShadeSet last = forked ? ShadeSet{w.HL, w.hit_count2, w.S, w.cursor, w.chunk + 2 * w.chunks, w.ctrl}
+                                 : main_shade_set(w);
+    st = enqueue_shade(ctx, w, cfg, (uint32_t)rays, stream, e0, e1, false, 0, &last);
     if (st != KN_OK) return st;
+    if (forked) KN_HIP(ctx, hipStreamWaitEvent(stream, ctx->ev_join, 0));
   } else {
     RaygenPtArgs rp{};
     rp.sg = rg.sg;
@@ -1352,12 +1498,20 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
     KN_HIP(ctx, launch_resolve(ra, stream));
   }
   KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr], &w.ctrl->scan_err, 4, hipMemcpyDeviceToHost, stream));
+  if (forked)
+    KN_HIP(ctx, hipMemcpyAsync(&ctx->pinned[kPinnedScanErr2], &w.ctrl2->scan_err, 4, hipMemcpyDeviceToHost, stream));
   KN_HIP(ctx, hipEventRecord(ctx->ev_end, stream));
   KN_HIP(ctx, hipEventSynchronize(ctx->ev_end));
   if ((st = check_scan(ctx, ctx->pinned[kPinnedScanErr])) != KN_OK) return st;
+  if (forked && (st = check_scan(ctx, ctx->pinned[kPinnedScanErr2])) != KN_OK) return st;
   if (stats) {
     Ctrl hc;
     KN_HIP(ctx, hipMemcpy(&hc, w.ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost));
+    if (forked) {
+      uint32_t h2 = 0;
+      KN_HIP(ctx, hipMemcpy(&h2, &w.ctrl2->n_hits, 4, hipMemcpyDeviceToHost));
+      hc.n_hits += h2;
+    }
     float ms = 0.0f;
     KN_HIP(ctx, hipEventElapsedTime(&ms, ctx->ev_start, ctx->ev_end));
     stats->gpu_ms = ms;

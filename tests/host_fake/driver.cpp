@@ -354,6 +354,27 @@ void case_world() {
   expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy frees the remaining worlds");
 }
 
+// a primary frame large enough for early shading (the fake's round counts
+// fall, so the first shading pass is forked onto the second stream)
+void case_render_early() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, (uint64_t)2 << 30, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(4, 64, 17);
+  kn_scene_desc d = desc_of(s, kAll);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  for (kn_precision p : {KN_BF16, KN_FP32}) {
+    DevFrame fr((size_t)1024 * 512);
+    kn_camera c = camera(1024, 512, p);
+    kn_stats st{};
+    st.kernel_times = 1;
+    expect(kn_render(ctx, id, &c, &fr.f, &st) == KN_OK, "large frame with early shading");
+    expect(st.rounds >= 9, "rounds went on past the fork");
+  }
+  kn_scene_destroy(ctx, id);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
 void case_query_scan_err() {
   kn_ctx* ctx = nullptr;
   expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
@@ -425,6 +446,7 @@ int main(int argc, char** argv) {
   else if (c == "query_scan_err") case_query_scan_err();
   else if (c == "grid_eikonal") case_grid_eikonal();
   else if (c == "world") case_world();
+  else if (c == "render_early") case_render_early();
   else if (c == "noalloc") case_noalloc();
   else if (c == "serve") case_serve(false);
   else if (c == "serve_scan_err") case_serve(true);

@@ -96,7 +96,21 @@ hipError_t hipHostMalloc(void** p, size_t bytes, unsigned) {
   std::memset(*p, 0xA5, bytes);
   return hipSuccess;
 }
-hipError_t hipHostFree(void* p) { std::free(p); return hipSuccess; }
+hipError_t hipHostFree(void* p) {
+  (void)untrack(p);   // mapped host memory is registered as device memory
+  std::free(p);
+  return hipSuccess;
+}
+// mapped host memory: the device address is the host address; registered as
+// device memory so that kernel stubs may be handed it
+hipError_t hipHostGetDevicePointer(void** dev, void* host, unsigned) {
+  *dev = host;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_live.emplace(static_cast<const char*>(host), (size_t)kn::kRoundRing * 8);
+  return hipSuccess;
+}
+hipError_t hipStreamQuery(hipStream_t) { return hipSuccess; }
+hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) { return hipSuccess; }
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind) {
   if (kind == hipMemcpyHostToDevice || kind == hipMemcpyDeviceToDevice) need(dst, bytes, "copy destination");
   if (kind == hipMemcpyDeviceToHost || kind == hipMemcpyDeviceToDevice) need(src, bytes, "copy source");
@@ -193,6 +207,15 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t) {
   need(a.grab, kGroups * kGroupStride * 4, "work cursors");
   need(a.err, 4, "scan_err");
   *a.n_chunks = 0u;
+  if (a.host_ring) {
+    // the chunk count the host sees: 0, or with KN_FAKE_ROUND_CHUNKS set, a
+    // count that falls from 2000 by 250 per round (so that a large frame
+    // takes its early-shading branch)
+    need(a.host_ring, kRoundRing * 8, "round ring");
+    const uint32_t r = a.ring_tag & 2047u;
+    const uint32_t n = std::getenv("KN_FAKE_ROUND_CHUNKS") && r < 8u ? 2000u - 250u * r : 0u;
+    a.host_ring[a.ring_tag % kRoundRing] = ((unsigned long long)a.ring_tag << 32) | n;
+  }
   if (std::getenv("KN_FAKE_SCAN_ERR")) *a.err |= 1u;
   return hipSuccess;
 }

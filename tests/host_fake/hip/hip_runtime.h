@@ -15,7 +15,7 @@
 #define HIP_SYMBOL(x) (&(x))
 
 typedef enum hipError_t { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2,
-                          hipErrorNoDevice = 100 } hipError_t;
+                          hipErrorNoDevice = 100, hipErrorNotReady = 600 } hipError_t;
 typedef enum hipMemcpyKind { hipMemcpyHostToHost = 0, hipMemcpyHostToDevice = 1, hipMemcpyDeviceToHost = 2,
                              hipMemcpyDeviceToDevice = 3, hipMemcpyDefault = 4 } hipMemcpyKind;
 struct FakeStream;
@@ -34,6 +34,8 @@ inline uint4 make_uint4(uint32_t x, uint32_t y, uint32_t z, uint32_t w) { return
 constexpr unsigned hipStreamNonBlocking = 1u;
 constexpr unsigned hipEventDisableTiming = 2u;
 constexpr unsigned hipHostMallocDefault = 0u;
+constexpr unsigned hipHostMallocMapped = 2u;
+constexpr unsigned hipHostMallocCoherent = 0x40000000u;
 
 hipError_t hipGetDeviceCount(int* n);
 hipError_t hipSetDevice(int dev);
@@ -47,6 +49,9 @@ hipError_t hipMalloc(T** p, size_t bytes) { return hipMalloc(reinterpret_cast<vo
 hipError_t hipFree(void* p);
 hipError_t hipHostMalloc(void** p, size_t bytes, unsigned flags);
 hipError_t hipHostFree(void* p);
+hipError_t hipHostGetDevicePointer(void** dev, void* host, unsigned flags);
+hipError_t hipStreamQuery(hipStream_t st);
+hipError_t hipStreamWaitEvent(hipStream_t st, hipEvent_t e, unsigned flags);
 hipError_t hipMemcpy(void* dst, const void* src, size_t bytes, hipMemcpyKind kind);
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t st);
 hipError_t hipMemset(void* dst, int v, size_t bytes);

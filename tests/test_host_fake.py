@@ -38,13 +38,15 @@ def driver(tmp_path_factory):
 
 
 @pytest.mark.parametrize("case", ["scenes", "validation", "render", "render_scan_err", "query_scan_err", "noalloc",
-                                  "grid_eikonal", "world",
+                                  "grid_eikonal", "world", "render_early",
                                   "serve", "serve_scan_err"])
 def test_host_runtime_under_sanitizers(driver, case):
     env = dict(os.environ)
     env.pop("KN_FAKE_SCAN_ERR", None)
     if case.endswith("scan_err"):
         env["KN_FAKE_SCAN_ERR"] = "1"
+    if case == "render_early":
+        env["KN_FAKE_ROUND_CHUNKS"] = "1"
     env["ASAN_OPTIONS"] = "detect_leaks=1:abort_on_error=0"
     res = subprocess.run([driver, case], capture_output=True, text=True, env=env, timeout=600)
     out = res.stdout + res.stderr
