@@ -35,10 +35,13 @@ TOL_HIT_MASK = 0.999
 
 
 def angle_deg(a: np.ndarray, b: np.ndarray) -> np.ndarray:
-    na = np.linalg.norm(a, axis=-1)
-    nb = np.linalg.norm(b, axis=-1)
-    c = np.sum(a * b, axis=-1) / np.maximum(na * nb, 1e-300)
-    return np.degrees(np.arccos(np.clip(c, -1.0, 1.0)))
+    """Angle between vectors in degrees, in float64 from atan2(|a x b|, a.b),
+    which stays accurate for small angles (arccos of a float32 cosine cannot
+    resolve angles below about 0.02 degrees)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    cr = np.linalg.norm(np.cross(a, b), axis=-1)
+    return np.degrees(np.arctan2(cr, np.sum(a * b, axis=-1)))
 
 
 def perturbed(scene: synth.Scene, rel: float, seed: int) -> synth.Scene:

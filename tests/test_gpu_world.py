@@ -130,8 +130,6 @@ def test_world_primary_matches_oracle(ctx, world):
     same = og == orf
     prim = same & (orf <= -2)
     assert np.abs(depth[prim] - ref["depth"][prim]).max() <= 1e-5 * max(1.0, ref["depth"][prim].max())
-    # near a sphere's silhouette the hit point moves fast with the ray, so the
-    # float32 ray's rounding shows in the normal there
     an = P.angle_deg(normal[prim], ref["normal"][prim])
     log(f"primitive normals: {np.mean(an <= 0.01):.5f} within 0.01 deg, max {an.max():.4f} deg; per primitive max "
         + str({int(k): float(an[orf[prim] == k].max()) for k in (-2, -3, -4)}))
@@ -139,7 +137,7 @@ def test_world_primary_matches_oracle(ctx, world):
     for q in pi:
         log(f"  pixel {q}: object {orf[q]}, gpu n {normal[q].tolist()} d {depth[q]:.7f}; "
             f"oracle n {ref['normal'][q].round(7).tolist()} d {ref['depth'][q]:.7f}")
-    assert np.mean(an <= 0.01) >= 0.99 and an.max() <= 0.1
+    assert an.max() <= 0.01
     assert np.abs(rgb[prim] - ref["rgb"][prim]).max() <= 1e-7
     scale = np.array([INST_A[2], INST_B[2]])
     inst = same & (orf >= 0)
