@@ -293,11 +293,13 @@ def _fstop_bound(scene, mode, n=6000, seed=11):
     return 1.5 * float(np.abs(lowp - f["d"][near]).max()), int(near.size)
 
 
-@pytest.mark.parametrize("precision,split", [("bf16", False), ("bf16", True), ("fp8", False), ("fp8", True)])
-def test_render_c3_lowp_against_oracle(ctx, precision, split):
+@pytest.mark.parametrize("cfg,precision,split", [("c3", "bf16", False), ("c3", "bf16", True), ("c3", "fp8", False),
+                                                ("c3", "fp8", True), ("c2", "bf16", False), ("c2", "fp8", False)])
+def test_render_lowp_against_oracle(ctx, cfg, precision, split):
     """The headline frames: C3 (16^3, H=64, 1920x1080, S=128) marched in bf16
     or fp8, in the launch configuration the benchmark times, against the FP64
-    oracle on seeded pixel samples of two orbit views.
+    oracle on seeded pixel samples of two orbit views; likewise C2 (16^3,
+    H=32, 800x800, S=128).
 
     Asserted (whatever the march precision, refinement and shading, with
     float32 weights or, in the split variant, on split-bf16 MFMA, must land on
@@ -316,21 +318,21 @@ def test_render_c3_lowp_against_oracle(ctx, precision, split):
     Reported (and kept): hit agreement with FP64 and depth / normal / colour
     p50 / p99 / max over the pixels where both hit."""
     from oracle import quant
-    c = synth.CONFIGS["c3"]
-    sc = synth.config_scene("c3")
+    c = synth.CONFIGS[cfg]
+    sc = synth.config_scene(cfg)
     sid = ctx.scene_create(sc, precisions=(precision,))
     bound, nb = _fstop_bound(sc, precision)
     log(f"{precision}: stated march-stop bound {bound:.3e} (from {nb} points near the surface)")
     os_ = O.OracleScene.from_scene(sc)
-    for vi, view in enumerate(synth.config_views("c3")[:2]):
+    for vi, view in enumerate(synth.config_views(cfg)[:2]):
         out = _render(ctx, sid, view, c["width"], c["height"], c["max_steps"], c["eps"], precision=precision,
                       split=split)
         pix = synth.sample_pixels(c["width"], c["height"], 2500, seed=c["seed"] + 40 + vi)
         g = P.gpu_arrays(out, pix)
         rep = P.compare(sc, view, c["width"], c["height"], c["max_steps"], c["eps"], g, pixels=pix)
         tag = f"{precision}{'_split' if split else ''}"
-        log(f"C3 {tag} view {vi}:", rep.as_dict())
-        P.record(f"c3_{tag}_view{vi}", dict(hit_agree=rep.hit_agree, n=rep.n, **rep.err_all,
+        log(f"{cfg.upper()} {tag} view {vi}:", rep.as_dict())
+        P.record(f"{cfg}_{tag}_view{vi}", dict(hit_agree=rep.hit_agree, n=rep.n, **rep.err_all,
                                                   point_n=rep.point_n, point_bad=rep.point_bad,
                                                   replay_n=rep.replay_n, replay_bad=rep.replay_bad,
                                                   fstop_max=rep.fstop_max, fstop_bound=bound))
