@@ -387,6 +387,11 @@ kn_status kn_render_world(kn_ctx* ctx, kn_world_id world, const kn_camera* cam, 
  * with continuous batching (requests arriving while others run join the
  * shared ray pool as memory allows).
  * --------------------------------------------------------------------- */
+/* Starts the loop with a ray pool sized to what the HBM budget leaves (at
+ * most 32 M rays).  When the budget leaves too little, the workspace that
+ * kn_render keeps between calls is released first (the next kn_render
+ * allocates it again).  Errors: KN_E_INVALID, KN_E_BUSY (already running),
+ * KN_E_NOMEM, KN_E_DEVICE. */
 kn_status kn_serve_start(kn_ctx* ctx, uint32_t max_inflight, kn_precision precision);
 kn_status kn_serve_submit(kn_ctx* ctx, kn_scene_id scene, const kn_camera* cam,
                           const kn_frame* frame, kn_request_id* out);

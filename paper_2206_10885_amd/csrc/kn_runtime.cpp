@@ -1313,6 +1313,7 @@ kn_status render_frame(kn_ctx* ctx, KnScene* s, const kn_camera* c, const kn_fra
   const size_t cells = (size_t)s->N * s->N * s->N;
   const bool jumps = (c->flags & KN_CAMERA_UNCLAMPED_STEPS) != 0;
   const double early_frac = early_shade_fraction();
+
   // (frames timed kernel by kernel run their shading in one pass: their
   // per-launch times are not to be shared with a concurrent kernel)
   const bool early = !pt && rays >= kEarlyShadeMinRays && early_frac > 0.0 && !(stats && stats->kernel_times);
@@ -2533,13 +2534,23 @@ kn_status kn_serve_start(kn_ctx* ctx, uint32_t max_inflight, kn_precision precis
   std::lock_guard<std::mutex> lk(ctx->serve_mu);
   if (ctx->serve) return fail(KN_E_BUSY, "serving loop already running");
   // ray state: what the budget leaves, at most 32 M rays
-  const uint64_t used = ctx->used.load();
-  const uint64_t avail = ctx->budget > used ? ctx->budget - used : 0;
   const size_t cell_cap = (size_t)1 << 18;
   const size_t fixed = pool_bytes(0, cell_cap, cell_cap + 2);
   // bytes per pool ray, from the pool's own size formula (rounded up)
   const size_t probe = (size_t)1 << 20;
   const size_t per_ray = (pool_bytes(probe, cell_cap, probe / kShadeChunk + cell_cap + 2) - fixed) / probe + 1;
+  uint64_t used = ctx->used.load();
+  uint64_t avail = ctx->budget > used ? ctx->budget - used : 0;
+  if (avail < fixed + probe * per_ray && ctx->ws.ctrl) {
+    // the workspace of kn_render is grow-only; its memory goes to the
+    // serving pool (the next kn_render allocates a workspace again)
+    std::lock_guard<std::mutex> rk(ctx->render_mu);
+    KN_HIP(ctx, hipDeviceSynchronize());
+    ctx->used -= ctx->ws.bytes;
+    free_pool(ctx->ws);
+    used = ctx->used.load();
+    avail = ctx->budget > used ? ctx->budget - used : 0;
+  }
   if (avail < fixed + probe * per_ray) return fail(KN_E_NOMEM, "HBM budget leaves no room for a serving pool");
   const size_t cap = std::min<size_t>((avail - fixed) / per_ray, (size_t)32 << 20);
   std::shared_ptr<kn::ServeLoop> loop(new kn::ServeLoop(ctx, max_inflight, precision));

@@ -339,6 +339,73 @@ def test_progressive_accumulation_equals_one_call(ctx, kind):
     ctx.scene_destroy(sid)
 
 
+def test_one_scene_placed_twice(ctx):
+    """Two instances of one resident scene (shared weights) at different
+    scales and places, with a ground box: objects, depths (world units),
+    normals and colours against the oracle."""
+    sc = synth.sphere_scene(8, 64, 0.6, 0.0, seed=43)
+    sid = ctx.scene_create(sc, precisions=("bf16",))
+    inst = [((-1.1, 0.0, 0.0), 0.9), ((1.2, -0.2, -0.6), 0.6)]
+    ground = [(PB, [-5.0, -1.4, -5.0, 5.0, -1.0, 5.0], (0.5, 0.6, 0.7))]
+    wid = ctx.world_create([(sid, t, s) for t, s in inst], ground)
+    os_ = O.OracleScene.from_scene(sc)
+    ow = O.OracleWorld([(os_, t, s) for t, s in inst], ground)
+    view = synth.View(eye=(0.2, 1.4, 4.2), look_at=(0.0, -0.2, 0.0), tan_half_diag=0.6)
+    W, H = 96, 72
+    for precision in ("fp32", "bf16"):
+        g = _world_render(ctx, wid, view, W, H, 128, precision)
+        ref = ow.render(view, W, H, 128, 1e-4)
+        og = _objects(g, [(0, 512), (512, 1024)])
+        orf = ref["object"].astype(np.int64)
+        inst_px = (og == orf) & (orf >= 0)
+        scale = np.array([s for _, s in inst])
+        dd = np.abs(g["depth"].reshape(-1)[inst_px] - ref["depth"][inst_px]) / scale[orf[inst_px]]
+        an = P.angle_deg(g["normal"].reshape(-1, 3)[inst_px], ref["normal"][inst_px])
+        dc = np.abs(g["rgb"].reshape(-1, 3)[inst_px] - ref["rgb"][inst_px]).max(1)
+        log(f"shared weights {precision}: agreement {np.mean(og == orf):.5f}, objects "
+            f"{ {int(k): int(np.sum(orf == k)) for k in np.unique(orf)} }, local depth max {dd.max():.2e}, "
+            f"normal max {an.max():.4f} deg, rgb max {dc.max():.2e}")
+        assert np.sum(orf == 0) > 300 and np.sum(orf == 1) > 150
+        if precision == "fp32":
+            assert np.mean(og == orf) >= 0.999
+            bad = (dd > P.TOL_DEPTH) | (an > P.TOL_NORMAL_DEG) | (dc > P.TOL_RGB)
+            assert bad.mean() <= 1e-3, bad.sum()
+        else:
+            # a bf16 march may stop at another crossing where the surface is
+            # grazed; as for the world's bf16 test: objects and refined depths
+            assert np.mean(og == orf) >= 0.995
+            assert np.median(dd) < 1e-5
+    ctx.world_destroy(wid)
+    ctx.scene_destroy(sid)
+
+
+def test_world_path_trace_matches_oracle(ctx):
+    """Path tracing a world of two scaled instances (smooth spheres) and a
+    ground box under an environment map, 2 spp, 2 bounces: per pixel against
+    the oracle (the same Philox samples; float32 against FP64 along paths
+    that cross instances and primitives)."""
+    a = synth.sphere_scene(8, 64, 0.6, 0.0, seed=44)
+    b = synth.sphere_scene(4, 32, 0.5, 0.0, seed=45)
+    sa, sb = ctx.scene_create(a), ctx.scene_create(b)
+    inst = [(sa, a, (-0.9, 0.0, 0.0), 0.8), (sb, b, (1.0, 0.1, -0.3), 0.7)]
+    ground = [(PB, [-4.0, -1.2, -4.0, 4.0, -0.9, 4.0], (0.7, 0.7, 0.6)),
+              (PS, [0.1, 0.9, -1.2, 0.3], (0.9, 0.3, 0.2))]
+    wid = ctx.world_create([(sid, t, s) for sid, _, t, s in inst], ground)
+    ow = O.OracleWorld([(O.OracleScene.from_scene(sc), t, s) for _, sc, t, s in inst], ground)
+    env = synth.env_map(128, 64, seed=5005)
+    W, H = 64, 48
+    g = _world_render(ctx, wid, VIEW, W, H, 128, spp=2, bounces=2, seed=123, env=env)
+    ref = ow.path_trace(VIEW, W, H, 128, 1e-4, 2, 2, 123, env)
+    d = np.abs(g["rgb"].reshape(-1, 3) - ref["rgb"]).max(1)
+    log(f"world path trace: rgb diff p50 {np.median(d):.2e} p99 {np.percentile(d, 99):.2e} max {d.max():.2e}; "
+        f"within 1e-4: {np.mean(d < 1e-4):.4f}; primary hits {int(g['hit'].sum())}")
+    assert np.mean(g["hit"].reshape(-1) == ref["hit"]) >= 0.999
+    assert np.mean(d < 1e-4) >= 0.98
+    ctx.world_destroy(wid)
+    ctx.scene_destroy(sa)
+    ctx.scene_destroy(sb)
+
+
 def test_empty_and_tiny_worlds(ctx):
     """An empty world renders background (primary) or the environment (path
     tracing); a 1x1 frame of a world renders its one pixel as the oracle."""
