@@ -375,6 +375,33 @@ void case_render_early() {
   expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
 }
 
+// a budget the render workspace of a large frame leaves too little of for
+// a serving pool: kn_serve_start releases the workspace, and rendering
+// afterwards allocates it again
+void case_serve_release() {
+  kn_ctx* ctx = nullptr;
+  expect(kn_ctx_create(0, (uint64_t)480 << 20, &ctx) == KN_OK, "ctx create");
+  HostScene s = make_scene(4, 32, 19);
+  kn_scene_desc d = desc_of(s, 1u << KN_BF16);
+  kn_scene_id id = 0;
+  expect(kn_scene_create(ctx, &d, &id) == KN_OK, "scene create");
+  {
+    DevFrame fr((size_t)2048 * 2048);
+    kn_camera c = camera(2048, 2048, KN_BF16);
+    expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_OK, "large frame (workspace grows)");
+  }
+  expect(kn_serve_start(ctx, 4, KN_BF16) == KN_OK, "serve start after releasing the workspace");
+  DevFrame fr(64 * 48);
+  kn_camera c = camera(64, 48, KN_BF16);
+  kn_request_id r = 0;
+  expect(kn_serve_submit(ctx, id, &c, &fr.f, &r) == KN_OK && kn_serve_poll(ctx, r, -1, nullptr) == KN_OK,
+         "served frame");
+  expect(kn_serve_stop(ctx) == KN_OK, "serve stop");
+  expect(kn_render(ctx, id, &c, &fr.f, nullptr) == KN_OK, "render after serving (workspace allocated again)");
+  kn_scene_destroy(ctx, id);
+  expect(kn_ctx_destroy(ctx) == KN_OK, "ctx destroy");
+}
+
 void case_query_scan_err() {
   kn_ctx* ctx = nullptr;
   expect(kn_ctx_create(0, 0, &ctx) == KN_OK, "ctx create");
@@ -447,6 +474,7 @@ int main(int argc, char** argv) {
   else if (c == "grid_eikonal") case_grid_eikonal();
   else if (c == "world") case_world();
   else if (c == "render_early") case_render_early();
+  else if (c == "serve_release") case_serve_release();
   else if (c == "noalloc") case_noalloc();
   else if (c == "serve") case_serve(false);
   else if (c == "serve_scan_err") case_serve(true);

@@ -38,7 +38,7 @@ def driver(tmp_path_factory):
 
 
 @pytest.mark.parametrize("case", ["scenes", "validation", "render", "render_scan_err", "query_scan_err", "noalloc",
-                                  "grid_eikonal", "world", "render_early",
+                                  "grid_eikonal", "world", "render_early", "serve_release",
                                   "serve", "serve_scan_err"])
 def test_host_runtime_under_sanitizers(driver, case):
     env = dict(os.environ)
