@@ -80,53 +80,68 @@ __device__ __forceinline__ float sigmoid(float x) {
 
 __device__ __forceinline__ float bf16_round(float x) { return (float)(__bf16)x; }
 
-// Per-lane description of the encoding slots this lane computes.
+// Per-lane description of the encoding slots this lane computes (the slot
+// layout of pe_index: slots 3a, 3a + 1 and 3a + 2 read axis a in every lane
+// group, slot 9 holds the raw coordinate or padding).
 struct PeLane {
-  uint32_t axes;     // 2 bits per slot: axis of the component (3 = padding)
-  float scale[kPeSlots];   // 2^(k-1): revolutions per unit of x (sin/cos slots)
-  float dscale[kPeSlots];  // pi 2^k: derivative factor of sin/cos slots
+  float s0, s2;    // revolutions per unit of x: 2^(k-1) of slots 3a, 3a+1 (k = g) and 3a+2 (k = 4 + g%2)
+  float d0, d2;    // derivative factors pi 2^k of the same slots
+  float ph2;       // phase of slot 3a+2 in revolutions: 1/4 (a cosine) for g >= 2
   int g;
 };
+
+__host__ __device__ constexpr bool pe_layout_as_read() {
+  for (int g = 0; g < 4; ++g) {
+    if (pe_index(9, g) != (g < 3 ? g : -1)) return false;
+    for (int a = 0; a < 3; ++a) {
+      const int k2 = 4 + (g & 1);
+      if (pe_index(3 * a, g) != 3 + 12 * a + 2 * g) return false;
+      if (pe_index(3 * a + 1, g) != 3 + 12 * a + 2 * g + 1) return false;
+      if (pe_index(3 * a + 2, g) != 3 + 12 * a + 2 * k2 + (g >= 2 ? 1 : 0)) return false;
+    }
+  }
+  return true;
+}
+static_assert(pe_layout_as_read(), "the encoding evaluators read the slot layout of pe_index");
 
 __device__ __forceinline__ PeLane make_pe_lane(int g) {
   PeLane L;
   L.g = g;
-  L.axes = 0;
-#pragma unroll
-  for (int j = 0; j < kPeSlots; ++j) {
-    int idx = pe_index(j, g);
-    int ax = idx < 0 ? 3 : (idx < 3 ? idx : (idx - 3) / 12);
-    int k = idx < 3 ? 0 : ((idx - 3) % 12) / 2;
-    L.axes |= (uint32_t)ax << (2 * j);
-    L.scale[j] = ldexpf(1.0f, k - 1);
-    L.dscale[j] = 3.14159265358979f * ldexpf(1.0f, k);
-  }
+  L.s0 = ldexpf(1.0f, g - 1);
+  L.s2 = ldexpf(1.0f, 3 + (g & 1));
+  L.d0 = 3.14159265358979f * ldexpf(1.0f, g);
+  L.d2 = 3.14159265358979f * ldexpf(1.0f, 4 + (g & 1));
+  L.ph2 = g >= 2 ? 0.25f : 0.0f;
   return L;
 }
 
-__device__ __forceinline__ float pick(uint32_t ax, float x, float y, float z) {
-  return ax == 0 ? x : (ax == 1 ? y : z);
+// the raw coordinate of slot 9 (lane groups 0..2) or its padding (group 3)
+__device__ __forceinline__ float pe_raw(int g, float x, float y, float z) {
+  return g == 0 ? x : (g == 1 ? y : (g == 2 ? z : 0.0f));
 }
 
-// Encoding values of this lane's slots at local position (x, y, z):
-// slot 0 is raw (g < 3) or a sine (g == 3); slots 1..4 sines; 5..8 cosines;
-// slot 9 sine (g == 0), cosine (g == 1, 2) or padding (g == 3).
+// Encoding values of this lane's slots at local position (x, y, z).
+// PHASE: slot 3a + 2 takes its cosines as sines a quarter revolution on
+// (one transcendental instead of two and a select; the argument is rounded
+// once more, by at most 2^-21 revolutions at the highest frequency, which
+// the low-precision march evaluators round away with the layer input).
+template <bool PHASE>
 __device__ __forceinline__ void pe_values(const PeLane& L, float x, float y, float z,
                                           float (&v)[kPeSlots]) {
-  {
-    float xa = pick(L.axes & 3u, x, y, z);
-    float s = sin_rev(xa * L.scale[0]);
-    v[0] = L.g == 3 ? s : xa;
-  }
+  const float xs[3] = {x, y, z};
 #pragma unroll
-  for (int j = 1; j <= 4; ++j) v[j] = sin_rev(pick((L.axes >> (2 * j)) & 3u, x, y, z) * L.scale[j]);
-#pragma unroll
-  for (int j = 5; j <= 8; ++j) v[j] = cos_rev(pick((L.axes >> (2 * j)) & 3u, x, y, z) * L.scale[j]);
-  {
-    float r = pick((L.axes >> 18) & 3u, x, y, z) * L.scale[9];
-    float s = sin_rev(r), c = cos_rev(r);
-    v[9] = L.g == 0 ? s : (L.g == 3 ? 0.0f : c);
+  for (int a = 0; a < 3; ++a) {
+    const float r = xs[a] * L.s0;
+    v[3 * a] = sin_rev(r);
+    v[3 * a + 1] = cos_rev(r);
+    if constexpr (PHASE) {
+      v[3 * a + 2] = sin_rev(fmaf(xs[a], L.s2, L.ph2));
+    } else {
+      const float r2 = xs[a] * L.s2;
+      v[3 * a + 2] = L.g < 2 ? sin_rev(r2) : cos_rev(r2);
+    }
   }
+  v[9] = pe_raw(L.g, x, y, z);
 }
 
 // Encoding values of a value column (s == 0) or of the derivative along
@@ -134,50 +149,47 @@ __device__ __forceinline__ void pe_values(const PeLane& L, float x, float y, flo
 // slots, for forward-mode differentiation in the shading kernel.
 __device__ __forceinline__ void pe_values_tangent(const PeLane& L, int s, float inv_half, float x,
                                                   float y, float z, float (&v)[kPeSlots]) {
+  const float xs[3] = {x, y, z};
+  const bool sin2 = L.g < 2;
 #pragma unroll
-  for (int j = 0; j < kPeSlots; ++j) {
-    uint32_t ax = (L.axes >> (2 * j)) & 3u;
-    float xa = pick(ax, x, y, z);
-    float r = xa * L.scale[j];
-    float sn = sin_rev(r), cs = cos_rev(r);
-    // kind of the slot for this lane group
-    bool raw = (j == 0 && L.g < 3);
-    bool pad = (j == 9 && L.g == 3);
-    bool is_sin = (j == 0 && L.g == 3) || (j >= 1 && j <= 4) || (j == 9 && L.g == 0);
-    float val;
+  for (int a = 0; a < 3; ++a) {
+    const float r = xs[a] * L.s0, r2 = xs[a] * L.s2;
+    const float sn = sin_rev(r), cs = cos_rev(r), sn2 = sin_rev(r2), cs2 = cos_rev(r2);
     if (s == 0) {
-      val = raw ? xa : (pad ? 0.0f : (is_sin ? sn : cs));
+      v[3 * a] = sn;
+      v[3 * a + 1] = cs;
+      v[3 * a + 2] = sin2 ? sn2 : cs2;
     } else {
-      bool on = (int)ax == s - 1;
-      float dv = raw ? 1.0f : (pad ? 0.0f : (is_sin ? cs * L.dscale[j] : -sn * L.dscale[j]));
-      val = on ? dv * inv_half : 0.0f;
+      const bool on = a == s - 1;
+      v[3 * a] = on ? cs * L.d0 * inv_half : 0.0f;
+      v[3 * a + 1] = on ? -sn * L.d0 * inv_half : 0.0f;
+      v[3 * a + 2] = on ? (sin2 ? cs2 : -sn2) * L.d2 * inv_half : 0.0f;
     }
-    v[j] = val;
   }
+  v[9] = s == 0 ? pe_raw(L.g, x, y, z) : (L.g == s - 1 ? inv_half : 0.0f);
 }
 
 // Encoding values of a value column (value == true) or of the derivative
 // along a direction whose local-coordinate rates are (tx, ty, tz) per axis.
 __device__ __forceinline__ void pe_values_dir(const PeLane& L, bool value, float tx, float ty, float tz,
                                               float x, float y, float z, float (&v)[kPeSlots]) {
+  const float xs[3] = {x, y, z}, ts[3] = {tx, ty, tz};
+  const bool sin2 = L.g < 2;
 #pragma unroll
-  for (int j = 0; j < kPeSlots; ++j) {
-    uint32_t ax = (L.axes >> (2 * j)) & 3u;
-    float xa = pick(ax, x, y, z);
-    float r = xa * L.scale[j];
-    float sn = sin_rev(r), cs = cos_rev(r);
-    bool raw = (j == 0 && L.g < 3);
-    bool pad = (j == 9 && L.g == 3);
-    bool is_sin = (j == 0 && L.g == 3) || (j >= 1 && j <= 4) || (j == 9 && L.g == 0);
-    float val;
+  for (int a = 0; a < 3; ++a) {
+    const float r = xs[a] * L.s0, r2 = xs[a] * L.s2;
+    const float sn = sin_rev(r), cs = cos_rev(r), sn2 = sin_rev(r2), cs2 = cos_rev(r2);
     if (value) {
-      val = raw ? xa : (pad ? 0.0f : (is_sin ? sn : cs));
+      v[3 * a] = sn;
+      v[3 * a + 1] = cs;
+      v[3 * a + 2] = sin2 ? sn2 : cs2;
     } else {
-      float dv = raw ? 1.0f : (pad ? 0.0f : (is_sin ? cs * L.dscale[j] : -sn * L.dscale[j]));
-      val = pad ? 0.0f : dv * pick(ax, tx, ty, tz);
+      v[3 * a] = cs * L.d0 * ts[a];
+      v[3 * a + 1] = -sn * L.d0 * ts[a];
+      v[3 * a + 2] = (sin2 ? cs2 : -sn2) * L.d2 * ts[a];
     }
-    v[j] = val;
   }
+  v[9] = value ? pe_raw(L.g, x, y, z) : pe_raw(L.g, tx, ty, tz);
 }
 
 // LDS visibility between lanes of one wave (no workgroup barrier).

@@ -1337,7 +1337,12 @@ __device__ __forceinline__ CellBox cell_box(const SceneGeom& sg, uint32_t lc) {
 }
 
 // Nearest exit plane of cell (ix,iy,iz) along the ray; *axis gets its axis
-// (ties to the lowest axis).
+// (ties to the lowest axis).  RCP: the distance to each plane is taken
+// through the hardware reciprocal of the direction (within 2 ulp of the
+// quotient) instead of a correctly rounded division; the low-precision
+// marches use it, as the exit only bounds their steps and the next cell
+// starts from the same value.
+template <bool RCP = false>
 __device__ __forceinline__ float cell_exit(const SceneGeom& sg, const CellBox& cb, const float o[3],
                                            const float d[3], int* axis) {
   const int idx[3] = {cb.ix, cb.iy, cb.iz};
@@ -1347,7 +1352,7 @@ __device__ __forceinline__ float cell_exit(const SceneGeom& sg, const CellBox& c
   for (int k = 0; k < 3; ++k) {
     if (d[k] != 0.0f) {
       float plane = sg.bmin[k] + (float)(idx[k] + (d[k] > 0.0f ? 1 : 0)) * sg.side[k];
-      float tk = (plane - o[k]) / d[k];
+      float tk = RCP ? (plane - o[k]) * __builtin_amdgcn_rcpf(d[k]) : (plane - o[k]) / d[k];
       if (tk < best) {
         best = tk;
         ba = k;
@@ -1375,8 +1380,11 @@ struct Job {
 };
 
 // (plain LDS reads: the workgroup barrier before every call orders them)
+// (the fields are uniform: taken into scalar registers, so that the work
+// derived from them stays on the scalar unit)
 __device__ __forceinline__ Job read_job(const uint32_t* s) {
-  return Job{s[0], s[1], s[2], s[3], s[5], s[4] != 0u};
+  auto u = [](uint32_t x) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)x); };
+  return Job{u(s[0]), u(s[1]), u(s[2]), u(s[3]), u(s[5]), u(s[4]) != 0u};
 }
 
 // Thread 0's source of march work items.  Items are taken one at a time from
@@ -1563,7 +1571,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       const uint32_t qs = st.pix >> kPixBits;
       const float o[3] = {st.ox, st.oy, st.oz}, d[3] = {st.dx, st.dy, st.dz};
       int eax;
-      const float ce = cell_exit(sg, cb, o, d, &eax);
+      const float ce = cell_exit<P != kPrecF32>(sg, cb, o, d, &eax);
       s_t[tid] = r.t;
       s_te[tid] = r.t_entry;
       for (int k = 0; k < 3; ++k) {
@@ -1631,7 +1639,7 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
 #pragma unroll
           for (int k = 0; k < 3; ++k)
             xl[k] = valid[u] ? fmaf(fmaf(t[u], d[u][k], o[u][k]), sg.inv_half[k], cb.cs[k]) : 0.0f;
-          pe_values(pl, xl[0], xl[1], xl[2], v[u]);
+          pe_values<P != kPrecF32>(pl, xl[0], xl[1], xl[2], v[u]);
         }
         float f[2];
         if constexpr (PAIR) {
@@ -2368,7 +2376,7 @@ __global__ __launch_bounds__(256) void k_query_d(QueryArgs a) {
 #pragma unroll
       for (int k = 0; k < 3; ++k) xl[k] = valid ? fmaf(a.pts[3 * (size_t)pi + k], sg.inv_half[k], cb.cs[k]) : 0.0f;
       float v[kPeSlots];
-      pe_values(pl, xl[0], xl[1], xl[2], v);
+      pe_values<false>(pl, xl[0], xl[1], xl[2], v);
       const float f = march_eval<H, P>(s_block, lane, g, v, a.spk);
       if (valid && g == 0) a.d_out[pi] = f;
     }
@@ -2506,7 +2514,7 @@ __global__ __launch_bounds__(256) void k_grid_d(GridArgs a) {
       uint64_t o = 0;
       if (valid) o = grid_point(a, gi, cb, q, xl);
       float v[kPeSlots];
-      pe_values(pl, xl[0], xl[1], xl[2], v);
+      pe_values<false>(pl, xl[0], xl[1], xl[2], v);
       const float f = march_eval<H, P>(s_block, lane, g, v, a.spk);
       if (valid && g == 0) a.d_out[o] = f;
     }
