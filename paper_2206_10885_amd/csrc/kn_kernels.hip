@@ -1704,7 +1704,12 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       // the next work item's ray records (loaded before pass 0) are in: its
       // static ray data follows
       if (pass == 0 && pf_rec_ok) {
-        pf_st = a.rs[pf_rec.rid];
+        // the record's ray id is taken here, not before the passes: the
+        // compiler would otherwise form the address ahead of the loop and
+        // wait there for the record to arrive
+        uint32_t rid = pf_rec.rid;
+        asm volatile("" : "+v"(rid));
+        pf_st = a.rs[rid];
         pf_st_ok = true;
       }
       cur ^= 1;
