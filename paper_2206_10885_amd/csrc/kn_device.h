@@ -199,9 +199,9 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint64_t lanemask_lt() {
-  int l = lane_id();
-  return l == 0 ? 0ull : (~0ull >> (64 - l));
+// set bits of m (a mask over the wave) below this lane
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // value of lane (lane & ~3) + src within each quad

@@ -56,7 +56,7 @@ __device__ __forceinline__ uint32_t atomic_slot_grouped(uint32_t* arr, uint32_t 
     const uint64_t grp = __ballot(mine);
     if (mine) {
       leader = l;
-      rank = (uint32_t)__popcll(grp & lanemask_lt());
+      rank = lane_rank(grp);
     }
     if (lane == l) size = (uint32_t)__popcll(grp);
     todo &= ~grp;
@@ -517,7 +517,7 @@ __global__ __launch_bounds__(256) void k_world_step(WorldStepArgs a) {
       uint32_t b = 0;
       if (lane == 0) b = atomicAdd(a.n_spawn, ns);
       b = __shfl(b, 0);
-      if (spawn) a.spawn[b + (uint32_t)__popcll(sm & lanemask_lt())] = nrec;
+      if (spawn) a.spawn[b + lane_rank(sm)] = nrec;
     }
     atomic_count_grouped(a.counts_next, a.cs, ncell, spawn);
     wg_count(&a.tabs.miss_done[0], finished, &s_cnt);
@@ -1695,8 +1695,8 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
           uint32_t base = 0;
           if (lane == 0) base = atomicAdd(&s_nact[i1], n0 + (uint32_t)__popcll(sm1));
           base = __builtin_amdgcn_readfirstlane(base);   // every lane is active here
-          if (stay[0]) act_out[base + (uint32_t)__popcll(sm0 & lanemask_lt())] = (uint16_t)ri[0];
-          if (stay[1]) act_out[base + n0 + (uint32_t)__popcll(sm1 & lanemask_lt())] = (uint16_t)ri[1];
+          if (stay[0]) act_out[base + lane_rank(sm0)] = (uint16_t)ri[0];
+          if (stay[1]) act_out[base + n0 + lane_rank(sm1)] = (uint16_t)ri[1];
         }
       }
       __syncthreads();
@@ -1814,11 +1814,19 @@ __global__ __launch_bounds__(256, WPE) void k_march(MarchArgs a) {
       }
     }
     // this wave's count of each class and each lane's rank in its class
+    // (hits need no rank, and only the unclamped kernel has jumped rays)
     uint32_t rank = 0;
 #pragma unroll
     for (uint32_t c = 0; c < (uint32_t)kCls; ++c) {
+      if (!UNC && c == 7u) {
+        if (lane == 0) s_wcnt[wave][c] = 0u;
+        continue;
+      }
       const uint64_t m = __ballot(cls == c);
-      if (cls == c) rank = (uint32_t)__popcll(m & lanemask_lt());
+      if (c != 8u) {
+        const uint32_t r = lane_rank(m);
+        if (cls == c) rank = r;
+      }
       if (lane == 0) s_wcnt[wave][c] = (uint32_t)__popcll(m);
     }
     // misses per request slot: one lane per slot group adds to the wave's row
@@ -2316,7 +2324,7 @@ __global__ __launch_bounds__(256, 3) void k_shade(ShadeArgs a) {
             sp_cur = __shfl(b, 0);
             sp_end = sp_cur + kSpawnBlock;
           }
-          if (spawn) a.spawn[sp_cur + (uint32_t)__popcll(sm & lanemask_lt())] = nrec;
+          if (spawn) a.spawn[sp_cur + lane_rank(sm)] = nrec;
           sp_cur += ns;
         }
         atomic_count_grouped(a.counts_next, a.cs, ncell, spawn);
