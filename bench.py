@@ -50,8 +50,8 @@ PEAK_HBM = 8.0e12
 # commands in profiles/k_march_bf16_c3_1080p.md.  Valid only for the kernel
 # sources they were taken on (the device code's files, KERNEL_SOURCES): any
 # change to them makes the figure null.
-MARCH_TRAFFIC = dict(sources_sha256="e2b2c37d2febcbce3ea1f8eb528ac172897195779386f761bae58f778ad54543",
-                     bytes_per_launch=74098981.6, fetch_kib=25836.38, write_kib=20689.53,
+MARCH_TRAFFIC = dict(sources_sha256="e9d7a0b903a2f4cc314e2c072179353ed7f549c31b28449e94d0d175b81f5b23",
+                     bytes_per_launch=70326575.2, fetch_kib=25741.69, write_kib=17196.77,
                      fetch_factor=2.0, write_factor=1.0)
 
 
