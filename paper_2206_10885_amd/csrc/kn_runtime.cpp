@@ -513,7 +513,9 @@ constexpr size_t kEarlyShadeMinRays = (size_t)1 << 18;
 constexpr uint32_t kEarlyShadeMinChunks = 512;
 double early_shade_fraction() {
   if (const char* e = std::getenv("KN_EARLY_SHADE")) return std::atof(e);
-  return 0.4;   // 1080p C3 frames: 0.12 / 0.25 / 0.4 gave 5.999 / 5.962 / 5.875 ms (6.044 without)
+  // 1080p C3 BF16 frames (p50): 0.25 / 0.3 / 0.35 / 0.4 / 0.5 gave 5.66 / 5.58 /
+  // 5.52 / 5.66 / 5.80 ms, 5.86 ms without
+  return 0.35;
 }
 
 void free_pool(Pool& w) {
