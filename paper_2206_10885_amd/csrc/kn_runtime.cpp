@@ -516,9 +516,10 @@ constexpr size_t kEarlyShadeMinRays = (size_t)1 << 18;
 constexpr uint32_t kEarlyShadeMinChunks = 512;
 double early_shade_fraction() {
   if (const char* e = std::getenv("KN_EARLY_SHADE")) return std::atof(e);
-  // 1080p C3 BF16 frames (p50): 0.25 / 0.3 / 0.35 / 0.4 / 0.5 gave 5.66 / 5.58 /
-  // 5.52 / 5.66 / 5.80 ms, 5.86 ms without
-  return 0.35;
+  // 1080p C3 BF16 frames, two in-cell passes per round: 0.3 / 0.35 / 0.4 /
+  // 0.45 gave 375.6 / 373.9 / 367.8 / 362.5 M rays/s (5.47 / 5.50 / 5.64 /
+  // 5.68 ms p50)
+  return 0.3;
 }
 
 void free_pool(Pool& w) {
